@@ -1,0 +1,332 @@
+"""FP64 CPU oracle for the batched explicit quadrotor step -- TEST INFRASTRUCTURE.
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It wraps ``md_oracle.c`` (plain FP64
+C, built with gcc) through ctypes and shares no code with the HIP library.
+Each wrapper states the passage of the paper it follows; the readings of
+silent passages are documented in ``md_oracle.c``.
+
+Arrays are numpy float64 in the component-major SoA layout ``[c][N]``.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build_oracle
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+AERO_GND, AERO_DRAG, AERO_DW, AERO_SURROGATE = 1, 2, 4, 8
+ACT_RPM, ACT_PID = 0, 1
+N_FEAT, K_NN = 64, 8
+
+
+class Params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "m", "L", "kf", "km", "Ixx", "Iyy", "Izz", "thrust2weight", "r_p", "g",
+        "C_gnd", "c_xy", "c_z", "C1", "C2", "C3", "dw_dz_min")] + [
+        ("pos_kp", ctypes.c_double * 3), ("pos_ki", ctypes.c_double * 3),
+        ("pos_kd", ctypes.c_double * 3), ("pos_i_clamp", ctypes.c_double),
+        ("att_kp", ctypes.c_double * 3), ("att_ki", ctypes.c_double * 3),
+        ("att_kd", ctypes.c_double * 3), ("att_i_clamp", ctypes.c_double)]
+
+    def copy(self):
+        o = Params()
+        ctypes.memmove(ctypes.byref(o), ctypes.byref(self), ctypes.sizeof(Params))
+        return o
+
+
+class Derived(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("hover_rpm", "max_rpm", "max_thrust", "h_clip")]
+
+
+class _CState(ctypes.Structure):
+    _fields_ = [(n, ctypes.POINTER(ctypes.c_double)) for n in ("p", "q", "v", "w", "pid_int", "rpm")]
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = build_oracle.LIB
+    src = os.path.join(_HERE, "md_oracle.c")
+    if (not os.path.exists(path)) or os.path.getmtime(path) < os.path.getmtime(src):
+        build_oracle.build()
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER(Params)
+    lib.orc_params_cf2x.argtypes = [P]
+    lib.orc_derive.argtypes = [P, ctypes.POINTER(Derived)]
+    lib.orc_quat_to_rot.argtypes = [_D, _D]
+    lib.orc_quat_mul.argtypes = [_D, _D, _D]
+    lib.orc_euler_zyx.argtypes = [_D, _D]
+    lib.orc_motor.argtypes = [P, _D, _D, _D, _D]
+    lib.orc_ground_effect.argtypes = [P, ctypes.POINTER(Derived), _D, ctypes.c_double, _D]
+    lib.orc_ground_effect.restype = ctypes.c_double
+    lib.orc_drag.argtypes = [P, _D, _D, _D, _D]
+    lib.orc_downwash_pair.argtypes = [P, _D, _D]
+    lib.orc_downwash_pair.restype = ctypes.c_double
+    lib.orc_pid.argtypes = [P, ctypes.POINTER(Derived), ctypes.c_double, _D, _D, _D, _D, _D, _D, _D]
+    lib.orc_integrate.argtypes = [P, ctypes.c_double, _D, _D, _D, _D, _D, _D]
+    lib.orc_step.argtypes = [P, ctypes.c_double, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
+                             ctypes.c_int, _I32, ctypes.c_int, ctypes.POINTER(_CState), _D,
+                             ctypes.c_int, _D, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                             ctypes.c_int]
+    lib.orc_step.restype = ctypes.c_int
+    lib.orc_knn.argtypes = [ctypes.c_int, _I32, ctypes.c_int, _D, ctypes.c_int, _I32]
+    lib.orc_features.argtypes = [P, ctypes.c_int, _I32, ctypes.c_int, ctypes.POINTER(_CState),
+                                 _I32, ctypes.c_int, ctypes.c_int, _D]
+    lib.orc_aero_residual.argtypes = [P, ctypes.c_uint32, ctypes.c_int, _I32, ctypes.c_int,
+                                      ctypes.POINTER(_CState), _D, _D]
+    lib.orc_mlp_forward.argtypes = [ctypes.c_int, _I32, ctypes.POINTER(_D), ctypes.POINTER(_D),
+                                    ctypes.c_int, _D, _D, _D, ctypes.c_int]
+    lib.orc_mlp_backward.argtypes = [ctypes.c_int, _I32, ctypes.POINTER(_D), ctypes.POINTER(_D),
+                                     ctypes.c_int, _D, _D, _D, ctypes.POINTER(_D),
+                                     ctypes.POINTER(_D), _D]
+    lib.orc_adam.argtypes = [ctypes.c_int, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double,
+                             ctypes.c_double, ctypes.c_double, ctypes.c_int64]
+    lib.orc_bf16_round.argtypes = [ctypes.c_double]
+    lib.orc_bf16_round.restype = ctypes.c_double
+    _lib = lib
+    return lib
+
+
+def _dp(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+def _ip(a):
+    assert a.dtype == np.int32 and a.flags.c_contiguous
+    return a.ctypes.data_as(_I32)
+
+
+def _vec(x, n):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(n))
+    return a
+
+
+# --------------------------------------------------------------------------
+# Constants (Table "Drone model parameters", Eq. (6) coefficients, Table
+# "Default PIDControl gains"; readings in md_oracle.c).
+# --------------------------------------------------------------------------
+
+def cf2x():
+    P = Params()
+    _load().orc_params_cf2x(ctypes.byref(P))
+    return P
+
+
+def derive(P):
+    D = Derived()
+    _load().orc_derive(ctypes.byref(P), ctypes.byref(D))
+    return D
+
+
+# --------------------------------------------------------------------------
+# Per-drone building blocks.
+# --------------------------------------------------------------------------
+
+def quat_to_rot(q):
+    q = _vec(q, 4)
+    R = np.zeros(9)
+    _load().orc_quat_to_rot(_dp(q), _dp(R))
+    return R.reshape(3, 3)
+
+
+def quat_mul(a, b):
+    a, b = _vec(a, 4), _vec(b, 4)
+    o = np.zeros(4)
+    _load().orc_quat_mul(_dp(a), _dp(b), _dp(o))
+    return o
+
+
+def euler_zyx(q):
+    q = _vec(q, 4)
+    o = np.zeros(3)
+    _load().orc_euler_zyx(_dp(q), _dp(o))
+    return o
+
+
+def motor(P, n):
+    """Eq. (1)-(3): returns (F[4], T, tau_body[3])."""
+    n = _vec(n, 4)
+    F, T, tau = np.zeros(4), ctypes.c_double(0.0), np.zeros(3)
+    _load().orc_motor(ctypes.byref(P), _dp(n), _dp(F), ctypes.byref(T), _dp(tau))
+    return F, T.value, tau
+
+
+def ground_effect(P, n, pz, q):
+    """Eq. (4): extra world +z force."""
+    D = derive(P)
+    n, q = _vec(n, 4), _vec(q, 4)
+    return _load().orc_ground_effect(ctypes.byref(P), ctypes.byref(D), _dp(n), float(pz), _dp(q))
+
+
+def drag(P, n, q, v):
+    """Eq. (5): drag force in the world frame."""
+    n, q, v = _vec(n, 4), _vec(q, 4), _vec(v, 3)
+    F = np.zeros(3)
+    _load().orc_drag(ctypes.byref(P), _dp(n), _dp(q), _dp(v), _dp(F))
+    return F
+
+
+def downwash_pair(P, p_low, p_other):
+    """Eq. (6): world-z force on the drone at p_low from the drone at p_other."""
+    a, b = _vec(p_low, 3), _vec(p_other, 3)
+    return _load().orc_downwash_pair(ctypes.byref(P), _dp(a), _dp(b))
+
+
+def pid(P, dt_c, p, q, v, w, target, integ):
+    """Sec. "Control": cascaded PID; returns (rpm[4], new integrals[6])."""
+    D = derive(P)
+    p, q, v, w, t = _vec(p, 3), _vec(q, 4), _vec(v, 3), _vec(w, 3), _vec(target, 4)
+    I = _vec(integ, 6).copy()
+    n = np.zeros(4)
+    _load().orc_pid(ctypes.byref(P), ctypes.byref(D), float(dt_c), _dp(p), _dp(q), _dp(v),
+                    _dp(w), _dp(t), _dp(I), _dp(n))
+    return n, I
+
+
+def integrate(P, dt, Fw, tau, p, q, v, w):
+    """Sec. "Physics Modes": semi-implicit Euler + exponential map."""
+    Fw, tau = _vec(Fw, 3), _vec(tau, 3)
+    p, q, v, w = _vec(p, 3).copy(), _vec(q, 4).copy(), _vec(v, 3).copy(), _vec(w, 3).copy()
+    _load().orc_integrate(ctypes.byref(P), float(dt), _dp(Fw), _dp(tau), _dp(p), _dp(q),
+                          _dp(v), _dp(w))
+    return p, q, v, w
+
+
+# --------------------------------------------------------------------------
+# Batched step.
+# --------------------------------------------------------------------------
+
+STATE_ROWS = {"p": 3, "q": 4, "v": 3, "w": 3, "pid_int": 6, "rpm": 4}
+
+
+def new_state(n):
+    s = {k: np.zeros((r, n)) for k, r in STATE_ROWS.items()}
+    s["q"][0] = 1.0
+    return s
+
+
+def _cstate(s):
+    for k in STATE_ROWS:
+        assert s[k].dtype == np.float64 and s[k].flags.c_contiguous, k
+    return _CState(*[s[k].ctypes.data_as(_D) for k in ("p", "q", "v", "w", "pid_int", "rpm")])
+
+
+def step(P, dt, aero_mask, act_type, ctrl_decim, env_offsets, state, action,
+         action_per_step, n_steps, step0=0, n_obs_slots=0, n_threads=0):
+    """Advance ``state`` (dict of [c][N] float64 arrays, updated in place) by
+    n_steps; returns the observation array [slots][20][N] or None."""
+    off = np.ascontiguousarray(np.asarray(env_offsets, dtype=np.int32))
+    n_envs = len(off) - 1
+    n = int(off[-1])
+    act = np.ascontiguousarray(np.asarray(action, dtype=np.float64))
+    need = (n_steps if action_per_step else 1) * 4 * n
+    assert act.size == need, (act.size, need)
+    obs = np.zeros((n_obs_slots, 20, n)) if n_obs_slots > 0 else None
+    cs = _cstate(state)
+    rc = _load().orc_step(ctypes.byref(P), float(dt), int(aero_mask), int(act_type),
+                          int(ctrl_decim), n_envs, _ip(off), n, ctypes.byref(cs), _dp(act),
+                          int(bool(action_per_step)), _dp(obs) if obs is not None else None,
+                          int(n_obs_slots), int(n_steps), int(step0), int(n_threads))
+    if rc != 0:
+        raise ValueError("orc_step failed (%d)" % rc)
+    return obs
+
+
+# --------------------------------------------------------------------------
+# Surrogate support.
+# --------------------------------------------------------------------------
+
+def knn(env_offsets, p, k=K_NN):
+    off = np.ascontiguousarray(np.asarray(env_offsets, dtype=np.int32))
+    n = int(off[-1])
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    nbr = np.full((n, k), -1, dtype=np.int32)
+    rc = _load().orc_knn(len(off) - 1, _ip(off), n, _dp(p), int(k), _ip(nbr))
+    if rc != 0:
+        raise MemoryError("orc_knn")
+    return nbr
+
+
+def features(P, env_offsets, state, nbr, n_feat=N_FEAT):
+    off = np.ascontiguousarray(np.asarray(env_offsets, dtype=np.int32))
+    n = int(off[-1])
+    k = nbr.shape[1]
+    X = np.zeros((n, n_feat))
+    cs = _cstate(state)
+    rc = _load().orc_features(ctypes.byref(P), len(off) - 1, _ip(off), n, ctypes.byref(cs),
+                              _ip(np.ascontiguousarray(nbr, dtype=np.int32)), int(k),
+                              int(n_feat), _dp(X))
+    if rc != 0:
+        raise ValueError("orc_features")
+    return X
+
+
+def aero_residual(P, aero_mask, env_offsets, state, rpm=None):
+    off = np.ascontiguousarray(np.asarray(env_offsets, dtype=np.int32))
+    n = int(off[-1])
+    rpm = state["rpm"] if rpm is None else np.ascontiguousarray(rpm, dtype=np.float64)
+    Y = np.zeros((n, 6))
+    cs = _cstate(state)
+    _load().orc_aero_residual(ctypes.byref(P), int(aero_mask), len(off) - 1, _ip(off), n,
+                              ctypes.byref(cs), _dp(rpm), _dp(Y))
+    return Y
+
+
+def _ptrs(arrs):
+    return (_D * len(arrs))(*[_dp(a) for a in arrs])
+
+
+def mlp_forward(Ws, bs, X, bf16_acts=False):
+    """Ws[l]: [out][in] float64; returns (Y, acts)."""
+    dims = np.array([Ws[0].shape[1]] + [W.shape[0] for W in Ws], dtype=np.int32)
+    Ws = [np.ascontiguousarray(W, dtype=np.float64) for W in Ws]
+    bs = [np.ascontiguousarray(b, dtype=np.float64) for b in bs]
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    B = X.shape[0]
+    Y = np.zeros((B, dims[-1]))
+    acts = np.zeros(int(sum(2 * B * d for d in dims[1:])))
+    rc = _load().orc_mlp_forward(len(Ws), _ip(dims), _ptrs(Ws), _ptrs(bs), B, _dp(X), _dp(Y),
+                                 _dp(acts), int(bool(bf16_acts)))
+    if rc != 0:
+        raise MemoryError("orc_mlp_forward")
+    return Y, acts
+
+
+def mlp_backward(Ws, bs, X, acts, dY, want_dx=False):
+    dims = np.array([Ws[0].shape[1]] + [W.shape[0] for W in Ws], dtype=np.int32)
+    Ws = [np.ascontiguousarray(W, dtype=np.float64) for W in Ws]
+    bs = [np.ascontiguousarray(b, dtype=np.float64) for b in bs]
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    dY = np.ascontiguousarray(dY, dtype=np.float64)
+    B = X.shape[0]
+    dWs = [np.zeros_like(W) for W in Ws]
+    dbs = [np.zeros_like(b) for b in bs]
+    dX = np.zeros_like(X) if want_dx else None
+    rc = _load().orc_mlp_backward(len(Ws), _ip(dims), _ptrs(Ws), _ptrs(bs), B, _dp(X),
+                                  _dp(acts), _dp(dY), _ptrs(dWs), _ptrs(dbs),
+                                  _dp(dX) if dX is not None else None)
+    if rc != 0:
+        raise MemoryError("orc_mlp_backward")
+    return dWs, dbs, dX
+
+
+def adam(param, grad, m1, m2, lr, beta1, beta2, eps, t):
+    for a in (param, grad, m1, m2):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    _load().orc_adam(param.size, _dp(param), _dp(grad), _dp(m1), _dp(m2), float(lr),
+                     float(beta1), float(beta2), float(eps), int(t))
+
+
+def bf16_round(x):
+    f = _load().orc_bf16_round
+    return np.vectorize(f, otypes=[np.float64])(np.asarray(x, dtype=np.float64))

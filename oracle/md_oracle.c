@@ -1,0 +1,702 @@
+/*
+ * md_oracle.c -- FP64 CPU oracle for the batched explicit quadrotor step.
+ *
+ * TEST INFRASTRUCTURE ONLY (tests, the smoke check and the benchmark's CPU
+ * baseline leg).  Plain loops in double precision, written from the paper's
+ * equations in the paper's order.  No blocking, fusion or reordering; the
+ * only parallelism is an OpenMP loop over independent environments, which
+ * does not change any drone's arithmetic.  Shares nothing with the HIP path.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (see build_oracle.py)
+ */
+#include "md_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Constants.                                                                */
+/* ------------------------------------------------------------------------ */
+
+/* Table "Drone model parameters" (CF2X column), the downwash coefficients
+ * printed with Eq. (6), and Table "Default PIDControl gains".
+ * Readings (not printed in the paper):
+ *   g = 9.81 m/s^2 (MuJoCo's default gravity);
+ *   C_gnd, c_xy, c_z: the paper states its aerodynamic formulae and drone
+ *   parameters are identical to its predecessor's; these are that simulator's
+ *   CF2X values -- their physical values are "parity unpinned".
+ *   Units: n in rev/min and kf, km per RPM^2 (the table's rad/s units are
+ *   inconsistent with hover at ~14.5k RPM and with Eq. (5)'s 2*pi*n/60). */
+void orc_params_cf2x(orc_params *P)
+{
+    memset(P, 0, sizeof *P);
+    P->m = 0.027;
+    P->L = 0.0397;
+    P->thrust2weight = 2.25;
+    P->Ixx = 1.4e-5;
+    P->Iyy = 1.4e-5;
+    P->Izz = 2.17e-5;
+    P->kf = 3.16e-10;
+    P->km = 7.94e-12;
+    P->r_p = 0.02325;
+    P->g = 9.81;
+    P->C_gnd = 11.36359;
+    P->c_xy = 9.1785e-7;
+    P->c_z = 10.311e-7;
+    P->C1 = 2267.18;
+    P->C2 = 0.16;
+    P->C3 = -0.11;
+    P->dw_dz_min = 0.0;
+    const double pkp[3] = {0.4, 0.4, 1.0}, pki[3] = {0.01, 0.01, 0.01}, pkd[3] = {0.9, 0.9, 2.0};
+    const double akp[3] = {2e-3, 2e-3, 1e-3}, aki[3] = {0.0, 0.0, 1e-4}, akd[3] = {5e-4, 5e-4, 2e-4};
+    for (int c = 0; c < 3; ++c) {
+        P->pos_kp[c] = pkp[c];
+        P->pos_ki[c] = pki[c];
+        P->pos_kd[c] = pkd[c];
+        P->att_kp[c] = akp[c];
+        P->att_ki[c] = aki[c];
+        P->att_kd[c] = akd[c];
+    }
+    P->pos_i_clamp = 2.0;
+    P->att_i_clamp = 0.5;
+}
+
+/* Sec. "Drone Models": HOVER_RPM = sqrt(m g / (4 kf)); MAX_RPM from
+ * (m, g, kf, T/W): the speed at which four rotors give T/W times the weight.
+ * Reading for h_clip (Sec. "Aerodynamic effects", under Eq. (4), "derived
+ * from the propeller radius and the model's maximum thrust"): the height at
+ * which one rotor's ground-effect force at MAX_RPM equals MAX_THRUST/15. */
+void orc_derive(const orc_params *P, orc_derived *D)
+{
+    D->hover_rpm = sqrt(P->m * P->g / (4.0 * P->kf));
+    D->max_rpm = sqrt(P->thrust2weight * P->m * P->g / (4.0 * P->kf));
+    D->max_thrust = 4.0 * P->kf * D->max_rpm * D->max_rpm;
+    D->h_clip = 0.25 * P->r_p *
+                sqrt(15.0 * P->C_gnd * P->kf * D->max_rpm * D->max_rpm / D->max_thrust);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Quaternion helpers, [w, x, y, z] body->world (Sec. "Notation").           */
+/* ------------------------------------------------------------------------ */
+
+void orc_quat_to_rot(const double q[4], double R[9])
+{
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1.0 - 2.0 * (y * y + z * z);
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = 1.0 - 2.0 * (x * x + z * z);
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+/* Hamilton product a (x) b. */
+void orc_quat_mul(const double a[4], const double b[4], double o[4])
+{
+    o[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    o[1] = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+    o[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+    o[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+}
+
+/* Roll, pitch, yaw of the KIN observation (Sec. "Observation types").
+ * Reading: intrinsic Z-Y-X (yaw, pitch, roll). */
+void orc_euler_zyx(const double q[4], double rpy[3])
+{
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    double sp = 2.0 * (w * y - z * x);
+    if (sp > 1.0) sp = 1.0;
+    if (sp < -1.0) sp = -1.0;
+    rpy[0] = atan2(2.0 * (w * x + y * z), 1.0 - 2.0 * (x * x + y * y));
+    rpy[1] = asin(sp);
+    rpy[2] = atan2(2.0 * (w * z + x * y), 1.0 - 2.0 * (y * y + z * z));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Forces.                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Eq. (1)-(3): F_i = kf n_i^2, tau_z,i = (-1)^{m_i} km n_i^2, X-config roll
+ * and pitch torques with lever L/sqrt(2), collective thrust T = sum F_i.
+ * Reading of the alternating sign: m = (1, 0, 1, 0), i.e. yaw signs
+ * (-, +, -, +) for motors 0..3. */
+void orc_motor(const orc_params *P, const double n[4], double F[4], double *T, double tau[3])
+{
+    static const int m_sign[4] = {1, 0, 1, 0};
+    double tz = 0.0, Tsum = 0.0;
+    for (int i = 0; i < 4; ++i) {
+        F[i] = P->kf * n[i] * n[i];
+        Tsum += F[i];
+        const double s = (m_sign[i] ? -1.0 : 1.0);
+        tz += s * P->km * n[i] * n[i];
+    }
+    const double l = P->L / sqrt(2.0);
+    tau[0] = l * (F[0] + F[1] - F[2] - F[3]);
+    tau[1] = l * (-F[0] + F[1] + F[2] - F[3]);
+    tau[2] = tz;
+    *T = Tsum;
+}
+
+/* Eq. (4): extra vertical force C_gnd * sum(kf n_i^2) * (r_p / (4 h))^2,
+ * h = max(p_z, h_clip), applied only while |roll| and |pitch| < pi/2.
+ * Reading: one h taken at the body's centre, force along world +z. */
+double orc_ground_effect(const orc_params *P, const orc_derived *D, const double n[4],
+                         double pz, const double q[4])
+{
+    double rpy[3];
+    orc_euler_zyx(q, rpy);
+    if (!(fabs(rpy[0]) < 0.5 * M_PI && fabs(rpy[1]) < 0.5 * M_PI)) return 0.0;
+    const double h = (pz > D->h_clip) ? pz : D->h_clip;
+    double s = 0.0;
+    for (int i = 0; i < 4; ++i) s += P->kf * n[i] * n[i];
+    const double r = P->r_p / (4.0 * h);
+    return P->C_gnd * s * r * r;
+}
+
+/* Eq. (5): body-frame drag -diag(c_xy, c_xy, c_z) * (sum 2 pi n_i / 60) * v_body,
+ * rotated back to the world frame: F_w = R * f_body with v_body = R^T v. */
+void orc_drag(const orc_params *P, const double n[4], const double q[4], const double v[3],
+              double Fw[3])
+{
+    double R[9];
+    orc_quat_to_rot(q, R);
+    double vb[3];
+    for (int a = 0; a < 3; ++a) vb[a] = R[0 * 3 + a] * v[0] + R[1 * 3 + a] * v[1] + R[2 * 3 + a] * v[2];
+    double S = 0.0;
+    for (int i = 0; i < 4; ++i) S += 2.0 * M_PI * n[i] / 60.0;
+    const double c[3] = {P->c_xy, P->c_xy, P->c_z};
+    double fb[3];
+    for (int a = 0; a < 3; ++a) fb[a] = -c[a] * S * vb[a];
+    for (int a = 0; a < 3; ++a) Fw[a] = R[a * 3 + 0] * fb[0] + R[a * 3 + 1] * fb[1] + R[a * 3 + 2] * fb[2];
+}
+
+/* Eq. (6): the drone at p_low receives -alpha exp(-(dxy/beta)^2 / 2) along
+ * world z from a drone at p_other above it (dz = z_other - z_low > 0) with
+ * lateral distance dxy < 10 m; alpha = C1 (r_p / (4 dz))^2, beta = C2 dz + C3.
+ * Readings: strict dz > 0; beta enters only squared, and for beta = 0 the
+ * Gaussian is 1 at dxy = 0 and 0 elsewhere (its limit); the optional floor
+ * dw_dz_min (0 = off, the literal equation) bounds dz from below. */
+double orc_downwash_pair(const orc_params *P, const double p_low[3], const double p_other[3])
+{
+    const double dz = p_other[2] - p_low[2];
+    const double dx = p_other[0] - p_low[0];
+    const double dy = p_other[1] - p_low[1];
+    const double dxy = sqrt(dx * dx + dy * dy);
+    if (!(dz > 0.0 && dxy < 10.0)) return 0.0;
+    double dze = dz;
+    if (P->dw_dz_min > 0.0 && dze < P->dw_dz_min) dze = P->dw_dz_min;
+    const double r = P->r_p / (4.0 * dze);
+    const double alpha = P->C1 * r * r;
+    const double beta = P->C2 * dze + P->C3;
+    double gauss;
+    if (beta == 0.0) {
+        gauss = (dxy == 0.0) ? 1.0 : 0.0;
+    } else {
+        const double t = dxy / beta;
+        gauss = exp(-0.5 * t * t);
+    }
+    return -alpha * gauss;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cascaded PID (Sec. "Control", Eq. (9), Table "Default PIDControl gains"). */
+/* ------------------------------------------------------------------------ */
+
+static double wrap_pi(double a)
+{
+    /* into [-pi, pi) */
+    return a - 2.0 * M_PI * floor((a + M_PI) / (2.0 * M_PI));
+}
+
+static double clampd(double x, double lo, double hi)
+{
+    return x < lo ? lo : (x > hi ? hi : x);
+}
+
+/* Position loop: a* = Kp e + Ki int(e) + Kd (v* - v) + g z_hat with v* = 0;
+ * T = m |a*|.  Readings: the integrals advance by e * dt_c and are clamped
+ * before use; the small-angle attitude target is the near-hover inversion of
+ * the thrust direction at the current yaw psi,
+ *   roll*  = (a*_x sin psi - a*_y cos psi) / g,
+ *   pitch* = (a*_x cos psi + a*_y sin psi) / g,  yaw* = waypoint yaw;
+ * the attitude PID acts on (roll*-roll, pitch*-pitch, wrap(yaw*-yaw)) with
+ * derivative term Kd (0 - omega); the allocation T,tau = M [kf n_i^2] is
+ * inverted exactly (its rows are mutually orthogonal) and each rotor force is
+ * clipped to [0, kf MAX_RPM^2] (parity unpinned when saturated). */
+void orc_pid(const orc_params *P, const orc_derived *D, double dt_c, const double p[3],
+             const double q[4], const double v[3], const double w[3], const double target[4],
+             double integ[6], double n_out[4])
+{
+    double e[3], acc[3];
+    for (int c = 0; c < 3; ++c) {
+        e[c] = target[c] - p[c];
+        integ[c] = clampd(integ[c] + e[c] * dt_c, -P->pos_i_clamp, P->pos_i_clamp);
+        acc[c] = P->pos_kp[c] * e[c] + P->pos_ki[c] * integ[c] + P->pos_kd[c] * (0.0 - v[c]);
+    }
+    acc[2] += P->g;
+    const double T = P->m * sqrt(acc[0] * acc[0] + acc[1] * acc[1] + acc[2] * acc[2]);
+
+    double rpy[3];
+    orc_euler_zyx(q, rpy);
+    const double sps = sin(rpy[2]), cps = cos(rpy[2]);
+    const double roll_t = (acc[0] * sps - acc[1] * cps) / P->g;
+    const double pitch_t = (acc[0] * cps + acc[1] * sps) / P->g;
+    double ea[3] = {roll_t - rpy[0], pitch_t - rpy[1], wrap_pi(target[3] - rpy[2])};
+    double tau[3];
+    for (int c = 0; c < 3; ++c) {
+        integ[3 + c] = clampd(integ[3 + c] + ea[c] * dt_c, -P->att_i_clamp, P->att_i_clamp);
+        tau[c] = P->att_kp[c] * ea[c] + P->att_ki[c] * integ[3 + c] + P->att_kd[c] * (0.0 - w[c]);
+    }
+
+    /* Allocation inverse.  Rows of M: (1,1,1,1), l(1,1,-1,-1), l(-1,1,1,-1),
+     * kappa(-1,1,-1,1), l = L/sqrt(2), kappa = km/kf; each row has squared
+     * norm 4 * scale^2, so M^-1 = M^T diag(1/(4 scale^2)). */
+    const double l = P->L / sqrt(2.0), kap = P->km / P->kf;
+    static const double sx[4] = {1, 1, -1, -1}, sy[4] = {-1, 1, 1, -1}, sz[4] = {-1, 1, -1, 1};
+    const double fmax = P->kf * D->max_rpm * D->max_rpm;
+    for (int i = 0; i < 4; ++i) {
+        double F = 0.25 * (T + sx[i] * tau[0] / l + sy[i] * tau[1] / l + sz[i] * tau[2] / kap);
+        F = clampd(F, 0.0, fmax);
+        n_out[i] = sqrt(F / P->kf);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Integrator (Sec. "Physics Modes", Eq. (7)).                                */
+/* ------------------------------------------------------------------------ */
+
+/* Newton-Euler with a = F_w / m and omega_dot = J^-1 (tau - omega x J omega).
+ * Readings: semi-implicit Euler (v and omega first; p uses the new v; q uses
+ * the new omega), omega in the body frame; the exponential map of Eq. (7),
+ * with Lambda(omega) the quaternion-product matrix that carries the 1/2 of
+ * q_dot = Lambda q, equals q <- q (x) [cos th, sin th omega/|omega|] with
+ * th = |omega| dt / 2; q is renormalised every step. */
+void orc_integrate(const orc_params *P, double dt, const double Fw[3], const double tau[3],
+                   double p[3], double q[4], double v[3], double w[3])
+{
+    const double J[3] = {P->Ixx, P->Iyy, P->Izz};
+    double Jw[3] = {J[0] * w[0], J[1] * w[1], J[2] * w[2]};
+    double cr[3] = {w[1] * Jw[2] - w[2] * Jw[1], w[2] * Jw[0] - w[0] * Jw[2],
+                    w[0] * Jw[1] - w[1] * Jw[0]};
+    double wd[3];
+    for (int c = 0; c < 3; ++c) wd[c] = (tau[c] - cr[c]) / J[c];
+    for (int c = 0; c < 3; ++c) {
+        v[c] += dt * (Fw[c] / P->m);
+        w[c] += dt * wd[c];
+    }
+    for (int c = 0; c < 3; ++c) p[c] += dt * v[c];
+    const double nw = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    if (nw > 0.0) {
+        const double th = 0.5 * nw * dt;
+        const double s = sin(th) / nw;
+        const double r[4] = {cos(th), s * w[0], s * w[1], s * w[2]};
+        double o[4];
+        orc_quat_mul(q, r, o);
+        memcpy(q, o, sizeof o);
+    }
+    const double nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int c = 0; c < 4; ++c) q[c] /= nq;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Whole batched step.                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* One call advances every drone n_steps times.  Per step (all drones use the
+ * pre-step positions of the others for the downwash, i.e. synchronously):
+ *   rotor speeds (RPM action clipped to [0, MAX_RPM], or the PID every
+ *   ctrl_decim steps with phase (step0 + k) mod ctrl_decim = 0, held between),
+ *   motor model, F_w = R (0,0,T) - m g z_hat, optional ground effect, drag and
+ *   downwash (each env's drones in ascending index), Newton-Euler, exp map,
+ *   optional KIN observation [p, q, roll/pitch/yaw, v, omega, n] to slot
+ *   k mod n_obs_slots.  Layouts: action [n_act][4][N] with n_act = n_steps
+ *   when action_per_step else 1; obs [slot][20][N]. */
+int orc_step(const orc_params *P, double dt, uint32_t aero_mask, int act_type, int ctrl_decim,
+             int n_envs, const int32_t *env_offsets, int n_drones, orc_state *s,
+             const double *action, int action_per_step, double *obs, int n_obs_slots,
+             int n_steps, int64_t step0, int n_threads)
+{
+    if (n_drones < 0 || n_envs < 0 || n_steps < 0 || ctrl_decim < 1) return -1;
+    if (env_offsets[0] != 0 || env_offsets[n_envs] != n_drones) return -1;
+    if (aero_mask & ORC_AERO_SURROGATE) return -1; /* handled by the surrogate oracle */
+    orc_derived D;
+    orc_derive(P, &D);
+    const int N = n_drones;
+    double *p_pre = (double *)malloc(sizeof(double) * 3 * (size_t)(N > 0 ? N : 1));
+    if (!p_pre) return -2;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    for (int k = 0; k < n_steps; ++k) {
+        memcpy(p_pre, s->p, sizeof(double) * 3 * (size_t)N);
+        const double *act = action + (action_per_step ? (size_t)k * 4 * N : 0);
+        const int do_pid = (act_type == ORC_ACT_PID) && (((step0 + k) % ctrl_decim) == 0);
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int e = 0; e < n_envs; ++e) {
+            for (int i = env_offsets[e]; i < env_offsets[e + 1]; ++i) {
+                double p[3], q[4], v[3], w[3], n[4];
+                for (int c = 0; c < 3; ++c) {
+                    p[c] = s->p[c * N + i];
+                    v[c] = s->v[c * N + i];
+                    w[c] = s->w[c * N + i];
+                }
+                for (int c = 0; c < 4; ++c) q[c] = s->q[c * N + i];
+
+                if (act_type == ORC_ACT_RPM) {
+                    for (int c = 0; c < 4; ++c) n[c] = clampd(act[c * N + i], 0.0, D.max_rpm);
+                } else if (do_pid) {
+                    double tgt[4], integ[6];
+                    for (int c = 0; c < 4; ++c) tgt[c] = act[c * N + i];
+                    for (int c = 0; c < 6; ++c) integ[c] = s->pid_int[c * N + i];
+                    orc_pid(P, &D, dt * ctrl_decim, p, q, v, w, tgt, integ, n);
+                    for (int c = 0; c < 6; ++c) s->pid_int[c * N + i] = integ[c];
+                } else {
+                    for (int c = 0; c < 4; ++c) n[c] = s->rpm[c * N + i];
+                }
+                for (int c = 0; c < 4; ++c) s->rpm[c * N + i] = n[c];
+
+                double F[4], T, tau[3], R[9];
+                orc_motor(P, n, F, &T, tau);
+                orc_quat_to_rot(q, R);
+                double Fw[3] = {R[2] * T, R[5] * T, R[8] * T - P->m * P->g};
+                if (aero_mask & ORC_AERO_GND) Fw[2] += orc_ground_effect(P, &D, n, p[2], q);
+                if (aero_mask & ORC_AERO_DRAG) {
+                    double Fd[3];
+                    orc_drag(P, n, q, v, Fd);
+                    for (int c = 0; c < 3; ++c) Fw[c] += Fd[c];
+                }
+                if (aero_mask & ORC_AERO_DW) {
+                    const double pi_[3] = {p_pre[0 * N + i], p_pre[1 * N + i], p_pre[2 * N + i]};
+                    for (int j = env_offsets[e]; j < env_offsets[e + 1]; ++j) {
+                        if (j == i) continue;
+                        const double pj[3] = {p_pre[0 * N + j], p_pre[1 * N + j], p_pre[2 * N + j]};
+                        Fw[2] += orc_downwash_pair(P, pi_, pj);
+                    }
+                }
+                orc_integrate(P, dt, Fw, tau, p, q, v, w);
+                for (int c = 0; c < 3; ++c) {
+                    s->p[c * N + i] = p[c];
+                    s->v[c * N + i] = v[c];
+                    s->w[c * N + i] = w[c];
+                }
+                for (int c = 0; c < 4; ++c) s->q[c * N + i] = q[c];
+
+                if (obs && n_obs_slots > 0) {
+                    double *o = obs + (size_t)(k % n_obs_slots) * 20 * N;
+                    double rpy[3];
+                    orc_euler_zyx(q, rpy);
+                    const double row[20] = {p[0], p[1], p[2], q[0], q[1], q[2], q[3],
+                                            rpy[0], rpy[1], rpy[2], v[0], v[1], v[2],
+                                            w[0], w[1], w[2], n[0], n[1], n[2], n[3]};
+                    for (int c = 0; c < 20; ++c) o[(size_t)c * N + i] = row[c];
+                }
+            }
+        }
+    }
+    free(p_pre);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Surrogate support: neighbours, features, residual targets, MLP, Adam.     */
+/* ------------------------------------------------------------------------ */
+
+/* k nearest same-environment neighbours by 3-D distance, ascending, ties to
+ * the lower index, padded with -1.  The distance that decides the order is
+ * formed in binary32 exactly as the GPU forms it (dx*dx + dy*dy, then + dz*dz,
+ * each operation rounded), so both sides take the same integer decision. */
+typedef struct { float d2; int32_t j; } orc_cand;
+
+static int cand_cmp(const void *a, const void *b)
+{
+    const orc_cand *x = (const orc_cand *)a, *y = (const orc_cand *)b;
+    if (x->d2 < y->d2) return -1;
+    if (x->d2 > y->d2) return 1;
+    return (x->j < y->j) ? -1 : (x->j > y->j);
+}
+
+int orc_knn(int n_envs, const int32_t *env_offsets, int n_drones, const double *p, int k,
+            int32_t *nbr)
+{
+    const int N = n_drones;
+    int maxm = 0;
+    for (int e = 0; e < n_envs; ++e) {
+        const int m = env_offsets[e + 1] - env_offsets[e];
+        if (m > maxm) maxm = m;
+    }
+    int rc = 0;
+#pragma omp parallel
+    {
+        orc_cand *c = (orc_cand *)malloc(sizeof(orc_cand) * (size_t)(maxm > 0 ? maxm : 1));
+        if (!c) {
+#pragma omp atomic write
+            rc = -2;
+        }
+#pragma omp for schedule(dynamic, 16)
+        for (int e = 0; e < n_envs; ++e) {
+            if (!c) continue;
+            for (int i = env_offsets[e]; i < env_offsets[e + 1]; ++i) {
+                int nc = 0;
+                const float xi = (float)p[0 * N + i], yi = (float)p[1 * N + i], zi = (float)p[2 * N + i];
+                for (int j = env_offsets[e]; j < env_offsets[e + 1]; ++j) {
+                    if (j == i) continue;
+                    volatile float dx = (float)p[0 * N + j] - xi;
+                    volatile float dy = (float)p[1 * N + j] - yi;
+                    volatile float dz = (float)p[2 * N + j] - zi;
+                    volatile float a = dx * dx;
+                    volatile float b = dy * dy;
+                    volatile float cz = dz * dz;
+                    volatile float s1 = a + b;
+                    volatile float d2 = s1 + cz;
+                    c[nc].d2 = d2;
+                    c[nc].j = j;
+                    ++nc;
+                }
+                qsort(c, (size_t)nc, sizeof *c, cand_cmp);
+                for (int t = 0; t < k; ++t) nbr[(size_t)i * k + t] = (t < nc) ? c[t].j : -1;
+            }
+        }
+        free(c);
+    }
+    return rc;
+}
+
+/* Surrogate inputs of one drone (raw, before any scaling), n_feat >= 59:
+ *   [0..2]  v_body = R^T v
+ *   [3..5]  world up axis in the body frame, R^T z_hat
+ *   [6..9]  n_i / HOVER_RPM
+ *   [10..57] for each of the k = 8 nearest neighbours: p_j - p_i, v_j - v_i
+ *            (world frame), zeros for a missing neighbour
+ *   [58]    p_z
+ *   [59..]  zero padding. */
+int orc_features(const orc_params *P, int n_envs, const int32_t *env_offsets, int n_drones,
+                 const orc_state *s, const int32_t *nbr, int k, int n_feat, double *X)
+{
+    (void)n_envs;
+    (void)env_offsets;
+    if (n_feat < 10 + 6 * k + 1) return -1;
+    orc_derived D;
+    orc_derive(P, &D);
+    const int N = n_drones;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < N; ++i) {
+        double *x = X + (size_t)i * n_feat;
+        for (int f = 0; f < n_feat; ++f) x[f] = 0.0;
+        double q[4], R[9], v[3];
+        for (int c = 0; c < 4; ++c) q[c] = s->q[c * N + i];
+        for (int c = 0; c < 3; ++c) v[c] = s->v[c * N + i];
+        orc_quat_to_rot(q, R);
+        for (int a = 0; a < 3; ++a) x[a] = R[0 * 3 + a] * v[0] + R[1 * 3 + a] * v[1] + R[2 * 3 + a] * v[2];
+        for (int a = 0; a < 3; ++a) x[3 + a] = R[2 * 3 + a];
+        for (int c = 0; c < 4; ++c) x[6 + c] = s->rpm[c * N + i] / D.hover_rpm;
+        for (int t = 0; t < k; ++t) {
+            const int j = nbr[(size_t)i * k + t];
+            if (j < 0) continue;
+            for (int c = 0; c < 3; ++c) {
+                x[10 + 6 * t + c] = s->p[c * N + j] - s->p[c * N + i];
+                x[10 + 6 * t + 3 + c] = s->v[c * N + j] - s->v[c * N + i];
+            }
+        }
+        x[10 + 6 * k] = s->p[2 * N + i];
+    }
+    return 0;
+}
+
+/* Residual the surrogate learns: the aerodynamic wrench of Eq. (4)-(6) that
+ * the selected effects add to the rotor wrench, in the body frame:
+ * Y[i] = (R^T F_aero_w, tau_aero_body).  With the centre-of-mass readings of
+ * Eq. (4)-(6) the aerodynamic torque is identically zero. */
+int orc_aero_residual(const orc_params *P, uint32_t aero_mask, int n_envs,
+                      const int32_t *env_offsets, int n_drones, const orc_state *s,
+                      const double *rpm, double *Y)
+{
+    orc_derived D;
+    orc_derive(P, &D);
+    const int N = n_drones;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int e = 0; e < n_envs; ++e) {
+        for (int i = env_offsets[e]; i < env_offsets[e + 1]; ++i) {
+            double p[3], q[4], v[3], n[4], R[9];
+            for (int c = 0; c < 3; ++c) {
+                p[c] = s->p[c * N + i];
+                v[c] = s->v[c * N + i];
+            }
+            for (int c = 0; c < 4; ++c) {
+                q[c] = s->q[c * N + i];
+                n[c] = rpm[c * N + i];
+            }
+            double Fa[3] = {0.0, 0.0, 0.0};
+            if (aero_mask & ORC_AERO_GND) Fa[2] += orc_ground_effect(P, &D, n, p[2], q);
+            if (aero_mask & ORC_AERO_DRAG) {
+                double Fd[3];
+                orc_drag(P, n, q, v, Fd);
+                for (int c = 0; c < 3; ++c) Fa[c] += Fd[c];
+            }
+            if (aero_mask & ORC_AERO_DW) {
+                for (int j = env_offsets[e]; j < env_offsets[e + 1]; ++j) {
+                    if (j == i) continue;
+                    const double pj[3] = {s->p[0 * N + j], s->p[1 * N + j], s->p[2 * N + j]};
+                    Fa[2] += orc_downwash_pair(P, p, pj);
+                }
+            }
+            orc_quat_to_rot(q, R);
+            double *y = Y + (size_t)i * 6;
+            for (int a = 0; a < 3; ++a) y[a] = R[0 * 3 + a] * Fa[0] + R[1 * 3 + a] * Fa[1] + R[2 * 3 + a] * Fa[2];
+            y[3] = y[4] = y[5] = 0.0;
+        }
+    }
+    return 0;
+}
+
+/* Round to the nearest bfloat16 value (8 significant bits), ties to even. */
+double orc_bf16_round(double x)
+{
+    if (x == 0.0 || !isfinite(x)) return x;
+    int e;
+    const double m = frexp(x, &e);
+    return ldexp(nearbyint(ldexp(m, 8)), e - 8);
+}
+
+static double silu(double z) { return z / (1.0 + exp(-z)); }
+
+static double silu_grad(double z)
+{
+    const double sg = 1.0 / (1.0 + exp(-z));
+    return sg * (1.0 + z * (1.0 - sg));
+}
+
+/* Multilayer perceptron y = W_L h_{L-1} + b_L, h_l = SiLU(W_l h_{l-1} + b_l),
+ * h_0 = x.  W[l] is [dims[l+1]][dims[l]] row-major.  acts receives, per layer,
+ * the pre-activation z_l [B][dims[l+1]] followed by the output h_l
+ * [B][dims[l+1]] (h = z for the last layer).  With bf16_acts the input and
+ * every hidden output are rounded to bfloat16, the precision the in-step
+ * network stores them in; sums stay in double. */
+int orc_mlp_forward(int n_layers, const int32_t *dims, const double *const *W,
+                    const double *const *b, int B, const double *X, double *Y, double *acts,
+                    int bf16_acts)
+{
+    size_t off = 0;
+    const double *hin = X;
+    double *xr = NULL;
+    if (bf16_acts) {
+        xr = (double *)malloc(sizeof(double) * (size_t)B * dims[0]);
+        if (!xr) return -2;
+        for (size_t t = 0; t < (size_t)B * dims[0]; ++t) xr[t] = orc_bf16_round(X[t]);
+        hin = xr;
+    }
+    for (int l = 0; l < n_layers; ++l) {
+        const int din = dims[l], dout = dims[l + 1];
+        double *z = acts + off;
+        double *h = acts + off + (size_t)B * dout;
+        off += 2 * (size_t)B * dout;
+#pragma omp parallel for schedule(static)
+        for (int r = 0; r < B; ++r) {
+            for (int o = 0; o < dout; ++o) {
+                double sacc = b[l][o];
+                for (int c = 0; c < din; ++c) sacc += W[l][(size_t)o * din + c] * hin[(size_t)r * din + c];
+                z[(size_t)r * dout + o] = sacc;
+                double hv = (l < n_layers - 1) ? silu(sacc) : sacc;
+                if (bf16_acts && l < n_layers - 1) hv = orc_bf16_round(hv);
+                h[(size_t)r * dout + o] = hv;
+            }
+        }
+        hin = h;
+    }
+    memcpy(Y, hin, sizeof(double) * (size_t)B * dims[n_layers]);
+    free(xr);
+    return 0;
+}
+
+/* Reverse-mode gradient of the network above for upstream gradient dY
+ * [B][dims[L]]: dW[l] = sum_r g_l[r] h_{l-1}[r]^T, db[l] = sum_r g_l[r],
+ * g_{l-1} = (W_l^T g_l) * SiLU'(z_{l-1}); dX = W_0^T g_0 (may be NULL).
+ * X must be the input exactly as the forward pass used it. */
+int orc_mlp_backward(int n_layers, const int32_t *dims, const double *const *W,
+                     const double *const *b, int B, const double *X, const double *acts,
+                     const double *dY, double *const *dW, double *const *db, double *dX)
+{
+    (void)b;
+    size_t *offs = (size_t *)malloc(sizeof(size_t) * (size_t)n_layers);
+    int maxd = 0;
+    for (int l = 0; l <= n_layers; ++l)
+        if (dims[l] > maxd) maxd = dims[l];
+    double *g = (double *)malloc(sizeof(double) * (size_t)B * maxd);
+    double *gn = (double *)malloc(sizeof(double) * (size_t)B * maxd);
+    if (!offs || !g || !gn) {
+        free(offs);
+        free(g);
+        free(gn);
+        return -2;
+    }
+    size_t off = 0;
+    for (int l = 0; l < n_layers; ++l) {
+        offs[l] = off;
+        off += 2 * (size_t)B * dims[l + 1];
+    }
+    memcpy(g, dY, sizeof(double) * (size_t)B * dims[n_layers]);
+    for (int l = n_layers - 1; l >= 0; --l) {
+        const int din = dims[l], dout = dims[l + 1];
+        const double *hin = (l == 0) ? X : acts + offs[l - 1] + (size_t)B * dims[l];
+#pragma omp parallel for schedule(static)
+        for (int o = 0; o < dout; ++o) {
+            double sb = 0.0;
+            for (int r = 0; r < B; ++r) sb += g[(size_t)r * dout + o];
+            db[l][o] = sb;
+            for (int c = 0; c < din; ++c) {
+                double sw = 0.0;
+                for (int r = 0; r < B; ++r) sw += g[(size_t)r * dout + o] * hin[(size_t)r * din + c];
+                dW[l][(size_t)o * din + c] = sw;
+            }
+        }
+        if (l == 0 && !dX) break;
+#pragma omp parallel for schedule(static)
+        for (int r = 0; r < B; ++r) {
+            for (int c = 0; c < din; ++c) {
+                double sacc = 0.0;
+                for (int o = 0; o < dout; ++o) sacc += W[l][(size_t)o * din + c] * g[(size_t)r * dout + o];
+                if (l > 0) {
+                    const double zp = acts[offs[l - 1] + (size_t)r * din + c];
+                    gn[(size_t)r * din + c] = sacc * silu_grad(zp);
+                } else {
+                    dX[(size_t)r * din + c] = sacc;
+                }
+            }
+        }
+        if (l > 0) {
+            double *t = g;
+            g = gn;
+            gn = t;
+        }
+    }
+    free(offs);
+    free(g);
+    free(gn);
+    return 0;
+}
+
+/* Adam (Kingma and Ba): m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2,
+ * param -= lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps), t >= 1. */
+void orc_adam(int n, double *param, const double *grad, double *m1, double *m2, double lr,
+              double beta1, double beta2, double eps, int64_t t)
+{
+    const double bc1 = 1.0 - pow(beta1, (double)t), bc2 = 1.0 - pow(beta2, (double)t);
+    for (int i = 0; i < n; ++i) {
+        m1[i] = beta1 * m1[i] + (1.0 - beta1) * grad[i];
+        m2[i] = beta2 * m2[i] + (1.0 - beta2) * grad[i] * grad[i];
+        const double mh = m1[i] / bc1, vh = m2[i] / bc2;
+        param[i] -= lr * mh / (sqrt(vh) + eps);
+    }
+}

@@ -1,0 +1,103 @@
+/*
+ * md_oracle.h -- FP64 CPU oracle for the batched explicit quadrotor step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, obviously-correct
+ * reference of what the GPU path computes.  Only the test-suite, the smoke
+ * check and the CPU-baseline leg of the benchmark may load it.  It shares no
+ * code, header, table or helper with the HIP library and never calls it.
+ *
+ * Every routine follows the paper (MuJoCo-Drones-Gym) step by step:
+ *   - motor model and X mixer            : Sec. "Quadrotor Dynamics", Eq. (1)-(3)
+ *   - ground effect                      : Sec. "Aerodynamic effects", Eq. (4)
+ *   - blade drag                         : Sec. "Aerodynamic effects", Eq. (5)
+ *   - downwash                           : Sec. "Aerodynamic effects", Eq. (6)
+ *   - explicit integrator + exp map      : Sec. "Physics Modes", Eq. (7)
+ *   - HOVER_RPM / MAX_RPM                : Sec. "Drone Models", Table "Drone model parameters"
+ *   - cascaded PID                       : Sec. "Control", Eq. (9), Table "Default PIDControl gains"
+ *   - KIN observation                    : Sec. "Observation types"
+ * Readings of silent / ambiguous passages are noted at each routine.
+ *
+ * Parity status: every routine is pinned by CPU tests (closed forms,
+ * invariants, library routines, brute force) except the physical values of
+ * C_gnd, c_xy, c_z and the h_clip rule (not printed in the paper) and the
+ * PID allocation in saturated cases: "parity unpinned" for those.
+ */
+#ifndef MD_ORACLE_H
+#define MD_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_params {
+    double m, L, kf, km, Ixx, Iyy, Izz, thrust2weight, r_p, g;
+    double C_gnd, c_xy, c_z, C1, C2, C3, dw_dz_min;
+    double pos_kp[3], pos_ki[3], pos_kd[3], pos_i_clamp;
+    double att_kp[3], att_ki[3], att_kd[3], att_i_clamp;
+} orc_params;
+
+typedef struct orc_derived {
+    double hover_rpm, max_rpm, max_thrust, h_clip;
+} orc_derived;
+
+/* SoA state, component-major: p[c*n + i]. */
+typedef struct orc_state {
+    double *p;       /* [3][n] world position, m                         */
+    double *q;       /* [4][n] body->world quaternion, w,x,y,z            */
+    double *v;       /* [3][n] world linear velocity, m/s                 */
+    double *w;       /* [3][n] body angular velocity, rad/s               */
+    double *pid_int; /* [6][n] position (0..2) and attitude (3..5) sums   */
+    double *rpm;     /* [4][n] rotor speeds applied in the last step, RPM */
+} orc_state;
+
+enum { ORC_AERO_GND = 1, ORC_AERO_DRAG = 2, ORC_AERO_DW = 4, ORC_AERO_SURROGATE = 8 };
+enum { ORC_ACT_RPM = 0, ORC_ACT_PID = 1 };
+
+void orc_params_cf2x(orc_params *P);
+void orc_derive(const orc_params *P, orc_derived *D);
+
+void orc_quat_to_rot(const double q[4], double R[9]);
+void orc_quat_mul(const double a[4], const double b[4], double out[4]);
+void orc_euler_zyx(const double q[4], double rpy[3]);
+
+void orc_motor(const orc_params *P, const double n[4], double F[4], double *T, double tau[3]);
+double orc_ground_effect(const orc_params *P, const orc_derived *D, const double n[4],
+                         double pz, const double q[4]);
+void orc_drag(const orc_params *P, const double n[4], const double q[4], const double v[3],
+              double Fw[3]);
+double orc_downwash_pair(const orc_params *P, const double p_low[3], const double p_other[3]);
+void orc_pid(const orc_params *P, const orc_derived *D, double dt_c, const double p[3],
+             const double q[4], const double v[3], const double w[3], const double target[4],
+             double integ[6], double n_out[4]);
+void orc_integrate(const orc_params *P, double dt, const double Fw[3], const double tau[3],
+                   double p[3], double q[4], double v[3], double w[3]);
+
+int orc_step(const orc_params *P, double dt, uint32_t aero_mask, int act_type, int ctrl_decim,
+             int n_envs, const int32_t *env_offsets, int n_drones, orc_state *s,
+             const double *action, int action_per_step, double *obs, int n_obs_slots,
+             int n_steps, int64_t step0, int n_threads);
+
+/* ---- surrogate support ------------------------------------------------ */
+int orc_knn(int n_envs, const int32_t *env_offsets, int n_drones, const double *p, int k,
+            int32_t *nbr);
+int orc_features(const orc_params *P, int n_envs, const int32_t *env_offsets, int n_drones,
+                 const orc_state *s, const int32_t *nbr, int k, int n_feat, double *X);
+int orc_aero_residual(const orc_params *P, uint32_t aero_mask, int n_envs,
+                      const int32_t *env_offsets, int n_drones, const orc_state *s,
+                      const double *rpm, double *Y);
+int orc_mlp_forward(int n_layers, const int32_t *dims, const double *const *W,
+                    const double *const *b, int B, const double *X, double *Y, double *acts,
+                    int bf16_acts);
+int orc_mlp_backward(int n_layers, const int32_t *dims, const double *const *W,
+                     const double *const *b, int B, const double *X, const double *acts,
+                     const double *dY, double *const *dW, double *const *db, double *dX);
+void orc_adam(int n, double *param, const double *grad, double *m1, double *m2, double lr,
+              double beta1, double beta2, double eps, int64_t t);
+double orc_bf16_round(double x);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,155 @@
+"""Seeded synthetic inputs for the batched quadrotor step.
+
+This module only draws inputs: initial states, rotor-speed or waypoint
+actions and ragged environment layouts.  It holds none of the method's
+arithmetic -- quantities such as the hover rotor speed are passed in by the
+caller -- and it imports nothing else from this package, so both the HIP path
+and the CPU oracle consume exactly the same float32 buffers.
+
+State arrays are float32, component-major ``[c][N]``:
+``p[3], q[4] (w,x,y,z), v[3], w[3], pid_int[6], rpm[4]``.
+
+Workloads (dt = 1/240 s):
+
+* ``single``       1 env x 1 drone at (0,0,1), level, at rest; rotor speeds
+                   hover*(1+u), u ~ U[-0.05, 0.05] per step and motor;
+                   no aerodynamic terms; ``jitter=0`` gives the pure hover run.
+* ``pid_field``    E envs x 1 drone, xy ~ U[-1,1]^2, z ~ U[0.05,1.5], random
+                   yaw, at rest; waypoints U[-2,2]^2 x U[0.2,2], yaw 0;
+                   PID every 5 steps; ground effect + drag.
+* ``ragged_grid``  E envs with M ~ U{2..32} drones on distinct cells of a
+                   4x4x4 grid of 0.15 m pitch (origin (-0.225,-0.225,0.5)),
+                   level, at rest; per-step rotor speeds hover*(1+U[-0.1,0.1]);
+                   ground effect + drag + downwash.
+* ``lattice``      E envs x (nx*ny*nz) drones on a yawed lattice with lateral
+                   pitch U[1.0,1.3] m, vertical pitch U[0.9,1.0] m, lower layer
+                   at z ~ U[0.3,0.5]; PID waypoints = lattice point +
+                   U[-0.05,0.05]^3, start = waypoint + U[-0.1,0.1]^3.
+                   2x2x2 / 16384 envs is the surrogate workload, 4x4x2 / 8192
+                   envs the formation workload.
+"""
+import numpy as np
+
+STATE_ROWS = (("p", 3), ("q", 4), ("v", 3), ("w", 3), ("pid_int", 6), ("rpm", 4))
+DT = 1.0 / 240.0
+
+
+def empty_state(n):
+    s = {k: np.zeros((r, n), dtype=np.float32) for k, r in STATE_ROWS}
+    s["q"][0] = 1.0
+    return s
+
+
+def _yaw_quat(yaw):
+    # A rotation by `yaw` about world z, as a [w, x, y, z] unit quaternion.
+    return np.cos(0.5 * yaw), np.sin(0.5 * yaw)
+
+
+def single(hover_rpm, n_steps=240, jitter=0.05, seed=0):
+    rng = np.random.default_rng(seed)
+    s = empty_state(1)
+    s["p"][2, 0] = 1.0
+    u = rng.uniform(-jitter, jitter, size=(n_steps, 4, 1)) if jitter > 0 else np.zeros((n_steps, 4, 1))
+    act = (hover_rpm * (1.0 + u)).astype(np.float32)
+    return dict(name="single", env_offsets=np.array([0, 1], dtype=np.int32), state=s,
+                action=act, action_per_step=True, aero_mask=0, act_type="rpm",
+                ctrl_decim=1, n_steps=n_steps, dt=DT)
+
+
+def pid_field(n_envs=4096, n_steps=2400, seed=1):
+    rng = np.random.default_rng(seed)
+    n = n_envs
+    s = empty_state(n)
+    s["p"][0:2] = rng.uniform(-1.0, 1.0, size=(2, n))
+    s["p"][2] = rng.uniform(0.05, 1.5, size=n)
+    yaw = rng.uniform(-np.pi, np.pi, size=n)
+    cw, sz = _yaw_quat(yaw)
+    s["q"][0], s["q"][3] = cw, sz
+    tgt = np.zeros((4, n), dtype=np.float32)
+    tgt[0:2] = rng.uniform(-2.0, 2.0, size=(2, n))
+    tgt[2] = rng.uniform(0.2, 2.0, size=n)
+    return dict(name="pid_field", env_offsets=np.arange(n + 1, dtype=np.int32), state=s,
+                action=tgt[None], action_per_step=False, aero_mask=1 | 2, act_type="pid",
+                ctrl_decim=5, n_steps=n_steps, dt=DT)
+
+
+def ragged_grid(hover_rpm, n_envs=1024, n_steps=100, m_lo=2, m_hi=32, pitch=0.15, seed=2):
+    rng = np.random.default_rng(seed)
+    m = rng.integers(m_lo, m_hi + 1, size=n_envs)
+    off = np.zeros(n_envs + 1, dtype=np.int32)
+    off[1:] = np.cumsum(m)
+    n = int(off[-1])
+    s = empty_state(n)
+    g = np.arange(4)
+    cells = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    origin = np.array([-0.225, -0.225, 0.5])
+    for e in range(n_envs):
+        pick = rng.permutation(64)[: m[e]]
+        pos = origin + pitch * cells[pick]
+        s["p"][:, off[e]:off[e + 1]] = pos.T
+    u = rng.uniform(-0.1, 0.1, size=(n_steps, 4, n))
+    act = (hover_rpm * (1.0 + u)).astype(np.float32)
+    return dict(name="ragged_grid", env_offsets=off, state=s, action=act, action_per_step=True,
+                aero_mask=1 | 2 | 4, act_type="rpm", ctrl_decim=1, n_steps=n_steps, dt=DT)
+
+
+def lattice(n_envs=16384, shape=(2, 2, 2), n_steps=1000, seed=3, target_jitter=0.05,
+            start_jitter=0.1):
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    m = nx * ny * nz
+    n = n_envs * m
+    off = (np.arange(n_envs + 1) * m).astype(np.int32)
+    sxy = rng.uniform(1.0, 1.3, size=n_envs)
+    szz = rng.uniform(0.9, 1.0, size=n_envs)
+    yaw = rng.uniform(0.0, 2.0 * np.pi, size=n_envs)
+    z0 = rng.uniform(0.3, 0.5, size=n_envs)
+    ix, iy, iz = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    lx = (ix.ravel() - 0.5 * (nx - 1))
+    ly = (iy.ravel() - 0.5 * (ny - 1))
+    lz = iz.ravel().astype(np.float64)
+    c, sn = np.cos(yaw)[:, None], np.sin(yaw)[:, None]
+    X = sxy[:, None] * (c * lx[None] - sn * ly[None])
+    Y = sxy[:, None] * (sn * lx[None] + c * ly[None])
+    Z = z0[:, None] + szz[:, None] * lz[None]
+    base = np.stack([X.ravel(), Y.ravel(), Z.ravel()])  # [3][n], env-major
+    tgt = np.zeros((4, n), dtype=np.float32)
+    tgt[0:3] = base + rng.uniform(-target_jitter, target_jitter, size=(3, n))
+    s = empty_state(n)
+    s["p"][:] = tgt[0:3].astype(np.float64) + rng.uniform(-start_jitter, start_jitter, size=(3, n))
+    return dict(name="lattice%dx%dx%d" % shape, env_offsets=off, state=s, action=tgt[None],
+                action_per_step=False, aero_mask=1 | 2 | 4, act_type="pid", ctrl_decim=5,
+                n_steps=n_steps, dt=DT)
+
+
+def formation(n_envs=8192, n_steps=1000, seed=4):
+    w = lattice(n_envs=n_envs, shape=(4, 4, 2), n_steps=n_steps, seed=seed)
+    w["name"] = "formation"
+    return w
+
+
+def permute_envs(w, perm):
+    """Same workload with its environments stored in the order ``perm``."""
+    off = w["env_offsets"]
+    idx = np.concatenate([np.arange(off[e], off[e + 1]) for e in perm]) if len(perm) else \
+        np.zeros(0, dtype=np.int64)
+    m = np.diff(off)[perm]
+    noff = np.zeros(len(perm) + 1, dtype=np.int32)
+    noff[1:] = np.cumsum(m)
+    out = dict(w)
+    out["env_offsets"] = noff
+    out["state"] = {k: np.ascontiguousarray(v[:, idx]) for k, v in w["state"].items()}
+    out["action"] = np.ascontiguousarray(w["action"][:, :, idx])
+    out["drone_index"] = idx
+    return out
+
+
+def subset_envs(w, n_envs):
+    """The first n_envs environments of a workload."""
+    off = w["env_offsets"][: n_envs + 1].copy()
+    n = int(off[-1])
+    out = dict(w)
+    out["env_offsets"] = off
+    out["state"] = {k: np.ascontiguousarray(v[:, :n]) for k, v in w["state"].items()}
+    out["action"] = np.ascontiguousarray(w["action"][:, :, :n])
+    return out

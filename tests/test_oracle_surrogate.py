@@ -1,0 +1,193 @@
+"""Pins of the oracle's surrogate support: neighbour search against a brute
+force sort, features against library rotations, the MLP forward/backward
+against PyTorch float64 autograd and central finite differences, Adam against
+torch.optim.Adam, bfloat16 rounding against PyTorch's conversion."""
+import numpy as np
+import pytest
+import torch
+from scipy.spatial.transform import Rotation
+
+import oracle as orc
+
+
+def _env_positions(rng, sizes):
+    off = np.zeros(len(sizes) + 1, dtype=np.int32)
+    off[1:] = np.cumsum(sizes)
+    p = rng.uniform(-1, 1, size=(3, off[-1])).astype(np.float32).astype(np.float64)
+    return off, p
+
+
+def test_knn_matches_brute_force_sort():
+    rng = np.random.default_rng(30)
+    off, p = _env_positions(rng, [1, 2, 5, 9, 12, 33])
+    # plant exact ties: two drones at the same offset from a third
+    p[:, 10] = p[:, 9] + [0.25, 0, 0]
+    p[:, 11] = p[:, 9] + [-0.25, 0, 0]
+    nbr = orc.knn(off, p, 8)
+    pf = p.astype(np.float32)
+    for e in range(len(off) - 1):
+        for i in range(off[e], off[e + 1]):
+            js = np.array([j for j in range(off[e], off[e + 1]) if j != i], dtype=np.int64)
+            d = pf[:, js] - pf[:, [i]]
+            d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]  # float32, same order
+            order = js[np.lexsort((js, d2))][:8]
+            expect = np.full(8, -1)
+            expect[: len(order)] = order
+            np.testing.assert_array_equal(nbr[i], expect)
+    assert nbr[9][0] == 10 and nbr[9][1] == 11  # tie broken to the lower index
+
+
+def test_features_match_library_rotations():
+    rng = np.random.default_rng(31)
+    P = orc.cf2x()
+    D = orc.derive(P)
+    off, p = _env_positions(rng, [3, 10])
+    n = off[-1]
+    s = orc.new_state(n)
+    s["p"][:] = p
+    rots = Rotation.random(n, random_state=rng)
+    xyzw = rots.as_quat()
+    s["q"][:] = np.stack([xyzw[:, 3], xyzw[:, 0], xyzw[:, 1], xyzw[:, 2]])
+    s["v"][:] = rng.normal(size=(3, n))
+    s["rpm"][:] = rng.uniform(10000, 20000, size=(4, n))
+    nbr = orc.knn(off, p, 8)
+    X = orc.features(P, off, s, nbr)
+    assert X.shape == (n, 64)
+    np.testing.assert_allclose(X[:, 0:3], rots.inv().apply(s["v"].T), atol=1e-12)
+    np.testing.assert_allclose(X[:, 3:6], rots.inv().apply([0, 0, 1]), atol=1e-12)
+    np.testing.assert_allclose(X[:, 6:10], s["rpm"].T / D.hover_rpm, rtol=1e-15)
+    for i in range(n):
+        for t in range(8):
+            j = nbr[i, t]
+            blk = X[i, 10 + 6 * t: 16 + 6 * t]
+            if j < 0:
+                assert np.all(blk == 0)
+            else:
+                np.testing.assert_allclose(blk[:3], p[:, j] - p[:, i], rtol=1e-15)
+                np.testing.assert_allclose(blk[3:], s["v"][:, j] - s["v"][:, i], rtol=1e-15)
+    np.testing.assert_array_equal(X[:, 58], p[2])
+    assert np.all(X[:, 59:] == 0)
+
+
+def test_aero_residual_is_body_frame_sum_of_terms():
+    rng = np.random.default_rng(32)
+    P = orc.cf2x()
+    off, p = _env_positions(rng, [4])
+    p[2] += 1.5
+    s = orc.new_state(4)
+    s["p"][:] = p
+    rots = Rotation.random(4, random_state=rng)
+    xyzw = rots.as_quat()
+    s["q"][:] = np.stack([xyzw[:, 3], xyzw[:, 0], xyzw[:, 1], xyzw[:, 2]])
+    s["v"][:] = rng.normal(size=(3, 4))
+    rpm = rng.uniform(10000, 20000, size=(4, 4))
+    mask = orc.AERO_GND | orc.AERO_DRAG | orc.AERO_DW
+    Y = orc.aero_residual(P, mask, off, s, rpm)
+    for i in range(4):
+        Fw = orc.drag(P, rpm[:, i], s["q"][:, i], s["v"][:, i])
+        Fw[2] += orc.ground_effect(P, rpm[:, i], p[2, i], s["q"][:, i])
+        for j in range(4):
+            if j != i:
+                Fw[2] += orc.downwash_pair(P, p[:, i], p[:, j])
+        np.testing.assert_allclose(Y[i, :3], rots[i].inv().apply(Fw), rtol=1e-10, atol=1e-18)
+        assert np.all(Y[i, 3:] == 0)
+
+
+def _net(rng, dims):
+    Ws = [rng.normal(size=(dims[l + 1], dims[l])) / np.sqrt(dims[l]) for l in range(len(dims) - 1)]
+    bs = [rng.normal(size=dims[l + 1]) * 0.1 for l in range(len(dims) - 1)]
+    return Ws, bs
+
+
+def _torch_net(Ws, bs):
+    layers = []
+    for l, (W, b) in enumerate(zip(Ws, bs)):
+        lin = torch.nn.Linear(W.shape[1], W.shape[0]).double()
+        with torch.no_grad():
+            lin.weight.copy_(torch.from_numpy(W))
+            lin.bias.copy_(torch.from_numpy(b))
+        layers.append(lin)
+        if l < len(Ws) - 1:
+            layers.append(torch.nn.SiLU())
+    return torch.nn.Sequential(*layers)
+
+
+def test_mlp_forward_backward_match_torch_float64():
+    rng = np.random.default_rng(33)
+    dims = [64, 128, 128, 128, 6]
+    Ws, bs = _net(rng, dims)
+    X = rng.normal(size=(37, 64))
+    dY = rng.normal(size=(37, 6))
+    Y, acts = orc.mlp_forward(Ws, bs, X)
+    net = _torch_net(Ws, bs)
+    xt = torch.from_numpy(X).requires_grad_(True)
+    yt = net(xt)
+    np.testing.assert_allclose(Y, yt.detach().numpy(), rtol=1e-12, atol=1e-13)
+    yt.backward(torch.from_numpy(dY))
+    dWs, dbs, dX = orc.mlp_backward(Ws, bs, X, acts, dY, want_dx=True)
+    lins = [m for m in net if isinstance(m, torch.nn.Linear)]
+    for l, lin in enumerate(lins):
+        np.testing.assert_allclose(dWs[l], lin.weight.grad.numpy(), rtol=1e-10, atol=1e-12)
+        np.testing.assert_allclose(dbs[l], lin.bias.grad.numpy(), rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(dX, xt.grad.numpy(), rtol=1e-10, atol=1e-12)
+
+
+def test_mlp_backward_matches_central_differences():
+    rng = np.random.default_rng(34)
+    dims = [7, 9, 8, 3]
+    Ws, bs = _net(rng, dims)
+    X = rng.normal(size=(5, 7))
+    dY = rng.normal(size=(5, 3))
+    loss = lambda Ws_, bs_: float(np.sum(orc.mlp_forward(Ws_, bs_, X)[0] * dY))
+    _, acts = orc.mlp_forward(Ws, bs, X)
+    dWs, dbs, _ = orc.mlp_backward(Ws, bs, X, acts, dY)
+    h = 1e-6
+    for l in range(len(Ws)):
+        for (o, c) in [(0, 0), (1, 2), (dims[l + 1] - 1, dims[l] - 1)]:
+            Wp = [W.copy() for W in Ws]
+            Wm = [W.copy() for W in Ws]
+            Wp[l][o, c] += h
+            Wm[l][o, c] -= h
+            fd = (loss(Wp, bs) - loss(Wm, bs)) / (2 * h)
+            assert dWs[l][o, c] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+        bp = [b.copy() for b in bs]
+        bm = [b.copy() for b in bs]
+        bp[l][1] += h
+        bm[l][1] -= h
+        fd = (loss(Ws, bp) - loss(Ws, bm)) / (2 * h)
+        assert dbs[l][1] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_adam_matches_torch():
+    rng = np.random.default_rng(35)
+    w0 = rng.normal(size=50)
+    grads = [rng.normal(size=50) for _ in range(4)]
+    wt = torch.nn.Parameter(torch.from_numpy(w0.copy()))
+    opt = torch.optim.Adam([wt], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    w, m1, m2 = w0.copy(), np.zeros(50), np.zeros(50)
+    for t, g in enumerate(grads, start=1):
+        wt.grad = torch.from_numpy(g.copy())
+        opt.step()
+        orc.adam(w, g.copy(), m1, m2, 1e-2, 0.9, 0.999, 1e-8, t)
+    np.testing.assert_allclose(w, wt.detach().numpy(), rtol=1e-13, atol=1e-15)
+
+
+def test_bf16_round_matches_torch():
+    rng = np.random.default_rng(36)
+    x = rng.normal(size=2000).astype(np.float32) * np.exp(rng.uniform(-20, 20, 2000)).astype(np.float32)
+    # exact ties between two bfloat16 values
+    ties = np.array([1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -3.0 - 2 ** -7], dtype=np.float32)
+    x = np.concatenate([x, ties])
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(orc.bf16_round(x.astype(np.float64)), ref)
+
+
+def test_bf16_forward_rounds_input_and_hidden_only():
+    rng = np.random.default_rng(37)
+    Ws, bs = _net(rng, [5, 6, 2])
+    X = rng.normal(size=(3, 5))
+    Y, acts = orc.mlp_forward(Ws, bs, X, bf16_acts=True)
+    Xr = orc.bf16_round(X)
+    z1 = Xr @ Ws[0].T + bs[0]
+    h1 = orc.bf16_round(z1 / (1 + np.exp(-z1)))
+    np.testing.assert_allclose(Y, h1 @ Ws[1].T + bs[1], rtol=1e-13)
