@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Throughput of the batched explicit quadrotor step on one MI355X.
+
+A bench "step" is one rollout of the whole hot path over the workload: one
+md_step call advancing every drone `physics_steps` steps (rotor speeds from
+the PID, motor model, ground effect, drag, pairwise downwash, Newton-Euler,
+exponential map, KIN-20 observation written to HBM every physics step).
+Throughput is drone-steps/s = drones x physics steps x K / time of K rollouts,
+inputs resident in HBM before the timed region.
+
+Default workload: 8192 environments x 32 drones (262,144 drones) on yawed
+4x4x2 lattices, PID formation targets, ground effect + drag + downwash,
+1000 physics steps per rollout, KIN-20 observation rows [1000][20][N] fp32.
+
+    python bench.py [--steps K] [--warmup W] [--workload formation|pid_field|ragged_grid|lattice8]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+METRIC = "drone-steps/s on 1 MI355X, full aero plain vs MLP-surrogate at ≤2% force err"
+
+# Algorithmic work per drone-step (FMA = 2 FLOP; transcendental calls are
+# not counted as FLOP).  Base: motor model + mixer, rotation matrix,
+# Newton-Euler, exponential map, renormalisation.
+FLOP_BASE = 130
+FLOP_GND = 8
+FLOP_DRAG = 55
+FLOP_DW_CANDIDATE = 6      # dx, dy, dz, dxy^2, two compares
+FLOP_DW_PAIR = 13          # alpha, beta, beta^2, exponent, product, accumulate
+FLOP_PID_UPDATE = 110
+FLOP_OBS = 15
+OBS_BYTES = 80             # 20 float32 per drone-step
+STATE_BYTES = 2 * 4 * 23   # state read + written once per launch (p,q,v,w,pid_int,rpm)
+
+
+def workload(name, hover):
+    from paper_2606_08039_amd import workloads as wl
+    if name == "formation":
+        w = wl.formation(n_envs=8192, n_steps=1000, seed=4)
+        return w, dict(workload="formation_8192x32_pid_gnd_drag_dw_kin20", n_envs=8192,
+                       drones_per_env=32, obs="KIN-20 every physics step")
+    if name == "lattice8":
+        w = wl.lattice(n_envs=16384, shape=(2, 2, 2), n_steps=1000, seed=3)
+        return w, dict(workload="lattice_16384x8_pid_gnd_drag_dw", n_envs=16384, drones_per_env=8,
+                       obs="none")
+    if name == "pid_field":
+        w = wl.pid_field(n_envs=4096, n_steps=2400, seed=1)
+        return w, dict(workload="pid_field_4096x1_pid_gnd_drag", n_envs=4096, drones_per_env=1,
+                       obs="none")
+    if name == "ragged_grid":
+        w = wl.ragged_grid(hover, n_envs=1024, n_steps=100, seed=2)
+        return w, dict(workload="ragged_grid_1024_envs_M2to32_rpm_gnd_drag_dw", n_envs=1024,
+                       drones_per_env="U{2..32}", obs="none")
+    raise SystemExit("unknown workload " + name)
+
+
+def algorithmic_counts(w, with_obs):
+    """FLOP and HBM bytes the method needs per rollout (one md_step call)."""
+    off = np.asarray(w["env_offsets"], dtype=np.int64)
+    m = np.diff(off)
+    n = int(off[-1])
+    K = w["n_steps"]
+    mask = w["aero_mask"]
+    per_drone = FLOP_BASE + (FLOP_GND if mask & 1 else 0) + (FLOP_DRAG if mask & 2 else 0)
+    if w["act_type"] == "pid":
+        per_drone += FLOP_PID_UPDATE / w["ctrl_decim"]
+    if with_obs:
+        per_drone += FLOP_OBS
+    flop = per_drone * n * K
+    if mask & 4:
+        # ordered candidate pairs (i, j != i) per env, about half of them pass dz > 0
+        cand = float(np.sum(m * (m - 1)))
+        flop += (FLOP_DW_CANDIDATE * cand + FLOP_DW_PAIR * cand / 2) * K
+    act_bytes = 16 * n * (K if w["action_per_step"] else 1)
+    bytes_ = STATE_BYTES * n + act_bytes + (OBS_BYTES * n * K if with_obs else 0)
+    return flop, bytes_
+
+
+def cpu_baseline(w, with_obs, seconds_target=12.0):
+    """The FP64 oracle on a bounded sample of the same workload."""
+    import oracle as orc
+    from paper_2606_08039_amd import workloads as wl
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
+    P = orc.cf2x()
+    off = np.asarray(w["env_offsets"])
+    # calibration pass on a few environments, then a sample sized to the target
+    def run(n_envs, steps):
+        sub = wl.subset_envs(w, n_envs)
+        s = {k: v.astype(np.float64) for k, v in sub["state"].items()}
+        act = sub["action"][:steps] if w["action_per_step"] else sub["action"]
+        n = int(sub["env_offsets"][-1])
+        t0 = time.perf_counter()
+        orc.step(P, w["dt"], w["aero_mask"], orc.ACT_RPM if w["act_type"] == "rpm" else orc.ACT_PID,
+                 w["ctrl_decim"], sub["env_offsets"], s, act.astype(np.float64),
+                 w["action_per_step"], steps, n_obs_slots=1 if with_obs else 0,
+                 n_threads=threads)
+        return n * steps, time.perf_counter() - t0
+    n_env_total = len(off) - 1
+    e0 = min(n_env_total, 64)
+    ds, dtm = run(e0, min(10, w["n_steps"]))
+    rate = ds / max(dtm, 1e-9)
+    steps = min(w["n_steps"], 100)
+    want = rate * seconds_target / steps  # drones for ~seconds_target wall
+    per_env = max(1, ds // (e0 * min(10, w["n_steps"])))
+    envs = int(max(1, min(n_env_total, want / per_env)))
+    ds, dtm = run(envs, steps)
+    return {"value": ds / dtm, "unit": "drone-steps/s", "cores": threads, "kind": "oracle",
+            "sample": "%d envs (%d drones) x %d physics steps of the same workload, FP64 C oracle, "
+                      "KIN rows to a 1-slot ring, %d OpenMP threads, %.1f s wall"
+                      % (envs, ds // steps, steps, threads, dtm)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="formation")
+    ap.add_argument("--no-obs", action="store_true", help="skip the KIN-20 writes")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for HBM counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus %d is not supported "
+              "(environments shard across GPUs with no per-step exchange; see DESIGN.md)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2606_08039_amd import md
+
+    torch.cuda.set_device(0)
+    p = md.md_default_params_cf2x()
+    hover = md.md_derive(p).hover_rpm
+    w, cfg = workload(args.workload, hover)
+    with_obs = (cfg["obs"] != "none") and not args.no_obs
+    n = int(w["env_offsets"][-1])
+    K = w["n_steps"]
+    act = md.MD_ACT_RPM if w["act_type"] == "rpm" else md.MD_ACT_PID
+
+    ctx = md.md_create(p, w["dt"], w["aero_mask"], act, w["ctrl_decim"])
+    md.md_bind_layout(ctx, w["env_offsets"])
+    state = md.DeviceState.from_numpy(w["state"])
+    action = torch.from_numpy(np.ascontiguousarray(w["action"], dtype=np.float32)).cuda()
+    obs = torch.empty((K, 20, n), dtype=torch.float32, device="cuda") if with_obs else None
+    n_slots = K if with_obs else 0
+    stream = torch.cuda.current_stream()
+
+    step0 = 0
+    for _ in range(args.warmup):
+        md.md_step(ctx, state, action, w["action_per_step"], obs, n_slots, K, step0, stream)
+        step0 += K
+    torch.cuda.synchronize()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        md.md_step(ctx, state, action, w["action_per_step"], obs, n_slots, K, step0, stream)
+        ev[i][1].record(stream)
+        step0 += K
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kernel_ms = [a.elapsed_time(b) for a, b in ev]
+    md.md_destroy(ctx)
+
+    wall = t1 - t0
+    ds = float(n) * K * args.steps
+    value = ds / wall
+    flop, bytes_ = algorithmic_counts(w, with_obs)
+    kavg = float(np.mean(kernel_ms)) * 1e-3
+    hbm = bytes_ / kavg / 1e9
+    alu = flop / kavg / 1e12
+    if with_obs:
+        roof = {"bound": "hbm", "achieved": round(hbm, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": None}
+    else:
+        roof = {"bound": "alu", "achieved": round(alu, 3), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(alu / FP32_PEAK_TFLOPS, 4), "traffic": None}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "drone-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded lattices / grids, PID targets or rotor speeds)",
+        "config": dict(cfg, n_drones=n, physics_steps_per_rollout=K, dt=w["dt"],
+                       aero="GND|DRAG|DW" if w["aero_mask"] == 7 else "GND|DRAG" if w["aero_mask"] == 3 else w["aero_mask"],
+                       action="pid waypoints, ctrl_decim %d" % w["ctrl_decim"] if w["act_type"] == "pid"
+                       else "rotor speeds per step", path="plain aero"),
+        "roofline": roof,
+        "roofline_alu": {"bound": "alu", "achieved": round(alu, 3), "peak": FP32_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(alu / FP32_PEAK_TFLOPS, 4)},
+        "kernel_ms_avg": kavg * 1e3,
+        "algorithmic_bytes_per_launch": bytes_,
+        "algorithmic_flop_per_launch": flop,
+    }
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": a.numel() * 4, "write": a.numel() * 4}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, with_obs)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,406 @@
+// md_api.cpp -- host implementation of the libmd C ABI (include/md.h).
+//
+// Validates arguments, owns the per-context device tables (environment bins),
+// turns md_params into the kernels' float32 constants and launches the step
+// kernel on the caller's stream.  No C++ exception crosses the ABI.
+#include "md.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "md_ctx.h"
+
+using md::KConst;
+
+static thread_local std::string g_create_err;
+
+namespace md {
+
+std::string hip_msg(const char *what, hipError_t e) {
+    return std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+}
+
+void derive(const md_params &p, md_derived &d) {
+    d.hover_rpm = std::sqrt(p.m * p.g / (4.0 * p.kf));
+    d.max_rpm = std::sqrt(p.thrust2weight * p.m * p.g / (4.0 * p.kf));
+    d.max_thrust = 4.0 * p.kf * d.max_rpm * d.max_rpm;
+    // height at which one rotor at MAX_RPM gains MAX_THRUST / 15 from Eq. 4
+    d.h_clip = 0.25 * p.r_p * std::sqrt(15.0 * p.C_gnd * p.kf * d.max_rpm * d.max_rpm / d.max_thrust);
+}
+
+KConst make_kconst(const md_params &p, const md_derived &d, double dt, int decim) {
+    KConst c;
+    std::memset(&c, 0, sizeof c);
+    c.dt = (float)dt;
+    c.m = (float)p.m;
+    c.m_inv = (float)(1.0 / p.m);
+    c.g = (float)p.g;
+    c.mg = (float)(p.m * p.g);
+    c.kf = (float)p.kf;
+    c.km = (float)p.km;
+    c.l_arm = (float)(p.L / std::sqrt(2.0));
+    c.Jx = (float)p.Ixx;
+    c.Jy = (float)p.Iyy;
+    c.Jz = (float)p.Izz;
+    c.Jx_inv = (float)(1.0 / p.Ixx);
+    c.Jy_inv = (float)(1.0 / p.Iyy);
+    c.Jz_inv = (float)(1.0 / p.Izz);
+    c.max_rpm = (float)d.max_rpm;
+    c.h_clip = (float)d.h_clip;
+    c.K_gnd = (float)(p.C_gnd * p.r_p * p.r_p / 16.0);
+    c.drag_s = (float)(2.0 * M_PI / 60.0);
+    c.c_xy = (float)p.c_xy;
+    c.c_z = (float)p.c_z;
+    c.K1 = (float)(p.C1 * p.r_p * p.r_p / 16.0);
+    c.C2 = (float)p.C2;
+    c.C3 = (float)p.C3;
+    c.dz_min = (float)std::max(0.0, p.dw_dz_min);
+    for (int k = 0; k < 3; ++k) {
+        c.pkp[k] = (float)p.pos_kp[k];
+        c.pki[k] = (float)p.pos_ki[k];
+        c.pkd[k] = (float)p.pos_kd[k];
+        c.akp[k] = (float)p.att_kp[k];
+        c.aki[k] = (float)p.att_ki[k];
+        c.akd[k] = (float)p.att_kd[k];
+    }
+    c.p_clamp = (float)p.pos_i_clamp;
+    c.a_clamp = (float)p.att_i_clamp;
+    c.dt_c = (float)(dt * decim);
+    c.g_inv = (float)(1.0 / p.g);
+    c.l_inv = (float)(std::sqrt(2.0) / p.L);
+    c.kappa_inv = (float)(p.kf / p.km);
+    c.fmax = (float)(p.kf * d.max_rpm * d.max_rpm);
+    c.kf_inv = (float)(1.0 / p.kf);
+    c.hover_inv = (float)(1.0 / d.hover_rpm);
+    c.decim = decim;
+    return c;
+}
+
+// Best-fit-decreasing packing of environments into bins of `slots` drone
+// slots; environments larger than a bin are rejected by the caller.  Each
+// environment occupies a contiguous run of slots.  Bins are ordered by their
+// largest environment, heaviest first, so the longest neighbour sweeps start
+// first.
+static void pack_bins(const std::vector<int32_t> &off, int slots, std::vector<int2> &tab,
+                      std::vector<int> &mmax, int &n_bins) {
+    const int E = (int)off.size() - 1;
+    std::vector<int> order;
+    order.reserve(E);
+    for (int e = 0; e < E; ++e)
+        if (off[e + 1] > off[e]) order.push_back(e);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (off[a + 1] - off[a]) > (off[b + 1] - off[b]);
+    });
+    struct Bin {
+        int used = 0, mmax = 0;
+        std::vector<int> envs;
+    };
+    std::vector<Bin> bins;
+    std::vector<std::vector<int>> by_free(slots + 1);  // bins indexed by free slots
+    for (int e : order) {
+        const int m = off[e + 1] - off[e];
+        int pick = -1;
+        for (int f = m; f <= slots && pick < 0; ++f) {
+            while (!by_free[f].empty()) {
+                const int b = by_free[f].back();
+                by_free[f].pop_back();
+                if (slots - bins[b].used == f) {
+                    pick = b;
+                    break;
+                }
+            }
+        }
+        if (pick < 0) {
+            pick = (int)bins.size();
+            bins.emplace_back();
+        }
+        Bin &B = bins[pick];
+        B.envs.push_back(e);
+        B.used += m;
+        B.mmax = std::max(B.mmax, m);
+        by_free[slots - B.used].push_back(pick);
+    }
+    std::vector<int> border(bins.size());
+    for (size_t b = 0; b < bins.size(); ++b) border[b] = (int)b;
+    std::stable_sort(border.begin(), border.end(),
+                     [&](int a, int b) { return bins[a].mmax > bins[b].mmax; });
+    n_bins = (int)bins.size();
+    tab.assign((size_t)n_bins * slots, make_int2(-1, 0));
+    mmax.assign(n_bins, 0);
+    for (int ob = 0; ob < n_bins; ++ob) {
+        const Bin &B = bins[border[ob]];
+        mmax[ob] = B.mmax;
+        int lo = 0;
+        for (int e : B.envs) {
+            const int m = off[e + 1] - off[e];
+            for (int t = 0; t < m; ++t)
+                tab[(size_t)ob * slots + lo + t] = make_int2(off[e] + t, (lo << 16) | m);
+            lo += m;
+        }
+    }
+}
+
+md_status build_bins(md_ctx *ctx, int slots, BinSet **out) {
+    auto it = ctx->binsets.find(slots);
+    if (it != ctx->binsets.end()) {
+        *out = &it->second;
+        return MD_OK;
+    }
+    if (ctx->max_m > slots) {
+        ctx->err = "environment of " + std::to_string(ctx->max_m) + " drones exceeds a bin of " +
+                   std::to_string(slots) + " slots";
+        return MD_E_UNSUPPORTED;
+    }
+    std::vector<int2> tab;
+    std::vector<int> mm;
+    BinSet bs;
+    pack_bins(ctx->off, slots, tab, mm, bs.n_bins);
+    bs.slots = slots;
+    if (bs.n_bins > 0) {
+        hipError_t e = hipMalloc(&bs.d_slot, sizeof(int2) * tab.size());
+        if (e == hipSuccess) e = hipMalloc(&bs.d_mmax, sizeof(int) * mm.size());
+        if (e != hipSuccess) {
+            (void)hipFree(bs.d_slot);
+            ctx->err = hip_msg("hipMalloc(bin tables)", e);
+            return MD_E_OOM;
+        }
+        e = hipMemcpy(bs.d_slot, tab.data(), sizeof(int2) * tab.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(bs.d_mmax, mm.data(), sizeof(int) * mm.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(bs.d_slot);
+            (void)hipFree(bs.d_mmax);
+            ctx->err = hip_msg("hipMemcpy(bin tables)", e);
+            return MD_E_HIP;
+        }
+        bs.h_mmax = mm;
+    }
+    auto ins = ctx->binsets.emplace(slots, std::move(bs));
+    *out = &ins.first->second;
+    return MD_OK;
+}
+
+void free_bins(md_ctx *ctx) {
+    for (auto &kv : ctx->binsets) {
+        (void)hipFree(kv.second.d_slot);
+        (void)hipFree(kv.second.d_mmax);
+    }
+    ctx->binsets.clear();
+}
+
+int slots_for(const md_ctx *ctx, const LaunchCfg &cfg) {
+    const int lpd = (ctx->mask & MD_AERO_DW) ? cfg.lpd : 1;
+    return 64 * cfg.waves / lpd;
+}
+
+LaunchCfg default_cfg(const md_ctx *ctx) {
+    LaunchCfg c{1, 4, 1};
+    while (64 * c.waves < ctx->max_m && c.waves < 16) c.waves *= 2;
+    return c;
+}
+
+md_status launch(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
+                 float *d_obs, int n_obs_slots, int n_steps, int64_t step0, hipStream_t st,
+                 const LaunchCfg &cfg) {
+    BinSet *bs = nullptr;
+    md_status rc = build_bins(ctx, slots_for(ctx, cfg), &bs);
+    if (rc != MD_OK) return rc;
+    StepArgs a;
+    a.c = ctx->kc;
+    a.s = StatePtr{s->p, s->q, s->v, s->w, s->pid_int, s->rpm};
+    a.action = d_action;
+    a.act_step_stride = action_per_step ? 4LL * ctx->n_drones : 0;
+    a.obs = (n_obs_slots > 0) ? d_obs : nullptr;
+    a.n_obs_slots = n_obs_slots > 0 ? n_obs_slots : 1;
+    a.n_steps = n_steps;
+    a.step0 = step0;
+    a.N = ctx->n_drones;
+    a.bins = BinTables{bs->d_slot, bs->d_mmax};
+    hipError_t e = launch_step(a, ctx->mask, ctx->act, cfg, bs->n_bins, bs->slots, st);
+    if (e != hipSuccess) {
+        ctx->err = hip_msg("step kernel launch", e);
+        return MD_E_HIP;
+    }
+    return MD_OK;
+}
+
+}  // namespace md
+
+extern "C" {
+
+const char *md_version(void) { return "libmd 0.1 (gfx950)"; }
+
+md_status md_default_params_cf2x(md_params *out) {
+    if (!out) return MD_E_INVALID_ARG;
+    std::memset(out, 0, sizeof *out);
+    // Table "Drone model parameters", CF2X
+    out->m = 0.027;
+    out->L = 0.0397;
+    out->thrust2weight = 2.25;
+    out->Ixx = 1.4e-5;
+    out->Iyy = 1.4e-5;
+    out->Izz = 2.17e-5;
+    out->kf = 3.16e-10;
+    out->km = 7.94e-12;
+    out->r_p = 0.02325;
+    out->g = 9.81;
+    // ground effect and drag coefficients (not printed; the predecessor's CF2X values)
+    out->C_gnd = 11.36359;
+    out->c_xy = 9.1785e-7;
+    out->c_z = 10.311e-7;
+    // Eq. 6
+    out->C1 = 2267.18;
+    out->C2 = 0.16;
+    out->C3 = -0.11;
+    out->dw_dz_min = 0.0;
+    // Table "Default PIDControl gains"
+    const double pkp[3] = {0.4, 0.4, 1.0}, pki[3] = {0.01, 0.01, 0.01}, pkd[3] = {0.9, 0.9, 2.0};
+    const double akp[3] = {2e-3, 2e-3, 1e-3}, aki[3] = {0.0, 0.0, 1e-4}, akd[3] = {5e-4, 5e-4, 2e-4};
+    for (int k = 0; k < 3; ++k) {
+        out->pos_kp[k] = pkp[k];
+        out->pos_ki[k] = pki[k];
+        out->pos_kd[k] = pkd[k];
+        out->att_kp[k] = akp[k];
+        out->att_ki[k] = aki[k];
+        out->att_kd[k] = akd[k];
+    }
+    out->pos_i_clamp = 2.0;
+    out->att_i_clamp = 0.5;
+    return MD_OK;
+}
+
+md_status md_derive(const md_params *p, md_derived *out) {
+    if (!p || !out) return MD_E_INVALID_ARG;
+    md::derive(*p, *out);
+    return MD_OK;
+}
+
+md_status md_create(const md_params *p, float dt, uint32_t aero_mask, int act_type, int ctrl_decim,
+                    md_ctx **out) {
+    if (out) *out = nullptr;
+    if (!p || !out) {
+        g_create_err = "md_create: null params or output pointer";
+        return MD_E_INVALID_ARG;
+    }
+    if (!(dt > 0.f) || ctrl_decim < 1 || (act_type != MD_ACT_RPM && act_type != MD_ACT_PID) ||
+        (aero_mask & ~15u) != 0) {
+        g_create_err = "md_create: invalid dt, ctrl_decim, act_type or aero_mask";
+        return MD_E_INVALID_ARG;
+    }
+    if ((aero_mask & MD_AERO_SURROGATE) && (aero_mask & 7u)) {
+        g_create_err = "md_create: MD_AERO_SURROGATE replaces GND|DRAG|DW and cannot be combined with them";
+        return MD_E_INVALID_ARG;
+    }
+    if (!(p->m > 0 && p->kf > 0 && p->km > 0 && p->Ixx > 0 && p->Iyy > 0 && p->Izz > 0 &&
+          p->L > 0 && p->g > 0 && p->thrust2weight > 0 && p->r_p > 0)) {
+        g_create_err = "md_create: non-positive mass, inertia, arm, rotor or gravity constant";
+        return MD_E_INVALID_ARG;
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) {
+        g_create_err = md::hip_msg("md_create: no usable HIP device", e);
+        return MD_E_HIP;
+    }
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        g_create_err = std::string("md_create: libmd is built for gfx950 only; device is ") + prop.gcnArchName;
+        return MD_E_UNSUPPORTED;
+    }
+    md_ctx *ctx = new (std::nothrow) md_ctx();
+    if (!ctx) {
+        g_create_err = "md_create: out of host memory";
+        return MD_E_OOM;
+    }
+    ctx->P = *p;
+    md::derive(*p, ctx->D);
+    ctx->dt = dt;
+    ctx->mask = aero_mask;
+    ctx->act = act_type;
+    ctx->decim = ctrl_decim;
+    ctx->device = dev;
+    ctx->n_cu = prop.multiProcessorCount;
+    ctx->kc = md::make_kconst(*p, ctx->D, dt, ctrl_decim);
+    *out = ctx;
+    return MD_OK;
+}
+
+void md_destroy(md_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipDeviceSynchronize();
+    md::destroy_extras(ctx);
+    md::free_bins(ctx);
+    delete ctx;
+}
+
+const char *md_last_error(const md_ctx *ctx) {
+    if (!ctx) return g_create_err.c_str();
+    return ctx->err.c_str();
+}
+
+md_status md_bind_layout(md_ctx *ctx, const int32_t *h_env_offsets, int n_envs, int n_drones) {
+    if (!ctx) return MD_E_INVALID_ARG;
+    if (!h_env_offsets || n_envs < 0 || n_drones < 0) {
+        ctx->err = "md_bind_layout: null offsets or negative sizes";
+        return MD_E_INVALID_ARG;
+    }
+    if (h_env_offsets[0] != 0 || h_env_offsets[n_envs] != n_drones) {
+        ctx->err = "md_bind_layout: offsets must start at 0 and end at n_drones";
+        return MD_E_LAYOUT;
+    }
+    int maxm = 0;
+    for (int e = 0; e < n_envs; ++e) {
+        const int m = h_env_offsets[e + 1] - h_env_offsets[e];
+        if (m < 0) {
+            ctx->err = "md_bind_layout: offsets must be non-decreasing";
+            return MD_E_LAYOUT;
+        }
+        maxm = std::max(maxm, m);
+    }
+    if (maxm > 1024) {
+        ctx->err = "md_bind_layout: environments of more than 1024 drones are not supported";
+        return MD_E_UNSUPPORTED;
+    }
+    (void)hipSetDevice(ctx->device);
+    md::invalidate_layout_users(ctx);
+    md::free_bins(ctx);
+    ctx->off.assign(h_env_offsets, h_env_offsets + n_envs + 1);
+    ctx->n_envs = n_envs;
+    ctx->n_drones = n_drones;
+    ctx->max_m = maxm;
+    ctx->has_layout = true;
+    ctx->cfg = md::default_cfg(ctx);
+    md::BinSet *bs = nullptr;
+    return md::build_bins(ctx, md::slots_for(ctx, ctx->cfg), &bs);
+}
+
+md_status md_step(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
+                  float *d_obs, int n_obs_slots, int n_steps, int64_t step0, void *stream) {
+    if (!ctx) return MD_E_INVALID_ARG;
+    if (!ctx->has_layout) {
+        ctx->err = "md_step: no layout bound (call md_bind_layout first)";
+        return MD_E_LAYOUT;
+    }
+    if (!s || n_steps < 0 || step0 < 0 || n_obs_slots < 0) {
+        ctx->err = "md_step: null state, or negative n_steps, step0 or n_obs_slots";
+        return MD_E_INVALID_ARG;
+    }
+    if (n_steps == 0 || ctx->n_drones == 0) return MD_OK;
+    if (!s->p || !s->q || !s->v || !s->w || !s->rpm || (ctx->act == MD_ACT_PID && !s->pid_int) ||
+        !d_action || (n_obs_slots > 0 && !d_obs)) {
+        ctx->err = "md_step: null state block, action or observation pointer";
+        return MD_E_INVALID_ARG;
+    }
+    if (ctx->mask & MD_AERO_SURROGATE) return md::surrogate_step(ctx, s, d_action, action_per_step, d_obs,
+                                                                 n_obs_slots, n_steps, step0,
+                                                                 (hipStream_t)stream);
+    return md::launch(ctx, s, d_action, action_per_step, d_obs, n_obs_slots, n_steps, step0,
+                      (hipStream_t)stream, ctx->cfg);
+}
+
+}  // extern "C"

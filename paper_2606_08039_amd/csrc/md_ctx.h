@@ -1,0 +1,69 @@
+// md_ctx.h -- the context object behind the opaque md_ctx* of the C ABI.
+#pragma once
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "md.h"
+#include "md_internal.h"
+
+namespace md {
+
+// Environment bins for one bin size (slots per workgroup).
+struct BinSet {
+    int slots = 0;
+    int n_bins = 0;
+    int2 *d_slot = nullptr;
+    int *d_mmax = nullptr;
+    std::vector<int> h_mmax;
+};
+
+struct SurrogateState;  // md_surrogate.cpp
+struct GraphCache;      // md_graph.cpp
+
+std::string hip_msg(const char *what, hipError_t e);
+void derive(const md_params &p, md_derived &d);
+
+}  // namespace md
+
+struct md_ctx {
+    md_params P{};
+    md_derived D{};
+    float dt = 0.f;
+    uint32_t mask = 0;
+    int act = 0;
+    int decim = 1;
+    int device = 0;
+    int n_cu = 0;
+    md::KConst kc{};
+    // layout
+    bool has_layout = false;
+    int n_envs = 0, n_drones = 0, max_m = 0;
+    std::vector<int32_t> off;
+    std::map<int, md::BinSet> binsets;  // keyed by slots per bin
+    md::LaunchCfg cfg{1, 4, 1};
+    bool tuned = false;
+    // optional subsystems
+    md::SurrogateState *sur = nullptr;
+    md::GraphCache *graphs = nullptr;
+    std::string err;
+};
+
+namespace md {
+
+md_status build_bins(md_ctx *ctx, int slots, BinSet **out);
+void free_bins(md_ctx *ctx);
+int slots_for(const md_ctx *ctx, const LaunchCfg &cfg);
+LaunchCfg default_cfg(const md_ctx *ctx);
+md_status launch(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
+                 float *d_obs, int n_obs_slots, int n_steps, int64_t step0, hipStream_t st,
+                 const LaunchCfg &cfg);
+
+// Subsystems with per-context resources.
+void destroy_extras(md_ctx *ctx);
+void invalidate_layout_users(md_ctx *ctx);
+md_status surrogate_step(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
+                         float *d_obs, int n_obs_slots, int n_steps, int64_t step0, hipStream_t st);
+
+}  // namespace md

@@ -1,0 +1,63 @@
+// md_internal.h -- shared between the host API (md_api.cpp) and the HIP
+// kernels of libmd.  Not installed; the public ABI is include/md.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace md {
+
+// Per-context float32 constants, precomputed on the host in double and passed
+// to the kernels by value.
+struct KConst {
+    float dt, m, m_inv, g, mg;
+    float kf, km, l_arm;                  // l_arm = L / sqrt(2)   (Eq. 2-3)
+    float Jx, Jy, Jz, Jx_inv, Jy_inv, Jz_inv;
+    float max_rpm, h_clip, K_gnd;         // K_gnd = C_gnd r_p^2 / 16   (Eq. 4)
+    float drag_s, c_xy, c_z;              // drag_s = 2 pi / 60         (Eq. 5)
+    float K1, C2, C3, dz_min;             // K1 = C1 r_p^2 / 16         (Eq. 6)
+    float pkp[3], pki[3], pkd[3], p_clamp;
+    float akp[3], aki[3], akd[3], a_clamp;
+    float dt_c, g_inv, l_inv, kappa_inv, fmax, kf_inv;
+    float hover_inv;                      // 1 / HOVER_RPM (surrogate inputs)
+    int decim;
+};
+
+// Six SoA device pointers of md_state.
+struct StatePtr {
+    float *p, *q, *v, *w, *pid_int, *rpm;
+};
+
+// One bin = one workgroup.  Per slot (drone slot inside the bin):
+//   x = global drone index or -1 for an idle slot,
+//   y = (first slot of the drone's environment inside the bin) << 16 | M_env.
+// Per bin: the largest environment it holds (uniform neighbour-loop bound).
+struct BinTables {
+    const int2 *slot;      // [n_bins * slots]
+    const int *bin_mmax;   // [n_bins]
+};
+
+struct StepArgs {
+    KConst c;
+    StatePtr s;
+    const float *action;
+    long long act_step_stride;  // 0 (held) or 4 * N
+    float *obs;
+    int n_obs_slots;
+    int n_steps;
+    long long step0;
+    int N;
+    BinTables bins;
+};
+
+// Launch configuration chosen per (shape, mask) by the autotuner.
+struct LaunchCfg {
+    int lpd;     // lanes per drone in the neighbour sweep: 1, 2 or 4
+    int unroll;  // neighbour-loop unroll: 1, 2, 4 or 8
+    int waves;   // waves per workgroup for environments of <= 64 drones: 1, 2 or 4
+};
+
+hipError_t launch_step(const StepArgs &a, uint32_t mask, int act, const LaunchCfg &cfg,
+                       int n_bins, int slots, hipStream_t stream);
+
+}  // namespace md

@@ -1,0 +1,197 @@
+"""ctypes binding of libmd (include/md.h), same names as the C ABI.
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels of libmd.so.  PyTorch supplies device memory and streams.  If the
+library is missing this module raises on first use -- there is no fallback.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmd.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "md.h")
+
+MD_OK = 0
+MD_E_INVALID_ARG, MD_E_HIP, MD_E_OOM, MD_E_UNSUPPORTED, MD_E_LAYOUT = -1, -2, -3, -4, -5
+MD_AERO_GND, MD_AERO_DRAG, MD_AERO_DW, MD_AERO_SURROGATE = 1, 2, 4, 8
+MD_ACT_RPM, MD_ACT_PID = 0, 1
+OBS_DIM = 20
+STATE_ROWS = (("p", 3), ("q", 4), ("v", 3), ("w", 3), ("pid_int", 6), ("rpm", 4))
+
+
+class MdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("libmd error %d: %s" % (status, msg))
+        self.status = status
+
+
+class md_params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "m", "L", "kf", "km", "Ixx", "Iyy", "Izz", "thrust2weight", "r_p", "g",
+        "C_gnd", "c_xy", "c_z", "C1", "C2", "C3", "dw_dz_min")] + [
+        ("pos_kp", ctypes.c_double * 3), ("pos_ki", ctypes.c_double * 3),
+        ("pos_kd", ctypes.c_double * 3), ("pos_i_clamp", ctypes.c_double),
+        ("att_kp", ctypes.c_double * 3), ("att_ki", ctypes.c_double * 3),
+        ("att_kd", ctypes.c_double * 3), ("att_i_clamp", ctypes.c_double)]
+
+
+class md_derived(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("hover_rpm", "max_rpm", "max_thrust", "h_clip")]
+
+
+class md_state(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("p", "q", "v", "w", "pid_int", "rpm")]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+
+
+def lib():
+    """The loaded libmd.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libmd.so is not built (%s); run `python -m paper_2606_08039_amd.build`"
+                           % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "md_version": (ctypes.c_char_p, []),
+        "md_default_params_cf2x": (ctypes.c_int32, [ctypes.POINTER(md_params)]),
+        "md_derive": (ctypes.c_int32, [ctypes.POINTER(md_params), ctypes.POINTER(md_derived)]),
+        "md_create": (ctypes.c_int32, [ctypes.POINTER(md_params), ctypes.c_float, ctypes.c_uint32,
+                                       ctypes.c_int, ctypes.c_int, ctypes.POINTER(_VP)]),
+        "md_destroy": (None, [_VP]),
+        "md_last_error": (ctypes.c_char_p, [_VP]),
+        "md_bind_layout": (ctypes.c_int32, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
+                                            ctypes.c_int]),
+        "md_step": (ctypes.c_int32, [_VP, ctypes.POINTER(md_state), _VP, ctypes.c_int, _VP,
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_int64, _VP]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    _bind_extra(L)
+    return L
+
+
+def _bind_extra(L):
+    """Signatures of the optional subsystems (autotuner, graphs, surrogate)."""
+    from . import md_extra_sigs
+    for name, (res, args) in md_extra_sigs.signatures().items():
+        if hasattr(L, name):
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+
+
+def header_symbols():
+    """Names of the functions include/md.h declares."""
+    txt = re.sub(r"/\*.*?\*/", " ", open(HEADER).read(), flags=re.S)
+    return sorted(set(re.findall(r"\b(md_[a-z0-9_]+)\s*\(", txt)))
+
+
+def check(status, ctx=None):
+    if status != MD_OK:
+        msg = lib().md_last_error(ctx).decode()
+        raise MdError(status, msg)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------------ C ABI
+
+def md_version():
+    return lib().md_version().decode()
+
+
+def md_default_params_cf2x():
+    p = md_params()
+    check(lib().md_default_params_cf2x(ctypes.byref(p)))
+    return p
+
+
+def md_derive(params):
+    d = md_derived()
+    check(lib().md_derive(ctypes.byref(params), ctypes.byref(d)))
+    return d
+
+
+def md_create(params, dt, aero_mask, act_type, ctrl_decim=1):
+    ctx = _VP()
+    st = lib().md_create(ctypes.byref(params), float(dt), int(aero_mask), int(act_type),
+                         int(ctrl_decim), ctypes.byref(ctx))
+    check(st, None)
+    return ctx
+
+
+def md_destroy(ctx):
+    lib().md_destroy(ctx)
+
+
+def md_last_error(ctx):
+    return lib().md_last_error(ctx).decode()
+
+
+def md_bind_layout(ctx, env_offsets):
+    off = np.ascontiguousarray(np.asarray(env_offsets, dtype=np.int32))
+    st = lib().md_bind_layout(ctx, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                              len(off) - 1, int(off[-1]))
+    check(st, ctx)
+
+
+def md_step(ctx, state, action, action_per_step, obs=None, n_obs_slots=0, n_steps=1, step0=0,
+            stream=None):
+    """state: DeviceState (or md_state); action/obs: CUDA float32 tensors."""
+    ms = state.as_md_state() if hasattr(state, "as_md_state") else state
+    st = lib().md_step(ctx, ctypes.byref(ms), _VP(action.data_ptr()), int(bool(action_per_step)),
+                       _VP(obs.data_ptr()) if obs is not None else None, int(n_obs_slots),
+                       int(n_steps), int(step0), _stream_ptr(stream))
+    check(st, ctx)
+
+
+# ------------------------------------------------------------------ device buffers
+
+class DeviceState:
+    """Float32 SoA state on the GPU, one torch tensor [rows][N] per field."""
+
+    def __init__(self, n, device="cuda"):
+        import torch
+        self.n = n
+        self.t = {k: torch.zeros((r, n), dtype=torch.float32, device=device) for k, r in STATE_ROWS}
+        self.t["q"][0] = 1.0
+
+    @classmethod
+    def from_numpy(cls, s, device="cuda"):
+        import torch
+        n = s["p"].shape[1]
+        d = cls(n, device)
+        for k, _ in STATE_ROWS:
+            if k in s:
+                d.t[k].copy_(torch.from_numpy(np.ascontiguousarray(s[k], dtype=np.float32)))
+        return d
+
+    def to_numpy(self):
+        return {k: v.cpu().numpy() for k, v in self.t.items()}
+
+    def clone(self):
+        d = DeviceState.__new__(DeviceState)
+        d.n = self.n
+        d.t = {k: v.clone() for k, v in self.t.items()}
+        return d
+
+    def as_md_state(self):
+        return md_state(*[self.t[k].data_ptr() for k in ("p", "q", "v", "w", "pid_int", "rpm")])

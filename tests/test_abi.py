@@ -1,0 +1,55 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+include/md.h declares, and its host-only entry points agree with the oracle's
+constants.  No device work is launched here."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_2606_08039_amd import md
+
+
+def test_library_exports_every_declared_symbol():
+    L = md.lib()
+    names = md.header_symbols()
+    assert "md_step" in names and "md_create" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_version_string():
+    assert "gfx950" in md.md_version()
+
+
+def test_default_params_match_oracle_constants():
+    p = md.md_default_params_cf2x()
+    P = orc.cf2x()
+    for name, _ in md.md_params._fields_:
+        a, b = getattr(p, name), getattr(P, name)
+        if isinstance(a, float):
+            assert a == b, name
+        else:
+            assert list(a) == list(b), name
+
+
+def test_derived_constants_match_oracle():
+    p = md.md_default_params_cf2x()
+    d = md.md_derive(p)
+    D = orc.derive(orc.cf2x())
+    for k in ("hover_rpm", "max_rpm", "max_thrust", "h_clip"):
+        assert getattr(d, k) == pytest.approx(getattr(D, k), rel=1e-15), k
+
+
+def test_create_rejects_bad_arguments_before_touching_a_device():
+    p = md.md_default_params_cf2x()
+    L = md.lib()
+    out = ctypes.c_void_p()
+    assert L.md_create(None, 1 / 240, 0, 0, 1, ctypes.byref(out)) == md.MD_E_INVALID_ARG
+    assert L.md_create(ctypes.byref(p), 0.0, 0, 0, 1, ctypes.byref(out)) == md.MD_E_INVALID_ARG
+    assert L.md_create(ctypes.byref(p), 1 / 240, 0, 7, 1, ctypes.byref(out)) == md.MD_E_INVALID_ARG
+    assert L.md_create(ctypes.byref(p), 1 / 240, 0, 0, 0, ctypes.byref(out)) == md.MD_E_INVALID_ARG
+    assert L.md_create(ctypes.byref(p), 1 / 240, 8 | 4, 0, 1, ctypes.byref(out)) == md.MD_E_INVALID_ARG
+    assert out.value is None
+    assert "SURROGATE" in md.md_last_error(None)
+    assert L.md_step(None, None, None, 0, None, 0, 1, 0, None) == md.MD_E_INVALID_ARG
