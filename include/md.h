@@ -135,6 +135,102 @@ md_status md_bind_layout(md_ctx *ctx, const int32_t *h_env_offsets, int n_envs, 
 md_status md_step(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
                   float *d_obs, int n_obs_slots, int n_steps, int64_t step0, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned aerodynamic residual (surrogate for Eq. 4-6).
+ *
+ * Network: 64 inputs (59 features, zero padded) -> 128 -> 128 -> 128 -> 6,
+ * SiLU on the hidden layers; bfloat16 operands with fp32 accumulation (the
+ * matrix products run on MFMA).  Inputs are standardised in fp32,
+ * x' = (x - x_mean) * x_inv_std, then rounded to bfloat16; the 6 outputs are
+ * standardised targets, y = y' * y_std + y_mean (body-frame force, N, and
+ * torque, N m).  Parameters are one flat fp32 vector of MD_MLP_NPARAMS:
+ * W1[128][64], b1[128], W2[128][128], b2[128], W3[128][128], b3[128],
+ * W4[6][128], b4[6] (W row-major [out][in]).  The normalisation vector has
+ * MD_MLP_NORM floats: x_mean[64], x_inv_std[64], y_mean[6], y_std[6].
+ * ---------------------------------------------------------------------- */
+#define MD_MLP_IN 64
+#define MD_MLP_HIDDEN 128
+#define MD_MLP_OUT 6
+#define MD_MLP_NPARAMS 42118
+#define MD_MLP_NORM 140
+
+typedef struct md_mlp md_mlp;
+
+/* A trainable network on the current device with buffers for batches of up
+ * to max_batch samples.  Parameters start at zero; set them with
+ * md_mlp_set_params. */
+md_status md_mlp_create(int max_batch, md_mlp **out);
+void md_mlp_destroy(md_mlp *m);
+const char *md_mlp_last_error(const md_mlp *m);
+
+/* Host <-> device copies of the flat fp32 parameters (synchronous).
+ * set_params also resets the Adam moments and step count. */
+md_status md_mlp_set_params(md_mlp *m, const float *h_params);
+md_status md_mlp_get_params(const md_mlp *m, float *h_params);
+/* Input / output standardisation (MD_MLP_NORM floats, synchronous). */
+md_status md_mlp_set_norm(md_mlp *m, const float *h_norm);
+md_status md_mlp_get_norm(const md_mlp *m, float *h_norm);
+
+/* Forward pass of B <= max_batch samples: d_X [B][64] raw features (fp32,
+ * device).  Keeps the activations for md_mlp_backward.  d_Y (nullable):
+ * [B][6] de-standardised outputs (fp32, device).  Asynchronous on stream. */
+md_status md_mlp_forward(md_mlp *m, const float *d_X, int B, float *d_Y, void *stream);
+
+/* Gradient of the mean squared error between the standardised outputs of
+ * the last forward pass and the standardised targets d_T [B][6] (raw fp32,
+ * device) with respect to every parameter, written to the network's gradient
+ * buffer.  Deterministic (fixed reduction order).  Asynchronous. */
+md_status md_mlp_backward(md_mlp *m, const float *d_T, int B, void *stream);
+/* The gradient vector (synchronous copy) and the last backward's loss. */
+md_status md_mlp_get_grads(const md_mlp *m, float *h_grads);
+md_status md_mlp_loss(const md_mlp *m, double *out);
+
+/* One Adam step (Kingma and Ba) on the fp32 parameters with the current
+ * gradients: lr, beta1, beta2 in [0, 1), eps > 0.  Asynchronous. */
+md_status md_mlp_adam(md_mlp *m, float lr, float beta1, float beta2, float eps, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Surrogate inside the step, training data, and its judge.
+ * ---------------------------------------------------------------------- */
+
+/* Load trained parameters (h_params[MD_MLP_NPARAMS], h_norm[MD_MLP_NORM],
+ * host fp32, layouts as for md_mlp_set_params / md_mlp_set_norm) into a
+ * context created with MD_AERO_SURROGATE.  The library keeps bfloat16
+ * copies on the device (about 85 KB).  Fallback: a drone with a same-env
+ * neighbour among its 8 nearest that sits above it by less than dz_ood
+ * metres (0 < dz < dz_ood, where Eq. 6 is singular) takes the plain ground
+ * effect + drag + downwash for that step.  Judge: every judge_stride-th
+ * drone-step (a power of two; 0 = off) also evaluates the plain terms and
+ * accumulates the surrogate's force error (md_judge_stats).  Synchronous. */
+md_status md_load_surrogate(md_ctx *ctx, const float *h_params, const float *h_norm, float dz_ood,
+                            int judge_stride);
+/* Same, reading the parameters and normalisation of a trained md_mlp. */
+md_status md_load_surrogate_mlp(md_ctx *ctx, const md_mlp *m, float dz_ood, int judge_stride);
+
+/* Training samples at the current state (bound layout, current device):
+ * d_X [N][64] fp32 raw surrogate inputs (v_body[3], world up axis in the
+ * body frame[3], rpm/HOVER_RPM[4], for the 8 nearest same-environment
+ * neighbours by 3-D distance (ascending, ties to the lower index, zeros when
+ * missing) p_j - p_i[3] and v_j - v_i[3], z[1], zeros[5]);
+ * d_Y [N][6] fp32: the aerodynamic force of the effects in aero_mask (a
+ * subset of GND|DRAG|DW) in the body frame, then the torque (identically 0
+ * for these centre-of-mass forces); d_nbr (nullable) [N][8] int32 neighbour
+ * drone indices or -1.  Rotor speeds are the state's rpm.  Asynchronous. */
+md_status md_datagen(md_ctx *ctx, const md_state *s, uint32_t aero_mask, float *d_X, float *d_Y,
+                     int32_t *d_nbr, void *stream);
+
+/* Judge statistics accumulated since the last reset (synchronous):
+ * n_judged judged drone-steps; force_err2 = sum |F_surrogate - F_plain|^2;
+ * force_ref2 = sum |F_plain|^2; torque_err2 = sum |tau_surrogate|^2 (plain
+ * torque is 0); n_fallback drone-steps that took the plain terms;
+ * n_drone_steps all drone-steps stepped; force_rel_err = sqrt(err2 / ref2). */
+typedef struct md_judge {
+    double n_judged, force_err2, force_ref2, torque_err2, n_fallback, n_drone_steps;
+    double force_rel_err;
+} md_judge;
+md_status md_judge_stats(md_ctx *ctx, md_judge *out);
+md_status md_judge_reset(md_ctx *ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,6 +22,9 @@ ACT_RPM, ACT_PID = 0, 1
 N_FEAT, K_NN = 64, 8
 
 
+_D_T = ctypes.POINTER(ctypes.c_double)
+
+
 class Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in (
         "m", "L", "kf", "km", "Ixx", "Iyy", "Izz", "thrust2weight", "r_p", "g",
@@ -39,6 +42,10 @@ class Params(ctypes.Structure):
 
 class Derived(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("hover_rpm", "max_rpm", "max_thrust", "h_clip")]
+
+
+class Net(ctypes.Structure):
+    _fields_ = [("W", _D_T * 4), ("b", _D_T * 4), ("norm", _D_T), ("dz_ood", ctypes.c_double)]
 
 
 class _CState(ctypes.Structure):
@@ -90,6 +97,11 @@ def _load():
                                      ctypes.POINTER(_D), _D]
     lib.orc_adam.argtypes = [ctypes.c_int, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double,
                              ctypes.c_double, ctypes.c_double, ctypes.c_int64]
+    lib.orc_step_surrogate.argtypes = [P, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       _I32, ctypes.c_int, ctypes.POINTER(_CState), _D, ctypes.c_int,
+                                       _D, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                       ctypes.POINTER(Net), _D, _I32, ctypes.c_int]
+    lib.orc_step_surrogate.restype = ctypes.c_int
     lib.orc_bf16_round.argtypes = [ctypes.c_double]
     lib.orc_bf16_round.restype = ctypes.c_double
     _lib = lib
@@ -330,3 +342,48 @@ def adam(param, grad, m1, m2, lr, beta1, beta2, eps, t):
 def bf16_round(x):
     f = _load().orc_bf16_round
     return np.vectorize(f, otypes=[np.float64])(np.asarray(x, dtype=np.float64))
+
+
+def make_net(flat_params, norm, dz_ood):
+    """The surrogate as the oracle evaluates it: weight matrices rounded to
+    bfloat16 (as the in-step network stores them), biases and normalisation
+    as given (float32 values).  Returns (Net, keepalive)."""
+    flat = np.asarray(flat_params, dtype=np.float32).astype(np.float64)
+    shapes = ((128, 64), (128,), (128, 128), (128,), (128, 128), (128,), (6, 128), (6,))
+    parts, o = [], 0
+    for sh in shapes:
+        k = int(np.prod(sh))
+        parts.append(flat[o:o + k].reshape(sh))
+        o += k
+    Ws = [np.ascontiguousarray(bf16_round(parts[2 * l])) for l in range(4)]
+    bs = [np.ascontiguousarray(parts[2 * l + 1]) for l in range(4)]
+    nrm = np.ascontiguousarray(np.asarray(norm, dtype=np.float32).astype(np.float64))
+    net = Net()
+    for l in range(4):
+        net.W[l] = _dp(Ws[l])
+        net.b[l] = _dp(bs[l])
+    net.norm = _dp(nrm)
+    net.dz_ood = float(np.float32(dz_ood))
+    return net, (Ws, bs, nrm)
+
+
+def step_surrogate(P, dt, act_type, ctrl_decim, env_offsets, state, action, action_per_step,
+                   n_steps, net, step0=0, n_obs_slots=0, n_threads=0):
+    """Step with the learned residual (see orc_step_surrogate); returns
+    (obs, aero_body[N][6] of the last step, fallback[N])."""
+    off = np.ascontiguousarray(np.asarray(env_offsets, dtype=np.int32))
+    n = int(off[-1])
+    act = np.ascontiguousarray(np.asarray(action, dtype=np.float64))
+    obs = np.zeros((n_obs_slots, 20, n)) if n_obs_slots > 0 else None
+    aero = np.zeros((n, 6))
+    fb = np.zeros(n, dtype=np.int32)
+    cs = _cstate(state)
+    rc = _load().orc_step_surrogate(ctypes.byref(P), float(dt), int(act_type), int(ctrl_decim),
+                                    len(off) - 1, _ip(off), n, ctypes.byref(cs), _dp(act),
+                                    int(bool(action_per_step)),
+                                    _dp(obs) if obs is not None else None, int(n_obs_slots),
+                                    int(n_steps), int(step0), ctypes.byref(net), _dp(aero),
+                                    _ip(fb), int(n_threads))
+    if rc != 0:
+        raise ValueError("orc_step_surrogate failed (%d)" % rc)
+    return obs, aero, fb

@@ -474,43 +474,56 @@ int orc_knn(int n_envs, const int32_t *env_offsets, int n_drones, const double *
     return rc;
 }
 
-/* Surrogate inputs of one drone (raw, before any scaling), n_feat >= 59:
+/* Surrogate inputs of drone i from pre-step positions / velocities and this
+ * step's rotor speeds n (layout as in orc_features). */
+static void features_one(const orc_derived *D, int N, int i, const double *p_pre,
+                         const double *v_pre, const double q[4], const double n[4],
+                         const int32_t *nbr, int k, double *x)
+{
+    double R[9];
+    orc_quat_to_rot(q, R);
+    for (int f = 0; f < 64; ++f) x[f] = 0.0;
+    const double v[3] = {v_pre[0 * N + i], v_pre[1 * N + i], v_pre[2 * N + i]};
+    for (int a = 0; a < 3; ++a) x[a] = R[0 * 3 + a] * v[0] + R[1 * 3 + a] * v[1] + R[2 * 3 + a] * v[2];
+    for (int a = 0; a < 3; ++a) x[3 + a] = R[2 * 3 + a];
+    for (int c = 0; c < 4; ++c) x[6 + c] = n[c] / D->hover_rpm;
+    for (int t = 0; t < k; ++t) {
+        const int j = nbr[t];
+        if (j < 0) continue;
+        for (int c = 0; c < 3; ++c) {
+            x[10 + 6 * t + c] = p_pre[c * N + j] - p_pre[c * N + i];
+            x[10 + 6 * t + 3 + c] = v_pre[c * N + j] - v_pre[c * N + i];
+        }
+    }
+    x[10 + 6 * k] = p_pre[2 * N + i];
+}
+
+/* Surrogate inputs of one drone (raw, before any scaling), n_feat = 64:
  *   [0..2]  v_body = R^T v
  *   [3..5]  world up axis in the body frame, R^T z_hat
  *   [6..9]  n_i / HOVER_RPM
  *   [10..57] for each of the k = 8 nearest neighbours: p_j - p_i, v_j - v_i
  *            (world frame), zeros for a missing neighbour
  *   [58]    p_z
- *   [59..]  zero padding. */
+ *   [59..]  zero padding.
+ * Rotor speeds are the state's rpm. */
 int orc_features(const orc_params *P, int n_envs, const int32_t *env_offsets, int n_drones,
                  const orc_state *s, const int32_t *nbr, int k, int n_feat, double *X)
 {
     (void)n_envs;
     (void)env_offsets;
-    if (n_feat < 10 + 6 * k + 1) return -1;
+    if (n_feat != 64 || 10 + 6 * k + 1 > n_feat) return -1;
     orc_derived D;
     orc_derive(P, &D);
     const int N = n_drones;
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < N; ++i) {
-        double *x = X + (size_t)i * n_feat;
-        for (int f = 0; f < n_feat; ++f) x[f] = 0.0;
-        double q[4], R[9], v[3];
-        for (int c = 0; c < 4; ++c) q[c] = s->q[c * N + i];
-        for (int c = 0; c < 3; ++c) v[c] = s->v[c * N + i];
-        orc_quat_to_rot(q, R);
-        for (int a = 0; a < 3; ++a) x[a] = R[0 * 3 + a] * v[0] + R[1 * 3 + a] * v[1] + R[2 * 3 + a] * v[2];
-        for (int a = 0; a < 3; ++a) x[3 + a] = R[2 * 3 + a];
-        for (int c = 0; c < 4; ++c) x[6 + c] = s->rpm[c * N + i] / D.hover_rpm;
-        for (int t = 0; t < k; ++t) {
-            const int j = nbr[(size_t)i * k + t];
-            if (j < 0) continue;
-            for (int c = 0; c < 3; ++c) {
-                x[10 + 6 * t + c] = s->p[c * N + j] - s->p[c * N + i];
-                x[10 + 6 * t + 3 + c] = s->v[c * N + j] - s->v[c * N + i];
-            }
+        double q[4], n[4];
+        for (int c = 0; c < 4; ++c) {
+            q[c] = s->q[c * N + i];
+            n[c] = s->rpm[c * N + i];
         }
-        x[10 + 6 * k] = s->p[2 * N + i];
+        features_one(&D, N, i, s->p, s->v, q, n, nbr + (size_t)i * k, k, X + (size_t)i * n_feat);
     }
     return 0;
 }
@@ -699,4 +712,146 @@ void orc_adam(int n, double *param, const double *grad, double *m1, double *m2, 
         const double mh = m1[i] / bc1, vh = m2[i] / bc2;
         param[i] -= lr * mh / (sqrt(vh) + eps);
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step with the learned residual in place of Eq. (4)-(6).                   */
+/* ------------------------------------------------------------------------ */
+
+/* Per drone and step: rotor speeds and motor model as in orc_step; the 8
+ * nearest neighbours (binary32 decisions, see orc_knn) and the raw inputs;
+ * fallback when a neighbour is above by less than dz_ood (the difference
+ * formed in binary32, as the GPU forms it) -> the plain Eq. (4)-(6) force;
+ * otherwise inputs standardised x' = (x - mean) * inv_std, rounded to
+ * bfloat16, the network (W already rounded to bfloat16 by the caller; hidden
+ * outputs rounded to bfloat16, sums in double), y = y' * y_std + y_mean,
+ * body-frame force y[0..2] rotated to the world frame and body torque
+ * y[3..5] added.  aero_out [N][6] (nullable) receives the body-frame
+ * residual used in the last step, fallback_out [N] whether it was plain. */
+int orc_step_surrogate(const orc_params *P, double dt, int act_type, int ctrl_decim, int n_envs,
+                       const int32_t *env_offsets, int n_drones, orc_state *s,
+                       const double *action, int action_per_step, double *obs, int n_obs_slots,
+                       int n_steps, int64_t step0, const orc_net *net, double *aero_out,
+                       int32_t *fallback_out, int n_threads)
+{
+    if (n_drones < 0 || n_envs < 0 || n_steps < 0 || ctrl_decim < 1) return -1;
+    if (env_offsets[0] != 0 || env_offsets[n_envs] != n_drones) return -1;
+    orc_derived D;
+    orc_derive(P, &D);
+    const int N = n_drones;
+    const int K = 8;
+    const int32_t dims[5] = {64, 128, 128, 128, 6};
+    double *p_pre = (double *)malloc(sizeof(double) * 3 * (size_t)(N > 0 ? N : 1));
+    double *v_pre = (double *)malloc(sizeof(double) * 3 * (size_t)(N > 0 ? N : 1));
+    int32_t *nbr = (int32_t *)malloc(sizeof(int32_t) * K * (size_t)(N > 0 ? N : 1));
+    if (!p_pre || !v_pre || !nbr) {
+        free(p_pre);
+        free(v_pre);
+        free(nbr);
+        return -2;
+    }
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    int rc = 0;
+    for (int k = 0; k < n_steps; ++k) {
+        memcpy(p_pre, s->p, sizeof(double) * 3 * (size_t)N);
+        memcpy(v_pre, s->v, sizeof(double) * 3 * (size_t)N);
+        if (orc_knn(n_envs, env_offsets, N, p_pre, K, nbr) != 0) {
+            rc = -2;
+            break;
+        }
+        const double *act = action + (action_per_step ? (size_t)k * 4 * N : 0);
+        const int do_pid = (act_type == ORC_ACT_PID) && (((step0 + k) % ctrl_decim) == 0);
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int e = 0; e < n_envs; ++e) {
+            double acts[2 * (128 + 128 + 128 + 6)];
+            for (int i = env_offsets[e]; i < env_offsets[e + 1]; ++i) {
+                double p[3], q[4], v[3], w[3], n[4];
+                for (int c = 0; c < 3; ++c) {
+                    p[c] = s->p[c * N + i];
+                    v[c] = s->v[c * N + i];
+                    w[c] = s->w[c * N + i];
+                }
+                for (int c = 0; c < 4; ++c) q[c] = s->q[c * N + i];
+                if (act_type == ORC_ACT_RPM) {
+                    for (int c = 0; c < 4; ++c) n[c] = clampd(act[c * N + i], 0.0, D.max_rpm);
+                } else if (do_pid) {
+                    double tgt[4], integ[6];
+                    for (int c = 0; c < 4; ++c) tgt[c] = act[c * N + i];
+                    for (int c = 0; c < 6; ++c) integ[c] = s->pid_int[c * N + i];
+                    orc_pid(P, &D, dt * ctrl_decim, p, q, v, w, tgt, integ, n);
+                    for (int c = 0; c < 6; ++c) s->pid_int[c * N + i] = integ[c];
+                } else {
+                    for (int c = 0; c < 4; ++c) n[c] = s->rpm[c * N + i];
+                }
+                for (int c = 0; c < 4; ++c) s->rpm[c * N + i] = n[c];
+
+                double F[4], T, tau[3], R[9];
+                orc_motor(P, n, F, &T, tau);
+                orc_quat_to_rot(q, R);
+                double Fw[3] = {R[2] * T, R[5] * T, R[8] * T - P->m * P->g};
+
+                const int32_t *nb = nbr + (size_t)i * K;
+                int ood = 0;
+                for (int t = 0; t < K; ++t) {
+                    if (nb[t] < 0) continue;
+                    const float dz = (float)p_pre[2 * N + nb[t]] - (float)p_pre[2 * N + i];
+                    if (dz > 0.0f && dz < (float)net->dz_ood) ood = 1;
+                }
+                double yb[6];
+                if (ood) {
+                    double Fa[3] = {0.0, 0.0, 0.0}, Fd[3];
+                    Fa[2] += orc_ground_effect(P, &D, n, p[2], q);
+                    orc_drag(P, n, q, v, Fd);
+                    for (int c = 0; c < 3; ++c) Fa[c] += Fd[c];
+                    const double pi_[3] = {p_pre[0 * N + i], p_pre[1 * N + i], p_pre[2 * N + i]};
+                    for (int j = env_offsets[e]; j < env_offsets[e + 1]; ++j) {
+                        if (j == i) continue;
+                        const double pj[3] = {p_pre[0 * N + j], p_pre[1 * N + j], p_pre[2 * N + j]};
+                        Fa[2] += orc_downwash_pair(P, pi_, pj);
+                    }
+                    for (int c = 0; c < 3; ++c) Fw[c] += Fa[c];
+                    for (int a = 0; a < 3; ++a)
+                        yb[a] = R[0 * 3 + a] * Fa[0] + R[1 * 3 + a] * Fa[1] + R[2 * 3 + a] * Fa[2];
+                    yb[3] = yb[4] = yb[5] = 0.0;
+                } else {
+                    double x[64], y[6];
+                    features_one(&D, N, i, p_pre, v_pre, q, n, nb, K, x);
+                    for (int f = 0; f < 64; ++f) x[f] = (x[f] - net->norm[f]) * net->norm[64 + f];
+                    orc_mlp_forward(4, dims, net->W, net->b, 1, x, y, acts, 1);
+                    for (int o = 0; o < 6; ++o) yb[o] = y[o] * net->norm[134 + o] + net->norm[128 + o];
+                    for (int a = 0; a < 3; ++a)
+                        Fw[a] += R[a * 3 + 0] * yb[0] + R[a * 3 + 1] * yb[1] + R[a * 3 + 2] * yb[2];
+                    for (int c = 0; c < 3; ++c) tau[c] += yb[3 + c];
+                }
+                if (aero_out)
+                    for (int o = 0; o < 6; ++o) aero_out[(size_t)i * 6 + o] = yb[o];
+                if (fallback_out) fallback_out[i] = ood;
+
+                orc_integrate(P, dt, Fw, tau, p, q, v, w);
+                for (int c = 0; c < 3; ++c) {
+                    s->p[c * N + i] = p[c];
+                    s->v[c * N + i] = v[c];
+                    s->w[c * N + i] = w[c];
+                }
+                for (int c = 0; c < 4; ++c) s->q[c * N + i] = q[c];
+                if (obs && n_obs_slots > 0) {
+                    double *o = obs + (size_t)(k % n_obs_slots) * 20 * N;
+                    double rpy[3];
+                    orc_euler_zyx(q, rpy);
+                    const double row[20] = {p[0], p[1], p[2], q[0], q[1], q[2], q[3],
+                                            rpy[0], rpy[1], rpy[2], v[0], v[1], v[2],
+                                            w[0], w[1], w[2], n[0], n[1], n[2], n[3]};
+                    for (int c = 0; c < 20; ++c) o[(size_t)c * N + i] = row[c];
+                }
+            }
+        }
+    }
+    free(p_pre);
+    free(v_pre);
+    free(nbr);
+    return rc;
 }

@@ -97,6 +97,20 @@ void orc_adam(int n, double *param, const double *grad, double *m1, double *m2, 
               double beta1, double beta2, double eps, int64_t t);
 double orc_bf16_round(double x);
 
+/* The trained surrogate as the oracle evaluates it (see orc_step_surrogate). */
+typedef struct orc_net {
+    const double *W[4]; /* [128][64], [128][128], [128][128], [6][128], bfloat16 values */
+    const double *b[4]; /* [128], [128], [128], [6] */
+    const double *norm; /* x_mean[64], x_inv_std[64], y_mean[6], y_std[6] */
+    double dz_ood;
+} orc_net;
+
+int orc_step_surrogate(const orc_params *P, double dt, int act_type, int ctrl_decim, int n_envs,
+                       const int32_t *env_offsets, int n_drones, orc_state *s,
+                       const double *action, int action_per_step, double *obs, int n_obs_slots,
+                       int n_steps, int64_t step0, const orc_net *net, double *aero_out,
+                       int32_t *fallback_out, int n_threads);
+
 #ifdef __cplusplus
 }
 #endif

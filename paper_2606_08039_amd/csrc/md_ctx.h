@@ -65,5 +65,11 @@ void destroy_extras(md_ctx *ctx);
 void invalidate_layout_users(md_ctx *ctx);
 md_status surrogate_step(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
                          float *d_obs, int n_obs_slots, int n_steps, int64_t step0, hipStream_t st);
+void free_surrogate(md_ctx *ctx);
+md_status load_surrogate(md_ctx *ctx, const float *params, const float *norm, float dz_ood, int judge_stride);
+md_status datagen(md_ctx *ctx, const md_state *s, uint32_t mask, float *d_X, float *d_Y, int32_t *d_nbr,
+                  hipStream_t st);
+md_status judge_stats(md_ctx *ctx, md_judge *out);
+md_status judge_reset(md_ctx *ctx);
 
 }  // namespace md

@@ -1,16 +1,10 @@
-// md_extras.cpp -- per-context subsystems that are optional for the plain step.
+// md_extras.cpp -- teardown hooks for the per-context subsystems.
 #include "md_ctx.h"
 
 namespace md {
 
-void destroy_extras(md_ctx *ctx) { (void)ctx; }
+void destroy_extras(md_ctx *ctx) { free_surrogate(ctx); }
 
 void invalidate_layout_users(md_ctx *ctx) { (void)ctx; }
-
-md_status surrogate_step(md_ctx *ctx, const md_state *, const float *, int, float *, int, int, int64_t,
-                         hipStream_t) {
-    ctx->err = "md_step: surrogate weights not loaded";
-    return MD_E_UNSUPPORTED;
-}
 
 }  // namespace md

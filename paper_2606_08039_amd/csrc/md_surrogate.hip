@@ -1,0 +1,738 @@
+// md_surrogate.hip -- the learned aerodynamic residual inside the step.
+//
+// Three pieces share one feature builder:
+//   datagen_kernel   features + the plain residual (Eq. 4-6 in the body frame)
+//                    at the current state: the surrogate's training samples;
+//   sur_step_kernel  the persistent step with Eq. 4-6 replaced by the network:
+//                    per drone, 8 nearest same-environment neighbours, 59 features,
+//                    fp32 standardisation, bfloat16 rounding, then the 64-128-128-128-6
+//                    network on MFMA (v_mfma_f32_16x16x32_bf16) for the wave's 64
+//                    drones at once; a drone whose neighbour sits just above it
+//                    (0 < dz < dz_ood, the downwash singularity) takes the plain terms
+//                    instead (fallback); every judge_stride-th drone-step also
+//                    evaluates the plain terms and accumulates the force error (judge).
+//
+// MFMA data flow per wave (64 drones = 4 column tiles of 16 drones):
+//   Z^T[out][drone] = W[out][in] X^T[in][drone].  A operand = weight rows read
+//   from global memory (L2-resident, 84 KB bf16 for all layers), B operand =
+//   activations.  The 16x16 C tile leaves lane l holding rows 4*(l/16)+t of
+//   drone l%16, which is exactly half of the next layer's B fragment for a
+//   32-wide K chunk; the host permutes the K columns of layers 2-4 to match,
+//   so activations never leave registers between layers.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "md_ctx.h"
+#include "md_mlp.h"
+#include "md_physics.h"
+
+namespace md {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int KNN = 8;
+constexpr int FEAT_STRIDE = MLP_IN + 8;  // bf16 per staged feature row (144 B, 16 B aligned)
+constexpr int OUT_STRIDE = 8;
+constexpr int W4_ROWS = 16;
+// offsets (in bf16 elements) of the permuted device weights
+constexpr int WOFF1 = 0, WOFF2 = WOFF1 + MLP_H * MLP_IN, WOFF3 = WOFF2 + MLP_H * MLP_H,
+              WOFF4 = WOFF3 + MLP_H * MLP_H, WTOTAL = WOFF4 + W4_ROWS * MLP_H;
+constexpr int BOFF1 = 0, BOFF2 = 128, BOFF3 = 256, BOFF4 = 384, BTOTAL = 400;
+
+enum { J_ERR2 = 0, J_REF2, J_TERR2, J_N, J_FALLBACK, J_STEPS, J_COUNT };
+
+struct SurrogateState {
+    bf16 *W = nullptr;      // permuted bf16 weights [WTOTAL]
+    float *b = nullptr;     // biases [BTOTAL]
+    float *norm = nullptr;  // x_mean[64], x_inv_std[64], y_mean[6], y_std[6]
+    double *judge = nullptr;
+    float dz_ood = 1e-3f;
+    int judge_stride = 64;
+    bool loaded = false;
+};
+
+struct SurArgs {
+    StepArgs s;
+    const bf16 *W;
+    const float *b;
+    const float *norm;
+    double *judge;
+    float dz_ood;
+    int judge_mask;  // judge_stride - 1 (power of two), or -1 for no judging
+};
+
+struct GenArgs {
+    KConst c;
+    StatePtr s;
+    int N;
+    BinTables bins;
+    uint32_t mask;
+    float *X;
+    float *Y;
+    int *nbr;
+};
+
+namespace {
+
+using namespace phys;
+
+__device__ __forceinline__ void load_drone(const StatePtr &s, int N, int di, Drone &d) {
+    d.px = s.p[di];
+    d.py = s.p[N + di];
+    d.pz = s.p[2 * N + di];
+    d.qw = s.q[di];
+    d.qx = s.q[N + di];
+    d.qy = s.q[2 * N + di];
+    d.qz = s.q[3 * N + di];
+    d.vx = s.v[di];
+    d.vy = s.v[N + di];
+    d.vz = s.v[2 * N + di];
+    d.wx = s.w[di];
+    d.wy = s.w[N + di];
+    d.wz = s.w[2 * N + di];
+}
+
+// k nearest neighbours by 3-D distance among the environment's slots
+// [lo, lo + m) other than self, ascending, ties to the lower slot (= lower
+// drone index).  The squared distance is formed as (dx*dx + dy*dy) + dz*dz
+// with every operation rounded (no fused multiply-add), the order the oracle
+// uses, so both sides take the same integer decisions.
+__device__ __forceinline__ void knn8(const float4 *pos, int lo, int m, int mmax, int self, float px,
+                                     float py, float pz, int bj[KNN]) {
+#pragma clang fp contract(off)
+    float bd[KNN];
+#pragma unroll
+    for (int t = 0; t < KNN; ++t) {
+        bd[t] = __builtin_inff();
+        bj[t] = -1;
+    }
+    for (int jj = 0; jj < mmax; ++jj) {
+        const int j = lo + jj;
+        const float4 pj = pos[j];
+        const float dx = pj.x - px, dy = pj.y - py, dz = pj.z - pz;
+        const float a = dx * dx, b = dy * dy, cz = dz * dz;
+        float d2 = (a + b) + cz;
+        d2 = (jj < m && j != self) ? d2 : __builtin_inff();
+        bool c[KNN];
+#pragma unroll
+        for (int t = 0; t < KNN; ++t) c[t] = d2 < bd[t];
+#pragma unroll
+        for (int t = KNN - 1; t >= 1; --t) {
+            bd[t] = c[t] ? (c[t - 1] ? bd[t - 1] : d2) : bd[t];
+            bj[t] = c[t] ? (c[t - 1] ? bj[t - 1] : j) : bj[t];
+        }
+        bd[0] = c[0] ? d2 : bd[0];
+        bj[0] = c[0] ? j : bj[0];
+    }
+}
+
+// Raw surrogate inputs (see md.h): v_body, world up in the body frame, n/HOVER,
+// 8 x (dp, dv) of the nearest neighbours (world frame, zero if missing), z, 0-pad.
+// Returns whether a neighbour sits above within (0, dz_ood).
+__device__ __forceinline__ bool features(const KConst &c, const Drone &d, const Rot &R, const float n[4],
+                                         const float4 *pos, const float4 *vel, const int bj[KNN],
+                                         float dz_ood, float f[MLP_IN]) {
+    f[0] = R.r00 * d.vx + R.r10 * d.vy + R.r20 * d.vz;
+    f[1] = R.r01 * d.vx + R.r11 * d.vy + R.r21 * d.vz;
+    f[2] = R.r02 * d.vx + R.r12 * d.vy + R.r22 * d.vz;
+    f[3] = R.r20;
+    f[4] = R.r21;
+    f[5] = R.r22;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) f[6 + k] = n[k] * c.hover_inv;
+    bool ood = false;
+#pragma unroll
+    for (int t = 0; t < KNN; ++t) {
+        const int j = bj[t];
+        float4 pj = make_float4(0.f, 0.f, 0.f, 0.f), vj = pj;
+        if (j >= 0) {
+            pj = pos[j];
+            vj = vel[j];
+        }
+        const bool h = j >= 0;
+        const float dz = pj.z - d.pz;
+        f[10 + 6 * t + 0] = h ? pj.x - d.px : 0.f;
+        f[10 + 6 * t + 1] = h ? pj.y - d.py : 0.f;
+        f[10 + 6 * t + 2] = h ? dz : 0.f;
+        f[10 + 6 * t + 3] = h ? vj.x - d.vx : 0.f;
+        f[10 + 6 * t + 4] = h ? vj.y - d.vy : 0.f;
+        f[10 + 6 * t + 5] = h ? vj.z - d.vz : 0.f;
+        ood |= h && dz > 0.f && dz < dz_ood;
+    }
+    f[58] = d.pz;
+#pragma unroll
+    for (int k = 59; k < MLP_IN; ++k) f[k] = 0.f;
+    return ood;
+}
+
+// Plain aerodynamic residual of the selected effects (world frame): ground
+// effect, drag, and the downwash sweep over the environment in ascending order.
+__device__ __forceinline__ void plain_aero(const KConst &c, uint32_t mask, const Drone &d, const Rot &R,
+                                           const float n[4], float T, const float4 *pos, int lo, int m,
+                                           int mmax, float &Fx, float &Fy, float &Fz) {
+    Fx = Fy = Fz = 0.f;
+    if (mask & 1u) Fz += ground_effect(c, d, R, T);
+    if (mask & 2u) {
+        float dx, dy, dz;
+        drag(c, d, R, n, dx, dy, dz);
+        Fx += dx;
+        Fy += dy;
+        Fz += dz;
+    }
+    if (mask & 4u) {
+        float acc = 0.f;
+        for (int j = 0; j < mmax; ++j) {
+            const float4 pj = pos[lo + j];
+            const float term = dw_term(c, pj.x - d.px, pj.y - d.py, pj.z - d.pz);
+            acc += (j < m) ? term : 0.f;
+        }
+        Fz -= acc;
+    }
+}
+
+__device__ __forceinline__ float silu(float z) { return z * __builtin_amdgcn_rcpf(1.f + __expf(-z)); }
+
+__device__ __forceinline__ bf16x8 ldw(const bf16 *p) { return *(const bf16x8 *)p; }
+
+// One hidden layer for the wave's 4 drone tiles: hout[ot][dt] = SiLU(W hin + b)
+// as bfloat16, K = 128 (4 chunks of 32), inputs in the permuted fragment order.
+__device__ __forceinline__ void hidden_layer(const bf16 *W, const float *b, const bf16x4 hin[8][4],
+                                             bf16x4 hout[8][4], int lane) {
+    const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int ot = 0; ot < 8; ++ot) {
+        f32x4 acc[4];
+#pragma unroll
+        for (int dt = 0; dt < 4; ++dt) acc[dt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+            const bf16x8 a = ldw(W + (16 * ot + r) * MLP_H + 32 * kc + 8 * g);
+#pragma unroll
+            for (int dt = 0; dt < 4; ++dt) {
+                const bf16x8 bv = __builtin_shufflevector(hin[2 * kc][dt], hin[2 * kc + 1][dt], 0, 1, 2, 3, 4, 5, 6, 7);
+                acc[dt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[dt], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int dt = 0; dt < 4; ++dt) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) hout[ot][dt][t] = (bf16)silu(acc[dt][t] + b[16 * ot + 4 * g + t]);
+        }
+    }
+}
+
+// The network on the 64 drones of one wave: standardised bfloat16 inputs in
+// feat (row per drone), standardised outputs to out (row per drone, 6 used).
+__device__ __forceinline__ void mlp_wave(const bf16 *feat, float *out, const bf16 *W, const float *b, int lane) {
+    const int r = lane & 15, g = lane >> 4;
+    bf16x4 h1[8][4], h2[8][4];
+    // layer 1: K = 64, B fragments straight from the staged rows
+    {
+        bf16x8 x[2][4];
+#pragma unroll
+        for (int kc = 0; kc < 2; ++kc)
+#pragma unroll
+            for (int dt = 0; dt < 4; ++dt)
+                x[kc][dt] = *(const bf16x8 *)(feat + (16 * dt + r) * FEAT_STRIDE + 32 * kc + 8 * g);
+#pragma unroll
+        for (int ot = 0; ot < 8; ++ot) {
+            f32x4 acc[4];
+#pragma unroll
+            for (int dt = 0; dt < 4; ++dt) acc[dt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kc = 0; kc < 2; ++kc) {
+                const bf16x8 a = ldw(W + WOFF1 + (16 * ot + r) * MLP_IN + 32 * kc + 8 * g);
+#pragma unroll
+                for (int dt = 0; dt < 4; ++dt)
+                    acc[dt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, x[kc][dt], acc[dt], 0, 0, 0);
+            }
+#pragma unroll
+            for (int dt = 0; dt < 4; ++dt)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) h1[ot][dt][t] = (bf16)silu(acc[dt][t] + b[BOFF1 + 16 * ot + 4 * g + t]);
+        }
+    }
+    hidden_layer(W + WOFF2, b + BOFF2, h1, h2, lane);
+    hidden_layer(W + WOFF3, b + BOFF3, h2, h1, lane);
+    // output layer: one 16-row tile (rows 0..5 used)
+    f32x4 acc[4];
+#pragma unroll
+    for (int dt = 0; dt < 4; ++dt) acc[dt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+        const bf16x8 a = ldw(W + WOFF4 + r * MLP_H + 32 * kc + 8 * g);
+#pragma unroll
+        for (int dt = 0; dt < 4; ++dt) {
+            const bf16x8 bv = __builtin_shufflevector(h1[2 * kc][dt], h1[2 * kc + 1][dt], 0, 1, 2, 3, 4, 5, 6, 7);
+            acc[dt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[dt], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int dt = 0; dt < 4; ++dt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int o = 4 * g + t;
+            if (o < MLP_OUT) out[(16 * dt + r) * OUT_STRIDE + o] = acc[dt][t] + b[BOFF4 + o];
+        }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int ACT>
+__global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
+    const StepArgs &a = sa.s;
+    const KConst &c = a.c;
+    const int S = blockDim.x;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    float4 *posb = (float4 *)smem;              // [2][2S]
+    float4 *velb = posb + 4 * S;                // [2][2S]
+    bf16 *feat = (bf16 *)(velb + 4 * S);        // [S][FEAT_STRIDE]
+    float *outs = (float *)(feat + S * FEAT_STRIDE);  // [S][OUT_STRIDE]
+    const int slot = threadIdx.x, lane = threadIdx.x & 63, wbase = threadIdx.x & ~63;
+    const int2 tab = a.bins.slot[blockIdx.x * S + slot];
+    const int di = tab.x;
+    const bool valid = di >= 0;
+    const int lo = tab.y >> 16, menv = tab.y & 0xffff;
+    const int mmax = a.bins.bin_mmax[blockIdx.x];
+    const int N = a.N;
+    const float *xm = sa.norm, *xs = sa.norm + MLP_IN, *ym = sa.norm + 2 * MLP_IN, *ysd = ym + MLP_OUT;
+
+    Drone d{};
+    d.qw = 1.f;
+    float I[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float n[4] = {0.f, 0.f, 0.f, 0.f};
+    if (valid) {
+        load_drone(a.s, N, di, d);
+        for (int k = 0; k < 4; ++k) n[k] = a.s.rpm[k * N + di];
+        if (ACT == 1)
+            for (int k = 0; k < 6; ++k) I[k] = a.s.pid_int[k * N + di];
+    }
+    double jerr = 0.0, jref = 0.0, jterr = 0.0, jn = 0.0, jfb = 0.0;
+    int phase = (ACT == 1) ? (int)(a.step0 % (long long)c.decim) : 0;
+    int oslot = 0;
+    for (int step = 0; step < a.n_steps; ++step) {
+        float4 *pos = posb + (step & 1) * 2 * S;
+        float4 *vel = velb + (step & 1) * 2 * S;
+        pos[slot] = make_float4(d.px, d.py, d.pz, 0.f);
+        vel[slot] = make_float4(d.vx, d.vy, d.vz, 0.f);
+        __syncthreads();
+        const float *act = a.action + a.act_step_stride * step;
+        if (ACT == 0) {
+            if (valid)
+                for (int k = 0; k < 4; ++k) n[k] = clampf(act[(long long)k * N + di], 0.f, c.max_rpm);
+        } else {
+            if (phase == 0 && valid) {
+                float tgt[4];
+                for (int k = 0; k < 4; ++k) tgt[k] = act[(long long)k * N + di];
+                pid_update(c, d, tgt, I, n);
+            }
+            phase = (phase + 1 == c.decim) ? 0 : phase + 1;
+        }
+        float T, tx, ty, tz;
+        motor(c, n, T, tx, ty, tz);
+        const Rot R = rot_of(d);
+        // ---- features -> standardised bfloat16 row
+        int bj[KNN];
+        knn8(pos, lo, menv, mmax, slot, d.px, d.py, d.pz, bj);
+        float f[MLP_IN];
+        const bool ood = features(c, d, R, n, pos, vel, bj, sa.dz_ood, f) && valid;
+        bf16 *row = feat + slot * FEAT_STRIDE;
+#pragma unroll
+        for (int k = 0; k < MLP_IN; k += 8) {
+            bf16x8 v;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) v[t] = valid ? (bf16)((f[k + t] - xm[k + t]) * xs[k + t]) : (bf16)0.f;
+            *(bf16x8 *)(row + k) = v;
+        }
+        __syncthreads();
+        mlp_wave(feat + wbase * FEAT_STRIDE, outs + wbase * OUT_STRIDE, sa.W, sa.b, lane);
+        __syncthreads();
+        float y[MLP_OUT];
+#pragma unroll
+        for (int o = 0; o < MLP_OUT; ++o) y[o] = outs[slot * OUT_STRIDE + o] * ysd[o] + ym[o];
+        float Fx = R.r02 * T, Fy = R.r12 * T, Fz = R.r22 * T - c.mg;
+        float ax, ay, az;
+        // surrogate force, body -> world
+        const float sx = R.r00 * y[0] + R.r01 * y[1] + R.r02 * y[2];
+        const float sy = R.r10 * y[0] + R.r11 * y[1] + R.r12 * y[2];
+        const float sz = R.r20 * y[0] + R.r21 * y[1] + R.r22 * y[2];
+        const bool judge = valid && !ood && sa.judge_mask >= 0 &&
+                           (((unsigned)di + (unsigned)(a.step0 + step)) & (unsigned)sa.judge_mask) == 0u;
+        float px_ = 0.f, py_ = 0.f, pz_ = 0.f;
+        if (ood || judge) plain_aero(c, 7u, d, R, n, T, pos, lo, menv, mmax, px_, py_, pz_);
+        if (ood) {
+            ax = px_;
+            ay = py_;
+            az = pz_;
+            jfb += 1.0;
+        } else {
+            ax = sx;
+            ay = sy;
+            az = sz;
+            tx += y[3];
+            ty += y[4];
+            tz += y[5];
+        }
+        if (judge) {
+            const float ex = sx - px_, ey = sy - py_, ez = sz - pz_;
+            jerr += (double)(ex * ex + ey * ey + ez * ez);
+            jref += (double)(px_ * px_ + py_ * py_ + pz_ * pz_);
+            jterr += (double)(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]);
+            jn += 1.0;
+        }
+        Fx += ax;
+        Fy += ay;
+        Fz += az;
+        integrate(c, d, Fx, Fy, Fz, tx, ty, tz);
+        if (a.obs != nullptr && valid) {
+            float roll, pitch, yaw;
+            euler_zyx(d, roll, pitch, yaw);
+            float *o = a.obs + (long long)oslot * 20 * N + di;
+            const float rowo[20] = {d.px, d.py, d.pz, d.qw, d.qx, d.qy, d.qz, roll, pitch, yaw,
+                                    d.vx, d.vy, d.vz, d.wx, d.wy, d.wz, n[0], n[1], n[2], n[3]};
+#pragma unroll
+            for (int k = 0; k < 20; ++k) o[(long long)k * N] = rowo[k];
+        }
+        oslot = (oslot + 1 == a.n_obs_slots) ? 0 : oslot + 1;
+    }
+    if (valid) {
+        a.s.p[di] = d.px;
+        a.s.p[N + di] = d.py;
+        a.s.p[2 * N + di] = d.pz;
+        a.s.q[di] = d.qw;
+        a.s.q[N + di] = d.qx;
+        a.s.q[2 * N + di] = d.qy;
+        a.s.q[3 * N + di] = d.qz;
+        a.s.v[di] = d.vx;
+        a.s.v[N + di] = d.vy;
+        a.s.v[2 * N + di] = d.vz;
+        a.s.w[di] = d.wx;
+        a.s.w[N + di] = d.wy;
+        a.s.w[2 * N + di] = d.wz;
+        for (int k = 0; k < 4; ++k) a.s.rpm[k * N + di] = n[k];
+        if (ACT == 1)
+            for (int k = 0; k < 6; ++k) a.s.pid_int[k * N + di] = I[k];
+    }
+    if (sa.judge != nullptr) {
+        const double s0 = wave_sum(jerr), s1 = wave_sum(jref), s2 = wave_sum(jterr), s3 = wave_sum(jn),
+                     s4 = wave_sum(jfb);
+        const double steps = wave_sum(valid ? (double)a.n_steps : 0.0);
+        if (lane == 0) {
+            atomicAdd(sa.judge + J_ERR2, s0);
+            atomicAdd(sa.judge + J_REF2, s1);
+            atomicAdd(sa.judge + J_TERR2, s2);
+            atomicAdd(sa.judge + J_N, s3);
+            atomicAdd(sa.judge + J_FALLBACK, s4);
+            atomicAdd(sa.judge + J_STEPS, steps);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) datagen_kernel(GenArgs g) {
+    const KConst &c = g.c;
+    const int S = blockDim.x;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    float4 *pos = (float4 *)smem;  // [2S]
+    float4 *vel = pos + 2 * S;     // [2S]
+    const int slot = threadIdx.x;
+    const int2 tab = g.bins.slot[blockIdx.x * S + slot];
+    const int di = tab.x;
+    const bool valid = di >= 0;
+    const int lo = tab.y >> 16, menv = tab.y & 0xffff;
+    const int mmax = g.bins.bin_mmax[blockIdx.x];
+    Drone d{};
+    d.qw = 1.f;
+    float n[4] = {0.f, 0.f, 0.f, 0.f};
+    if (valid) {
+        load_drone(g.s, g.N, di, d);
+        for (int k = 0; k < 4; ++k) n[k] = g.s.rpm[k * g.N + di];
+    }
+    pos[slot] = make_float4(d.px, d.py, d.pz, 0.f);
+    vel[slot] = make_float4(d.vx, d.vy, d.vz, 0.f);
+    pos[S + slot] = make_float4(0.f, 0.f, 0.f, 0.f);
+    vel[S + slot] = make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+    if (!valid) return;
+    float T, tx, ty, tz;
+    motor(c, n, T, tx, ty, tz);
+    const Rot R = rot_of(d);
+    int bj[KNN];
+    knn8(pos, lo, menv, mmax, slot, d.px, d.py, d.pz, bj);
+    float f[MLP_IN];
+    (void)features(c, d, R, n, pos, vel, bj, 0.f, f);
+    float *x = g.X + (long long)di * MLP_IN;
+#pragma unroll
+    for (int k = 0; k < MLP_IN; k += 4) *(float4 *)(x + k) = make_float4(f[k], f[k + 1], f[k + 2], f[k + 3]);
+    float Fx, Fy, Fz;
+    plain_aero(c, g.mask, d, R, n, T, pos, lo, menv, mmax, Fx, Fy, Fz);
+    float *y = g.Y + (long long)di * MLP_OUT;
+    y[0] = R.r00 * Fx + R.r10 * Fy + R.r20 * Fz;
+    y[1] = R.r01 * Fx + R.r11 * Fy + R.r21 * Fz;
+    y[2] = R.r02 * Fx + R.r12 * Fy + R.r22 * Fz;
+    y[3] = 0.f;
+    y[4] = 0.f;
+    y[5] = 0.f;
+    if (g.nbr) {
+        // neighbour slots back to drone indices: same environment, same offset
+        const int base = di - (slot - lo);
+        for (int t = 0; t < KNN; ++t) g.nbr[(long long)di * KNN + t] = bj[t] >= 0 ? base + (bj[t] - lo) : -1;
+    }
+}
+
+}  // namespace
+
+size_t sur_lds_bytes(int S) {
+    return sizeof(float4) * 8 * (size_t)S + sizeof(bf16) * (size_t)S * FEAT_STRIDE + sizeof(float) * (size_t)S * OUT_STRIDE;
+}
+
+hipError_t launch_sur_step(const SurArgs &sa, int act, int n_bins, int S, hipStream_t st) {
+    const size_t lds = sur_lds_bytes(S);
+    if (act == 0)
+        hipLaunchKernelGGL(sur_step_kernel<0>, dim3(n_bins), dim3(S), lds, st, sa);
+    else
+        hipLaunchKernelGGL(sur_step_kernel<1>, dim3(n_bins), dim3(S), lds, st, sa);
+    return hipGetLastError();
+}
+
+hipError_t launch_datagen(const GenArgs &g, int n_bins, int S, hipStream_t st) {
+    hipLaunchKernelGGL(datagen_kernel, dim3(n_bins), dim3(S), sizeof(float4) * 4 * (size_t)S, st, g);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- host side
+
+// Hidden unit that feeds slot s (0..31) of a 32-wide K chunk when the
+// previous layer's C tiles are used as B fragments in place (see top).
+static int permuted_unit(int s) {
+    const int g = s / 8, t = s % 8;
+    return t < 4 ? 4 * g + t : 16 + 4 * g + (t - 4);
+}
+
+static md_status sur_alloc(md_ctx *ctx) {
+    if (!ctx->sur) ctx->sur = new (std::nothrow) SurrogateState();
+    if (!ctx->sur) return MD_E_OOM;
+    SurrogateState *S = ctx->sur;
+    if (S->W) return MD_OK;
+    hipError_t e = hipMalloc(&S->W, sizeof(bf16) * WTOTAL);
+    if (e == hipSuccess) e = hipMalloc(&S->b, sizeof(float) * BTOTAL);
+    if (e == hipSuccess) e = hipMalloc(&S->norm, sizeof(float) * MLP_NORM);
+    if (e == hipSuccess) e = hipMalloc(&S->judge, sizeof(double) * 8);
+    if (e == hipSuccess) e = hipMemset(S->judge, 0, sizeof(double) * 8);
+    if (e != hipSuccess) {
+        ctx->err = hip_msg("surrogate buffers", e);
+        return MD_E_OOM;
+    }
+    return MD_OK;
+}
+
+md_status load_surrogate(md_ctx *ctx, const float *params, const float *norm, float dz_ood, int judge_stride) {
+    if (!(dz_ood >= 0.f) || judge_stride < 0 || (judge_stride > 0 && (judge_stride & (judge_stride - 1)))) {
+        ctx->err = "md_load_surrogate: dz_ood must be >= 0 and judge_stride 0 or a power of two";
+        return MD_E_INVALID_ARG;
+    }
+    for (int i = 0; i < MLP_IN; ++i)
+        if (!(norm[MLP_IN + i] > 0.f)) {
+            ctx->err = "md_load_surrogate: input scales must be > 0";
+            return MD_E_INVALID_ARG;
+        }
+    md_status rc = sur_alloc(ctx);
+    if (rc != MD_OK) return rc;
+    std::vector<bf16> W(WTOTAL, (bf16)0.f);
+    std::vector<float> b(BTOTAL, 0.f);
+    const float *W1 = params + kParamOff[0], *W2 = params + kParamOff[2], *W3 = params + kParamOff[4],
+                *W4 = params + kParamOff[6];
+    for (int o = 0; o < MLP_H; ++o)
+        for (int k = 0; k < MLP_IN; ++k) W[WOFF1 + o * MLP_IN + k] = (bf16)W1[o * MLP_IN + k];
+    const float *Ws[2] = {W2, W3};
+    const int offs[2] = {WOFF2, WOFF3};
+    for (int l = 0; l < 2; ++l)
+        for (int o = 0; o < MLP_H; ++o)
+            for (int kc = 0; kc < 4; ++kc)
+                for (int s = 0; s < 32; ++s)
+                    W[offs[l] + o * MLP_H + 32 * kc + s] = (bf16)Ws[l][o * MLP_H + 32 * kc + permuted_unit(s)];
+    for (int o = 0; o < MLP_OUT; ++o)
+        for (int kc = 0; kc < 4; ++kc)
+            for (int s = 0; s < 32; ++s)
+                W[WOFF4 + o * MLP_H + 32 * kc + s] = (bf16)W4[o * MLP_H + 32 * kc + permuted_unit(s)];
+    for (int i = 0; i < MLP_H; ++i) {
+        b[BOFF1 + i] = params[kParamOff[1] + i];
+        b[BOFF2 + i] = params[kParamOff[3] + i];
+        b[BOFF3 + i] = params[kParamOff[5] + i];
+    }
+    for (int o = 0; o < MLP_OUT; ++o) b[BOFF4 + o] = params[kParamOff[7] + o];
+    SurrogateState *S = ctx->sur;
+    hipError_t e = hipMemcpy(S->W, W.data(), sizeof(bf16) * WTOTAL, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(S->b, b.data(), sizeof(float) * BTOTAL, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(S->norm, norm, sizeof(float) * MLP_NORM, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        ctx->err = hip_msg("md_load_surrogate", e);
+        return MD_E_HIP;
+    }
+    S->dz_ood = dz_ood;
+    S->judge_stride = judge_stride;
+    S->loaded = true;
+    return MD_OK;
+}
+
+md_status surrogate_step(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step, float *d_obs,
+                         int n_obs_slots, int n_steps, int64_t step0, hipStream_t st) {
+    if (!ctx->sur || !ctx->sur->loaded) {
+        ctx->err = "md_step: surrogate weights not loaded (md_load_surrogate)";
+        return MD_E_INVALID_ARG;
+    }
+    if (ctx->max_m > 256) {
+        ctx->err = "md_step: the surrogate path supports environments of up to 256 drones";
+        return MD_E_UNSUPPORTED;
+    }
+    int waves = 1;
+    while (64 * waves < ctx->max_m) waves *= 2;
+    BinSet *bs = nullptr;
+    md_status rc = build_bins(ctx, 64 * waves, &bs);
+    if (rc != MD_OK) return rc;
+    SurArgs sa;
+    sa.s.c = ctx->kc;
+    sa.s.s = StatePtr{s->p, s->q, s->v, s->w, s->pid_int, s->rpm};
+    sa.s.action = d_action;
+    sa.s.act_step_stride = action_per_step ? 4LL * ctx->n_drones : 0;
+    sa.s.obs = (n_obs_slots > 0) ? d_obs : nullptr;
+    sa.s.n_obs_slots = n_obs_slots > 0 ? n_obs_slots : 1;
+    sa.s.n_steps = n_steps;
+    sa.s.step0 = step0;
+    sa.s.N = ctx->n_drones;
+    sa.s.bins = BinTables{bs->d_slot, bs->d_mmax};
+    sa.W = ctx->sur->W;
+    sa.b = ctx->sur->b;
+    sa.norm = ctx->sur->norm;
+    sa.judge = ctx->sur->judge;
+    sa.dz_ood = ctx->sur->dz_ood;
+    sa.judge_mask = ctx->sur->judge_stride > 0 ? ctx->sur->judge_stride - 1 : -1;
+    hipError_t e = launch_sur_step(sa, ctx->act, bs->n_bins, bs->slots, st);
+    if (e != hipSuccess) {
+        ctx->err = hip_msg("surrogate step launch", e);
+        return MD_E_HIP;
+    }
+    return MD_OK;
+}
+
+md_status datagen(md_ctx *ctx, const md_state *s, uint32_t mask, float *d_X, float *d_Y, int32_t *d_nbr,
+                  hipStream_t st) {
+    if (ctx->max_m > 256) {
+        ctx->err = "md_datagen: environments of up to 256 drones";
+        return MD_E_UNSUPPORTED;
+    }
+    int waves = 1;
+    while (64 * waves < ctx->max_m) waves *= 2;
+    BinSet *bs = nullptr;
+    md_status rc = build_bins(ctx, 64 * waves, &bs);
+    if (rc != MD_OK) return rc;
+    GenArgs g;
+    g.c = ctx->kc;
+    g.s = StatePtr{s->p, s->q, s->v, s->w, s->pid_int, s->rpm};
+    g.N = ctx->n_drones;
+    g.bins = BinTables{bs->d_slot, bs->d_mmax};
+    g.mask = mask;
+    g.X = d_X;
+    g.Y = d_Y;
+    g.nbr = d_nbr;
+    hipError_t e = launch_datagen(g, bs->n_bins, bs->slots, st);
+    if (e != hipSuccess) {
+        ctx->err = hip_msg("datagen launch", e);
+        return MD_E_HIP;
+    }
+    return MD_OK;
+}
+
+md_status judge_stats(md_ctx *ctx, md_judge *out) {
+    std::memset(out, 0, sizeof *out);
+    if (!ctx->sur || !ctx->sur->judge) return MD_OK;
+    double h[8];
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(h, ctx->sur->judge, sizeof h, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        ctx->err = hip_msg("md_judge_stats", e);
+        return MD_E_HIP;
+    }
+    out->n_judged = h[J_N];
+    out->force_err2 = h[J_ERR2];
+    out->force_ref2 = h[J_REF2];
+    out->torque_err2 = h[J_TERR2];
+    out->n_fallback = h[J_FALLBACK];
+    out->n_drone_steps = h[J_STEPS];
+    out->force_rel_err = h[J_REF2] > 0 ? std::sqrt(h[J_ERR2] / h[J_REF2]) : 0.0;
+    return MD_OK;
+}
+
+md_status judge_reset(md_ctx *ctx) {
+    if (!ctx->sur || !ctx->sur->judge) return MD_OK;
+    if (hipMemset(ctx->sur->judge, 0, sizeof(double) * 8) != hipSuccess) return MD_E_HIP;
+    return MD_OK;
+}
+
+void free_surrogate(md_ctx *ctx) {
+    if (!ctx->sur) return;
+    (void)hipFree(ctx->sur->W);
+    (void)hipFree(ctx->sur->b);
+    (void)hipFree(ctx->sur->norm);
+    (void)hipFree(ctx->sur->judge);
+    delete ctx->sur;
+    ctx->sur = nullptr;
+}
+
+}  // namespace md
+
+extern "C" {
+
+md_status md_load_surrogate(md_ctx *ctx, const float *h_params, const float *h_norm, float dz_ood,
+                            int judge_stride) {
+    if (!ctx) return MD_E_INVALID_ARG;
+    if (!h_params || !h_norm) {
+        ctx->err = "md_load_surrogate: null parameters";
+        return MD_E_INVALID_ARG;
+    }
+    (void)hipSetDevice(ctx->device);
+    return md::load_surrogate(ctx, h_params, h_norm, dz_ood, judge_stride);
+}
+
+md_status md_load_surrogate_mlp(md_ctx *ctx, const md_mlp *m, float dz_ood, int judge_stride) {
+    if (!ctx || !m) return MD_E_INVALID_ARG;
+    std::vector<float> p(md::MLP_NPARAMS), nrm(md::MLP_NORM);
+    if (md_mlp_get_params(m, p.data()) != MD_OK || md_mlp_get_norm(m, nrm.data()) != MD_OK) {
+        ctx->err = "md_load_surrogate_mlp: could not read the network";
+        return MD_E_HIP;
+    }
+    return md_load_surrogate(ctx, p.data(), nrm.data(), dz_ood, judge_stride);
+}
+
+md_status md_datagen(md_ctx *ctx, const md_state *s, uint32_t aero_mask, float *d_X, float *d_Y,
+                     int32_t *d_nbr, void *stream) {
+    if (!ctx) return MD_E_INVALID_ARG;
+    if (!ctx->has_layout) {
+        ctx->err = "md_datagen: no layout bound";
+        return MD_E_LAYOUT;
+    }
+    if (ctx->n_drones == 0) return MD_OK;
+    if (!s || !s->p || !s->q || !s->v || !s->w || !s->rpm || !d_X || !d_Y || (aero_mask & ~7u)) {
+        ctx->err = "md_datagen: null pointer or aero_mask outside GND|DRAG|DW";
+        return MD_E_INVALID_ARG;
+    }
+    return md::datagen(ctx, s, aero_mask, d_X, d_Y, d_nbr, (hipStream_t)stream);
+}
+
+md_status md_judge_stats(md_ctx *ctx, md_judge *out) {
+    if (!ctx || !out) return MD_E_INVALID_ARG;
+    return md::judge_stats(ctx, out);
+}
+
+md_status md_judge_reset(md_ctx *ctx) {
+    if (!ctx) return MD_E_INVALID_ARG;
+    return md::judge_reset(ctx);
+}
+
+}  // extern "C"

@@ -195,3 +195,132 @@ class DeviceState:
 
     def as_md_state(self):
         return md_state(*[self.t[k].data_ptr() for k in ("p", "q", "v", "w", "pid_int", "rpm")])
+
+
+# ------------------------------------------------------------------ surrogate network
+
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_NPARAMS, MLP_NORM = 64, 128, 6, 42118, 140
+MLP_SHAPES = ((128, 64), (128,), (128, 128), (128,), (128, 128), (128,), (6, 128), (6,))
+
+
+def _fptr(a):
+    assert a.dtype == np.float32 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def mlp_check(status, m):
+    if status != MD_OK:
+        raise MdError(status, lib().md_mlp_last_error(m).decode())
+
+
+def md_mlp_create(max_batch):
+    m = _VP()
+    st = lib().md_mlp_create(int(max_batch), ctypes.byref(m))
+    if st != MD_OK:
+        raise MdError(st, "md_mlp_create")
+    return m
+
+
+def md_mlp_destroy(m):
+    lib().md_mlp_destroy(m)
+
+
+def md_mlp_set_params(m, flat):
+    a = np.ascontiguousarray(flat, dtype=np.float32)
+    assert a.size == MLP_NPARAMS
+    mlp_check(lib().md_mlp_set_params(m, _fptr(a)), m)
+
+
+def md_mlp_get_params(m):
+    a = np.zeros(MLP_NPARAMS, dtype=np.float32)
+    mlp_check(lib().md_mlp_get_params(m, _fptr(a)), m)
+    return a
+
+
+def md_mlp_set_norm(m, norm):
+    a = np.ascontiguousarray(norm, dtype=np.float32)
+    assert a.size == MLP_NORM
+    mlp_check(lib().md_mlp_set_norm(m, _fptr(a)), m)
+
+
+def md_mlp_get_norm(m):
+    a = np.zeros(MLP_NORM, dtype=np.float32)
+    mlp_check(lib().md_mlp_get_norm(m, _fptr(a)), m)
+    return a
+
+
+def md_mlp_forward(m, X, B=None, Y=None, stream=None):
+    B = X.shape[0] if B is None else B
+    mlp_check(lib().md_mlp_forward(m, _VP(X.data_ptr()), int(B),
+                                   _VP(Y.data_ptr()) if Y is not None else None,
+                                   _stream_ptr(stream)), m)
+
+
+def md_mlp_backward(m, T, B=None, stream=None):
+    B = T.shape[0] if B is None else B
+    mlp_check(lib().md_mlp_backward(m, _VP(T.data_ptr()), int(B), _stream_ptr(stream)), m)
+
+
+def md_mlp_get_grads(m):
+    a = np.zeros(MLP_NPARAMS, dtype=np.float32)
+    mlp_check(lib().md_mlp_get_grads(m, _fptr(a)), m)
+    return a
+
+
+def md_mlp_loss(m):
+    d = ctypes.c_double()
+    mlp_check(lib().md_mlp_loss(m, ctypes.byref(d)), m)
+    return d.value
+
+
+def md_mlp_adam(m, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    mlp_check(lib().md_mlp_adam(m, float(lr), float(beta1), float(beta2), float(eps),
+                                _stream_ptr(stream)), m)
+
+
+def mlp_unflatten(flat):
+    """Split the flat parameter vector into W1, b1, ..., W4, b4."""
+    out, o = [], 0
+    for sh in MLP_SHAPES:
+        n = int(np.prod(sh))
+        out.append(np.asarray(flat[o:o + n]).reshape(sh))
+        o += n
+    return out
+
+
+def mlp_flatten(parts):
+    return np.concatenate([np.asarray(p, dtype=np.float32).ravel() for p in parts])
+
+
+# ------------------------------------------------------------------ surrogate in the step
+
+class md_judge(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("n_judged", "force_err2", "force_ref2", "torque_err2",
+                                                "n_fallback", "n_drone_steps", "force_rel_err")]
+
+
+def md_load_surrogate(ctx, flat, norm, dz_ood=1e-3, judge_stride=64):
+    a = np.ascontiguousarray(flat, dtype=np.float32)
+    b = np.ascontiguousarray(norm, dtype=np.float32)
+    assert a.size == MLP_NPARAMS and b.size == MLP_NORM
+    check(lib().md_load_surrogate(ctx, _fptr(a), _fptr(b), float(dz_ood), int(judge_stride)), ctx)
+
+
+def md_load_surrogate_mlp(ctx, m, dz_ood=1e-3, judge_stride=64):
+    check(lib().md_load_surrogate_mlp(ctx, m, float(dz_ood), int(judge_stride)), ctx)
+
+
+def md_datagen(ctx, state, aero_mask, X, Y, nbr=None, stream=None):
+    ms = state.as_md_state() if hasattr(state, "as_md_state") else state
+    check(lib().md_datagen(ctx, ctypes.byref(ms), int(aero_mask), _VP(X.data_ptr()), _VP(Y.data_ptr()),
+                           _VP(nbr.data_ptr()) if nbr is not None else None, _stream_ptr(stream)), ctx)
+
+
+def md_judge_stats(ctx):
+    j = md_judge()
+    check(lib().md_judge_stats(ctx, ctypes.byref(j)), ctx)
+    return {k: getattr(j, k) for k, _ in md_judge._fields_}
+
+
+def md_judge_reset(ctx):
+    check(lib().md_judge_reset(ctx), ctx)

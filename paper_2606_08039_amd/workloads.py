@@ -119,7 +119,18 @@ def lattice(n_envs=16384, shape=(2, 2, 2), n_steps=1000, seed=3, target_jitter=0
     s["p"][:] = tgt[0:3].astype(np.float64) + rng.uniform(-start_jitter, start_jitter, size=(3, n))
     return dict(name="lattice%dx%dx%d" % shape, env_offsets=off, state=s, action=tgt[None],
                 action_per_step=False, aero_mask=1 | 2 | 4, act_type="pid", ctrl_decim=5,
-                n_steps=n_steps, dt=DT)
+                n_steps=n_steps, dt=DT, lattice_points=base.astype(np.float32),
+                target_jitter=target_jitter)
+
+
+def rejitter_targets(w, rng):
+    """New PID waypoints for a lattice workload: its lattice points plus a
+    fresh U[-j, j]^3 jitter (the same draw as at creation), yaw 0."""
+    base = w["lattice_points"]
+    j = w["target_jitter"]
+    tgt = np.zeros((1, 4, base.shape[1]), dtype=np.float32)
+    tgt[0, 0:3] = base + rng.uniform(-j, j, size=base.shape)
+    return tgt
 
 
 def formation(n_envs=8192, n_steps=1000, seed=4):
@@ -140,6 +151,8 @@ def permute_envs(w, perm):
     out["env_offsets"] = noff
     out["state"] = {k: np.ascontiguousarray(v[:, idx]) for k, v in w["state"].items()}
     out["action"] = np.ascontiguousarray(w["action"][:, :, idx])
+    if "lattice_points" in w:
+        out["lattice_points"] = np.ascontiguousarray(w["lattice_points"][:, idx])
     out["drone_index"] = idx
     return out
 
@@ -152,4 +165,6 @@ def subset_envs(w, n_envs):
     out["env_offsets"] = off
     out["state"] = {k: np.ascontiguousarray(v[:, :n]) for k, v in w["state"].items()}
     out["action"] = np.ascontiguousarray(w["action"][:, :, :n])
+    if "lattice_points" in w:
+        out["lattice_points"] = np.ascontiguousarray(w["lattice_points"][:, :n])
     return out

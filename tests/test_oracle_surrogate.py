@@ -191,3 +191,76 @@ def test_bf16_forward_rounds_input_and_hidden_only():
     z1 = Xr @ Ws[0].T + bs[0]
     h1 = orc.bf16_round(z1 / (1 + np.exp(-z1)))
     np.testing.assert_allclose(Y, h1 @ Ws[1].T + bs[1], rtol=1e-13)
+
+
+def _lattice_pair_state(dz_low):
+    """Two envs: a stacked pair (lower drone dz_low below the upper one) and a
+    lone drone; level, at rest."""
+    s = orc.new_state(3)
+    s["p"][:, 0] = [0.0, 0.0, 1.0]
+    s["p"][:, 1] = [0.05, 0.0, 1.0 + dz_low]
+    s["p"][:, 2] = [3.0, 1.0, 0.7]
+    s["v"][:, 0] = [0.1, -0.2, 0.05]
+    return s, np.array([0, 2, 3], dtype=np.int32)
+
+
+def _flat_zero():
+    return np.zeros(42118, dtype=np.float32)
+
+
+def _norm_identity():
+    return np.concatenate([np.zeros(64), np.ones(64), np.zeros(6), np.ones(6)]).astype(np.float32)
+
+
+def test_surrogate_step_with_zero_network_is_the_aero_free_step():
+    P = orc.cf2x()
+    D = orc.derive(P)
+    rng = np.random.default_rng(38)
+    s1, off = _lattice_pair_state(0.9)
+    s2 = {k: v.copy() for k, v in s1.items()}
+    act = (D.hover_rpm * (1 + rng.uniform(-0.05, 0.05, size=(5, 4, 3))))
+    net, keep = orc.make_net(_flat_zero(), _norm_identity(), 1e-3)
+    orc.step_surrogate(P, 1 / 240, orc.ACT_RPM, 1, off, s1, act, True, 5, net)
+    orc.step(P, 1 / 240, 0, orc.ACT_RPM, 1, off, s2, act, True, 5)
+    for k in s1:
+        np.testing.assert_array_equal(s1[k], s2[k])
+
+
+def test_surrogate_step_constant_body_force_closed_form():
+    # W = 0, output bias b4 -> constant standardised output; body force
+    # y = b4 * y_std + y_mean on a level hovering drone changes v by dt F / m.
+    P = orc.cf2x()
+    D = orc.derive(P)
+    flat = _flat_zero()
+    flat[42112:42118] = [0.5, -1.0, 2.0, 0.0, 0.0, 0.0]
+    norm = _norm_identity()
+    norm[134:140] = [0.01, 0.01, 0.01, 1.0, 1.0, 1.0]
+    norm[128:131] = [0.001, 0.0, -0.002]
+    s = orc.new_state(1)
+    s["p"][:, 0] = [0, 0, 1]
+    net, keep = orc.make_net(flat, norm, 1e-3)
+    act = np.full((1, 4, 1), D.hover_rpm)
+    _, aero, fb = orc.step_surrogate(P, 1 / 240, orc.ACT_RPM, 1, [0, 1], s, act, False, 1, net)
+    f32 = lambda x: float(np.float32(x))
+    F = np.array([0.5 * f32(0.01) + f32(0.001), -1.0 * f32(0.01), 2.0 * f32(0.01) + f32(-0.002)])
+    np.testing.assert_allclose(aero[0, :3], F, rtol=1e-12)
+    np.testing.assert_allclose(s["v"][:, 0], F / P.m / 240, rtol=1e-9, atol=1e-15)
+    assert fb[0] == 0
+
+
+def test_surrogate_fallback_takes_the_plain_terms():
+    P = orc.cf2x()
+    D = orc.derive(P)
+    s, off = _lattice_pair_state(4e-4)  # drone 1 sits 0.4 mm above drone 0
+    s_ref = {k: v.copy() for k, v in s.items()}
+    net, keep = orc.make_net(_flat_zero(), _norm_identity(), 1e-3)
+    act = np.full((1, 4, 3), D.hover_rpm)
+    _, aero, fb = orc.step_surrogate(P, 1 / 240, orc.ACT_RPM, 1, off, s, act, False, 1, net)
+    assert list(fb) == [1, 0, 0]
+    Y = orc.aero_residual(P, 7, off, s_ref, rpm=np.full((4, 3), D.hover_rpm))
+    np.testing.assert_allclose(aero[0], Y[0], rtol=1e-12)
+    assert aero[0, 2] < -1.0  # the singular downwash is large here
+    # the fallback drone's step equals the plain full-aero step
+    orc.step(P, 1 / 240, 7, orc.ACT_RPM, 1, off, s_ref, act, False, 1)
+    for k in ("p", "v", "w", "q"):
+        np.testing.assert_allclose(s[k][:, 0], s_ref[k][:, 0], rtol=1e-12, atol=1e-15)
