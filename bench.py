@@ -43,6 +43,35 @@ OBS_BYTES = 80             # 20 float32 per drone-step
 STATE_BYTES = 2 * 4 * 23   # state read + written once per launch (p,q,v,w,pid_int,rpm)
 
 
+KERNEL_SOURCES = ("paper_2606_08039_amd/csrc/md_step.hip", "paper_2606_08039_amd/csrc/md_physics.h",
+                  "paper_2606_08039_amd/csrc/md_internal.h", "paper_2606_08039_amd/csrc/md_api.cpp")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload_name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE passes, each scaled by what the counter reads
+    for a plain 1 GiB device copy), or None when the kernel sources changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_%s_counters.json" % workload_name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec["fetch_kib_per_dispatch"] * 1024 * rec["fetch_scale"] + \
+        rec["write_kib_per_dispatch"] * 1024 * rec["write_scale"]
+
+
 def workload(name, hover):
     from paper_2606_08039_amd import workloads as wl
     if name == "formation":
@@ -120,6 +149,59 @@ def cpu_baseline(w, with_obs, seconds_target=12.0):
                       % (envs, ds // steps, steps, threads, dtm)}
 
 
+def surrogate_leg(args, w, p, with_obs):
+    """The same rollouts with the learned residual in place of Eq. 4-6
+    (fallback near the downwash singularity, 1/64 of drone-steps judged
+    against the plain terms)."""
+    import torch
+    from paper_2606_08039_amd import md, surrogate
+    path = args.weights or surrogate.DEFAULT_WEIGHTS
+    if not os.path.exists(path):
+        return {"value": None, "note": "no trained weights at %s" % os.path.relpath(path, ROOT)}
+    flat, norm, meta = surrogate.load(path)
+    n = int(w["env_offsets"][-1])
+    K = w["n_steps"]
+    act = md.MD_ACT_RPM if w["act_type"] == "rpm" else md.MD_ACT_PID
+    ctx = md.md_create(p, w["dt"], md.MD_AERO_SURROGATE, act, w["ctrl_decim"])
+    try:
+        md.md_bind_layout(ctx, w["env_offsets"])
+        md.md_load_surrogate(ctx, flat, norm, 1e-3, 64)
+        state = md.DeviceState.from_numpy(w["state"])
+        action = torch.from_numpy(np.ascontiguousarray(w["action"], dtype=np.float32)).cuda()
+        obs = torch.empty((K, 20, n), dtype=torch.float32, device="cuda") if with_obs else None
+        n_slots = K if with_obs else 0
+        stream = torch.cuda.current_stream()
+        step0 = 0
+        for _ in range(args.warmup):
+            md.md_step(ctx, state, action, w["action_per_step"], obs, n_slots, K, step0, stream)
+            step0 += K
+        torch.cuda.synchronize()
+        md.md_judge_reset(ctx)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ev[i][0].record(stream)
+            md.md_step(ctx, state, action, w["action_per_step"], obs, n_slots, K, step0, stream)
+            ev[i][1].record(stream)
+            step0 += K
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        j = md.md_judge_stats(ctx)
+    finally:
+        md.md_destroy(ctx)
+    ds = float(n) * K * args.steps
+    mfma_flop = 86016.0 * n * K
+    return {"value": ds / wall, "unit": "drone-steps/s", "ms_per_step": wall / args.steps * 1e3,
+            "kernel_ms_avg": kms,
+            "mfma_tflops": mfma_flop / (kms * 1e-3) / 1e12,
+            "judge_force_rel_err": j["force_rel_err"], "judged_drone_steps": j["n_judged"],
+            "fallback_fraction": j["n_fallback"] / max(j["n_drone_steps"], 1.0),
+            "held_out_force_rel_err": meta.get("eps_held_out"),
+            "weights": os.path.relpath(path, ROOT)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
@@ -128,6 +210,8 @@ def main():
     ap.add_argument("--workload", default="formation")
     ap.add_argument("--no-obs", action="store_true", help="skip the KIN-20 writes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-aero leg")
+    ap.add_argument("--weights", default=None, help="surrogate weights file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -186,7 +270,7 @@ def main():
     alu = flop / kavg / 1e12
     if with_obs:
         roof = {"bound": "hbm", "achieved": round(hbm, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": None}
+                "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload)}
     else:
         roof = {"bound": "alu", "achieved": round(alu, 3), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(alu / FP32_PEAK_TFLOPS, 4), "traffic": None}
@@ -214,6 +298,10 @@ def main():
         "algorithmic_bytes_per_launch": bytes_,
         "algorithmic_flop_per_launch": flop,
     }
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_leg(args, w, p, with_obs)
+        if out["surrogate"].get("value"):
+            out["surrogate"]["speed_vs_plain"] = out["surrogate"]["value"] / value
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)

@@ -60,6 +60,8 @@ KConst make_kconst(const md_params &p, const md_derived &d, double dt, int decim
     c.C2 = (float)p.C2;
     c.C3 = (float)p.C3;
     c.dz_min = (float)std::max(0.0, p.dw_dz_min);
+    c.C2s = (float)(std::sqrt(2.0 * std::log(2.0)) * p.C2);
+    c.C3s = (float)(std::sqrt(2.0 * std::log(2.0)) * p.C3);
     for (int k = 0; k < 3; ++k) {
         c.pkp[k] = (float)p.pos_kp[k];
         c.pki[k] = (float)p.pos_ki[k];
@@ -134,7 +136,9 @@ static void pack_bins(const std::vector<int32_t> &off, int slots, std::vector<in
     mmax.assign(n_bins, 0);
     for (int ob = 0; ob < n_bins; ++ob) {
         const Bin &B = bins[border[ob]];
-        mmax[ob] = B.mmax;
+        bool uniform = true;
+        for (int e : B.envs) uniform = uniform && (off[e + 1] - off[e] == B.mmax);
+        mmax[ob] = B.mmax | (uniform ? 0x10000 : 0);
         int lo = 0;
         for (int e : B.envs) {
             const int m = off[e + 1] - off[e];

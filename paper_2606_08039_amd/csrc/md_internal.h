@@ -16,6 +16,7 @@ struct KConst {
     float max_rpm, h_clip, K_gnd;         // K_gnd = C_gnd r_p^2 / 16   (Eq. 4)
     float drag_s, c_xy, c_z;              // drag_s = 2 pi / 60         (Eq. 5)
     float K1, C2, C3, dz_min;             // K1 = C1 r_p^2 / 16         (Eq. 6)
+    float C2s, C3s;                       // sqrt(2 ln 2) C2, sqrt(2 ln 2) C3
     float pkp[3], pki[3], pkd[3], p_clamp;
     float akp[3], aki[3], akd[3], a_clamp;
     float dt_c, g_inv, l_inv, kappa_inv, fmax, kf_inv;
@@ -31,7 +32,9 @@ struct StatePtr {
 // One bin = one workgroup.  Per slot (drone slot inside the bin):
 //   x = global drone index or -1 for an idle slot,
 //   y = (first slot of the drone's environment inside the bin) << 16 | M_env.
-// Per bin: the largest environment it holds (uniform neighbour-loop bound).
+// Per bin: the largest environment it holds (the uniform neighbour-loop
+// bound) in the low 16 bits, and bit 16 set when every environment in the
+// bin has that size (no per-lane bound check needed).
 struct BinTables {
     const int2 *slot;      // [n_bins * slots]
     const int *bin_mmax;   // [n_bins]

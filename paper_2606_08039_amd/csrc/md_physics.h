@@ -41,14 +41,47 @@ __device__ __forceinline__ Rot rot_of(const Drone &d) {
     return R;
 }
 
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// arctan(a) for a in [0, 1] as a * P(a^2), P of degree 7 fitted to atan(a)/a
+// by iteratively reweighted least squares on Chebyshev nodes (max error
+// 3.8e-8 rad in exact arithmetic, 1.3e-7 rad evaluated in float32).
+__device__ __forceinline__ float atan01(float a) {
+    const float s = a * a;
+    float p = -4.054536119e-03f;
+    p = p * s + 2.186285485e-02f;
+    p = p * s - 5.591219459e-02f;
+    p = p * s + 9.642189160e-02f;
+    p = p * s - 1.390862714e-01f;
+    p = p * s + 1.994656539e-01f;
+    p = p * s - 3.332986079e-01f;
+    p = p * s + 9.999993356e-01f;
+    return a * p;
+}
+
+// atan2 by octant reduction to atan01 (the quotient of the smaller over the
+// larger magnitude, then pi/2 - r, pi - r and the sign of y); 0 for (0, 0).
+__device__ __forceinline__ float atan2_poly(float y, float x) {
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+    const float a = mx > 0.f ? mn * rcp(mx) : 0.f;
+    float r = atan01(a);
+    r = (ay > ax) ? 1.5707963267948966f - r : r;
+    r = (x < 0.f) ? 3.141592653589793f - r : r;
+    return copysignf(r, y);
+}
+
+// asin(s) = atan2(s, sqrt((1 - s)(1 + s))), |s| <= 1
+__device__ __forceinline__ float asin_poly(float s) { return atan2_poly(s, fsqrt((1.f - s) * (1.f + s))); }
+
 // Roll, pitch, yaw (Z-Y-X) of the KIN observation.
 __device__ __forceinline__ void euler_zyx(const Drone &d, float &roll, float &pitch, float &yaw) {
     const float w = d.qw, x = d.qx, y = d.qy, z = d.qz;
     float sp = 2.f * (w * y - z * x);
     sp = fminf(fmaxf(sp, -1.f), 1.f);
-    roll = atan2f(2.f * (w * x + y * z), 1.f - 2.f * (x * x + y * y));
-    pitch = asinf(sp);
-    yaw = atan2f(2.f * (w * z + x * y), 1.f - 2.f * (y * y + z * z));
+    roll = atan2_poly(2.f * (w * x + y * z), 1.f - 2.f * (x * x + y * y));
+    pitch = asin_poly(sp);
+    yaw = atan2_poly(2.f * (w * z + x * y), 1.f - 2.f * (y * y + z * z));
 }
 
 __device__ __forceinline__ float clampf(float x, float lo, float hi) {
@@ -67,14 +100,14 @@ __device__ __forceinline__ void pid_update(const KConst &c, const Drone &d, cons
     const float ax = c.pkp[0] * ex + c.pki[0] * I[0] - c.pkd[0] * d.vx;
     const float ay = c.pkp[1] * ey + c.pki[1] * I[1] - c.pkd[1] * d.vy;
     const float az = c.pkp[2] * ez + c.pki[2] * I[2] - c.pkd[2] * d.vz + c.g;
-    const float T = c.m * sqrtf(ax * ax + ay * ay + az * az);
+    const float T = c.m * fsqrt(ax * ax + ay * ay + az * az);
 
     const float w = d.qw, x = d.qx, y = d.qy, z = d.qz;
     float sp = clampf(2.f * (w * y - z * x), -1.f, 1.f);
-    const float roll = atan2f(2.f * (w * x + y * z), 1.f - 2.f * (x * x + y * y));
-    const float pitch = asinf(sp);
+    const float roll = atan2_poly(2.f * (w * x + y * z), 1.f - 2.f * (x * x + y * y));
+    const float pitch = asin_poly(sp);
     const float ys = 2.f * (w * z + x * y), yc = 1.f - 2.f * (y * y + z * z);
-    const float yaw = atan2f(ys, yc);
+    const float yaw = atan2_poly(ys, yc);
     // sin and cos of the yaw straight from the atan2 arguments
     const float h2 = ys * ys + yc * yc;
     const float hinv = h2 > 0.f ? rsqrtf(h2) : 0.f;
@@ -98,10 +131,10 @@ __device__ __forceinline__ void pid_update(const KConst &c, const Drone &d, cons
     const float F1 = 0.25f * (T + a + b + e);
     const float F2 = 0.25f * (T - a + b - e);
     const float F3 = 0.25f * (T - a - b + e);
-    n[0] = sqrtf(clampf(F0, 0.f, c.fmax) * c.kf_inv);
-    n[1] = sqrtf(clampf(F1, 0.f, c.fmax) * c.kf_inv);
-    n[2] = sqrtf(clampf(F2, 0.f, c.fmax) * c.kf_inv);
-    n[3] = sqrtf(clampf(F3, 0.f, c.fmax) * c.kf_inv);
+    n[0] = fsqrt(clampf(F0, 0.f, c.fmax) * c.kf_inv);
+    n[1] = fsqrt(clampf(F1, 0.f, c.fmax) * c.kf_inv);
+    n[2] = fsqrt(clampf(F2, 0.f, c.fmax) * c.kf_inv);
+    n[3] = fsqrt(clampf(F3, 0.f, c.fmax) * c.kf_inv);
 }
 
 // Motor model and X mixer (Eq. 1-3).  Contraction into fused multiply-adds is
@@ -139,7 +172,7 @@ __device__ __forceinline__ void integrate(const KConst &c, Drone &d, float Fx, f
     d.pz += c.dt * d.vz;
     const float wn2 = d.wx * d.wx + d.wy * d.wy + d.wz * d.wz;
     if (wn2 > 0.f) {
-        const float wn = sqrtf(wn2);
+        const float wn = fsqrt(wn2);
         const float th = 0.5f * c.dt * wn;
         float co, so;  // cos th, sin(th) / |w|
         if (th < 0.25f) {
@@ -165,24 +198,24 @@ __device__ __forceinline__ void integrate(const KConst &c, Drone &d, float Fx, f
     d.qz *= inv;
 }
 
-// Downwash term of one candidate neighbour j on drone i (Eq. 6), given the
-// coordinate differences dx, dy, dz = p_j - p_i formed from stored positions
-// (so the sign of dz, and dz == 0, are exact).  Returns 0 unless dz > 0 and
-// dxy < 10 m.
+// Downwash term of one candidate neighbour j on drone i (Eq. 6) without its
+// constant factor K1 = C1 r_p^2 / 16 (applied once to the sum): given
+// dx, dy, dz = p_j - p_i formed from stored positions (so the sign of dz and
+// dz == 0 are exact), returns exp(-dxy^2 / (2 beta^2)) / dz^2 if dz > 0 and
+// dxy < 10 m, else 0.  The Gaussian is evaluated as 2^(-dxy^2 / beta'^2)
+// with beta' = sqrt(2 ln 2) beta (C2, C3 pre-scaled on the host), and
+// beta'^2 + FLT_MIN in the denominator reproduces the beta -> 0 limit
+// (1 at dxy = 0, 0 elsewhere) without changing any normal beta'^2.
+template <bool DZMIN>
 __device__ __forceinline__ float dw_term(const KConst &c, float dx, float dy, float dz) {
     const float d2 = dx * dx + dy * dy;
-    const float dze = fmaxf(dz, c.dz_min);
+    const float dze = DZMIN ? fmaxf(dz, c.dz_min) : dz;
     const float r = rcp(dze);
-    const float alpha = c.K1 * (r * r);
-    const float beta = c.C2 * dze + c.C3;
-    const float b2 = beta * beta;
-    // exp(-dxy^2 / (2 beta^2)); the limit for beta -> 0 is 1 at dxy = 0, else 0
-    const float t = (d2 == 0.f) ? 0.f : (-0.5f * d2) * rcp(b2);
-    const float gauss = __expf(t);
+    const float bs = c.C2s * dze + c.C3s;
+    const float gauss = __builtin_amdgcn_exp2f(-d2 * rcp(bs * bs + 1.17549435e-38f));
     const bool on = (dz > 0.f) && (d2 < 100.f);
-    return on ? alpha * gauss : 0.f;
+    return on ? (r * r) * gauss : 0.f;
 }
-
 
 // Ground effect (Eq. 4) on the world z force: C_gnd T (r_p / 4 h)^2 with
 // h = max(z, h_clip), while the body z axis points up (R33 > 0, equivalent to

@@ -21,6 +21,31 @@ namespace {
 
 using namespace phys;
 
+// This lane's share of the downwash sum over its environment's slots
+// [lo, lo + mmax), in ascending order (every LPD-th slot from `sub`).  In a
+// uniform bin every environment has mmax drones and the bound check is
+// dropped.
+template <bool DZMIN, int LPD, int UNROLL>
+__device__ __forceinline__ float dw_sweep(const KConst &c, const float4 *buf, int lo, int sub, int mmax,
+                                          int menv, bool uniform, const Drone &d) {
+    float acc = 0.f;
+    if (uniform) {
+#pragma unroll UNROLL
+        for (int j = sub; j < mmax; j += LPD) {
+            const float4 pj = buf[lo + j];
+            acc += dw_term<DZMIN>(c, pj.x - d.px, pj.y - d.py, pj.z - d.pz);
+        }
+    } else {
+#pragma unroll UNROLL
+        for (int j = sub; j < mmax; j += LPD) {
+            const float4 pj = buf[lo + j];
+            const float term = dw_term<DZMIN>(c, pj.x - d.px, pj.y - d.py, pj.z - d.pz);
+            acc += (j < menv) ? term : 0.f;
+        }
+    }
+    return acc;
+}
+
 template <uint32_t MASK, int ACT, int LPD, int UNROLL>
 __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     extern __shared__ float4 lds_pos[];  // [2][2 * slots]: double-buffered, padded
@@ -33,7 +58,9 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     const bool valid = di >= 0;
     const int lo = tab.y >> 16;
     const int menv = tab.y & 0xffff;
-    const int mmax = a.bins.bin_mmax[blockIdx.x];
+    const int mm_word = a.bins.bin_mmax[blockIdx.x];
+    const int mmax = mm_word & 0xffff;
+    const bool uniform = (mm_word >> 16) != 0;
     const int N = a.N;
     const bool writer = valid && (sub == 0);
 
@@ -62,6 +89,13 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         d.qw = 1.f;
     }
 
+    // Held waypoints (one action row for the whole launch) stay in registers:
+    // re-reading them at every PID update would fetch them from HBM again,
+    // since the observation stream evicts them from L2.
+    const bool held = a.act_step_stride == 0;
+    float tgt_held[4] = {0.f, 0.f, 0.f, 0.f};
+    if (ACT == 1 && held && valid)
+        for (int k = 0; k < 4; ++k) tgt_held[k] = a.action[(long long)k * N + di];
     // PID phase and observation slot advance as counters (no per-step division)
     int phase = (ACT == 1) ? (int)(a.step0 % (long long)c.decim) : 0;
     int oslot = 0;
@@ -80,7 +114,7 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         } else {
             if (phase == 0 && valid) {
                 float tgt[4];
-                for (int k = 0; k < 4; ++k) tgt[k] = act[(long long)k * N + di];
+                for (int k = 0; k < 4; ++k) tgt[k] = held ? tgt_held[k] : act[(long long)k * N + di];
                 pid_update(c, d, tgt, I, n);
             }
             phase = (phase + 1 == c.decim) ? 0 : phase + 1;
@@ -103,12 +137,10 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         // ---- downwash (Eq. 6): sweep the environment in ascending order
         if (MASK & 4u) {
             float acc = 0.f;
-#pragma unroll UNROLL
-            for (int j = sub; j < mmax; j += LPD) {
-                const float4 pj = buf[lo + j];
-                const float term = dw_term(c, pj.x - d.px, pj.y - d.py, pj.z - d.pz);
-                acc += (j < menv) ? term : 0.f;
-            }
+            if (c.dz_min > 0.f)
+                acc = dw_sweep<true, LPD, UNROLL>(c, buf, lo, sub, mmax, menv, uniform, d);
+            else
+                acc = dw_sweep<false, LPD, UNROLL>(c, buf, lo, sub, mmax, menv, uniform, d);
             if (LPD >= 2) {
                 const float o = __shfl_xor(acc, 1, 64);
                 acc = (sub & 1) ? (o + acc) : (acc + o);
@@ -117,7 +149,7 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
                 const float o = __shfl_xor(acc, 2, 64);
                 acc = (sub & 2) ? (o + acc) : (acc + o);
             }
-            Fz -= acc;
+            Fz -= c.K1 * acc;
         }
         // ---- Newton-Euler + exponential map (Eq. 7)
         integrate(c, d, Fx, Fy, Fz, tx, ty, tz);

@@ -187,10 +187,11 @@ __device__ __forceinline__ void plain_aero(const KConst &c, uint32_t mask, const
         float acc = 0.f;
         for (int j = 0; j < mmax; ++j) {
             const float4 pj = pos[lo + j];
-            const float term = dw_term(c, pj.x - d.px, pj.y - d.py, pj.z - d.pz);
+            const float term = c.dz_min > 0.f ? dw_term<true>(c, pj.x - d.px, pj.y - d.py, pj.z - d.pz)
+                                              : dw_term<false>(c, pj.x - d.px, pj.y - d.py, pj.z - d.pz);
             acc += (j < m) ? term : 0.f;
         }
-        Fz -= acc;
+        Fz -= c.K1 * acc;
     }
 }
 
@@ -300,7 +301,7 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
     const int di = tab.x;
     const bool valid = di >= 0;
     const int lo = tab.y >> 16, menv = tab.y & 0xffff;
-    const int mmax = a.bins.bin_mmax[blockIdx.x];
+    const int mmax = a.bins.bin_mmax[blockIdx.x] & 0xffff;
     const int N = a.N;
     const float *xm = sa.norm, *xs = sa.norm + MLP_IN, *ym = sa.norm + 2 * MLP_IN, *ysd = ym + MLP_OUT;
 
@@ -314,6 +315,10 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
         if (ACT == 1)
             for (int k = 0; k < 6; ++k) I[k] = a.s.pid_int[k * N + di];
     }
+    const bool held = a.act_step_stride == 0;
+    float tgt_held[4] = {0.f, 0.f, 0.f, 0.f};
+    if (ACT == 1 && held && valid)
+        for (int k = 0; k < 4; ++k) tgt_held[k] = a.action[(long long)k * N + di];
     double jerr = 0.0, jref = 0.0, jterr = 0.0, jn = 0.0, jfb = 0.0;
     int phase = (ACT == 1) ? (int)(a.step0 % (long long)c.decim) : 0;
     int oslot = 0;
@@ -330,7 +335,7 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
         } else {
             if (phase == 0 && valid) {
                 float tgt[4];
-                for (int k = 0; k < 4; ++k) tgt[k] = act[(long long)k * N + di];
+                for (int k = 0; k < 4; ++k) tgt[k] = held ? tgt_held[k] : act[(long long)k * N + di];
                 pid_update(c, d, tgt, I, n);
             }
             phase = (phase + 1 == c.decim) ? 0 : phase + 1;
@@ -446,7 +451,7 @@ __global__ void __launch_bounds__(256) datagen_kernel(GenArgs g) {
     const int di = tab.x;
     const bool valid = di >= 0;
     const int lo = tab.y >> 16, menv = tab.y & 0xffff;
-    const int mmax = g.bins.bin_mmax[blockIdx.x];
+    const int mmax = g.bins.bin_mmax[blockIdx.x] & 0xffff;
     Drone d{};
     d.qw = 1.f;
     float n[4] = {0.f, 0.f, 0.f, 0.f};

@@ -47,9 +47,31 @@ def test_datagen_matches_oracle(kind):
     Yr = orc.aero_residual(P, 7, w["env_offsets"], s)
     sc = np.maximum(np.max(np.abs(Yr[:, :3]), axis=1), 1e-3)
     e = np.max(np.abs(Y[:, :3] - Yr[:, :3]), axis=1) / sc
-    print("%s: worst residual error (scaled) %.2e, max |F| %.3g" % (kind, e.max(), np.abs(Yr).max()))
-    assert e.max() < 1e-5
+    # All downwash terms share one sign, so the sum's relative error is bounded
+    # by the worst term's: float32 exp(-u) with u = dxy^2 / (2 beta^2) carries
+    # about u times the relative error of u (a few ulp), plus a few ulp.
+    tol = (6.0 + 4.0 * _max_exponent(P, w["env_offsets"], s)) * 2.0 ** -23
+    print("%s: worst residual error (scaled) %.2e (bound %.2e), max |F| %.3g"
+          % (kind, e.max(), tol.max(), np.abs(Yr).max()))
+    assert np.all(e <= np.maximum(tol, 1e-5))
     assert np.all(Y[:, 3:] == 0)
+
+
+def _max_exponent(P, off, s):
+    """Per drone, the largest downwash exponent dxy^2 / (2 beta^2) among the
+    pairs that act on it (0 if none)."""
+    out = np.zeros(int(off[-1]))
+    p = s["p"]
+    for e in range(len(off) - 1):
+        i0, i1 = int(off[e]), int(off[e + 1])
+        dz = p[2, i0:i1][None, :] - p[2, i0:i1][:, None]
+        dx = p[0, i0:i1][None, :] - p[0, i0:i1][:, None]
+        dy = p[1, i0:i1][None, :] - p[1, i0:i1][:, None]
+        d2 = dx * dx + dy * dy
+        beta = P.C2 * dz + P.C3
+        u = np.where((dz > 0) & (d2 < 100), d2 / (2 * beta * beta + 1e-300), 0.0)
+        out[i0:i1] = u.max(axis=1)
+    return out
 
 
 def _random_net(rng, scale=0.5):
