@@ -136,6 +136,53 @@ md_status md_step(md_ctx *ctx, const md_state *s, const float *d_action, int act
                   float *d_obs, int n_obs_slots, int n_steps, int64_t step0, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Launch configuration, autotuning and captured rollouts.
+ * ---------------------------------------------------------------------- */
+
+/* How md_step maps drones to the GPU.  Every valid configuration computes
+ * the same physics: lanes_per_drone 1 with or without pair_symmetric and any
+ * waves_per_group give bitwise identical results; lanes_per_drone 2 or 4
+ * split each neighbour sum into interleaved partial sums (a different but
+ * fixed summation order). */
+typedef struct md_launch_config {
+    int lanes_per_drone; /* 1, 2 or 4 lanes share one drone's neighbour sweep */
+    int unroll;          /* neighbour-loop unroll: 1, 2 or 4 */
+    int waves_per_group; /* 1, 2, 4, 8 or 16 wave64s per workgroup (bin of 64*w/lpd slots) */
+    int pair_symmetric;  /* 1: each unordered pair evaluated once (needs lanes_per_drone 1) */
+} md_launch_config;
+
+md_status md_get_launch_config(const md_ctx *ctx, md_launch_config *out);
+/* MD_E_INVALID_ARG if the configuration cannot hold the bound layout's
+ * largest environment or its LDS need exceeds 64 KB. */
+md_status md_set_launch_config(md_ctx *ctx, md_launch_config *cfg);
+
+/* Time every valid launch configuration for the bound layout on scratch
+ * copies of s (s itself is not modified) over n_steps steps of d_action,
+ * and select the fastest.  The choice is remembered in the JSON file
+ * cache_path (NULL: the MD_AUTOTUNE_CACHE environment variable; empty: no
+ * cache) under a signature of the layout, mask and action type; a cached
+ * choice is reused unless force is non-zero.  Synchronous; allocates two
+ * temporary state copies. */
+md_status md_autotune(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
+                      int n_steps, int64_t step0, void *stream, const char *cache_path, int force);
+
+/* A rollout of n_launches consecutive md_step launches of steps_per_launch
+ * steps each (step0 advancing by steps_per_launch; per-step actions and, when
+ * n_obs_slots >= steps_per_launch * n_launches, observation slots advance
+ * with it), captured once into a HIP graph.  md_graph_launch replays the
+ * whole rollout on a stream with the same pointers and step indices: keep
+ * steps_per_launch * n_launches a multiple of ctrl_decim for replays to keep
+ * the PID phase.  The graph belongs to the context's current layout and
+ * configuration; destroy it before re-binding. */
+typedef struct md_graph md_graph;
+md_status md_rollout_graph_create(md_ctx *ctx, const md_state *s, const float *d_action,
+                                  int action_per_step, float *d_obs, int n_obs_slots,
+                                  int steps_per_launch, int n_launches, int64_t step0,
+                                  void *stream, md_graph **out);
+md_status md_graph_launch(md_graph *g, void *stream);
+void md_graph_destroy(md_graph *g);
+
+/* ------------------------------------------------------------------------
  * Learned aerodynamic residual (surrogate for Eq. 4-6).
  *
  * Network: 64 inputs (59 features, zero padded) -> 128 -> 128 -> 128 -> 6,

@@ -18,7 +18,8 @@ from . import build_oracle
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
 AERO_GND, AERO_DRAG, AERO_DW, AERO_SURROGATE = 1, 2, 4, 8
-ACT_RPM, ACT_PID = 0, 1
+ACT_RPM, ACT_PID, ACT_VEL, ACT_ATTITUDE, ACT_DSL = 0, 1, 2, 3, 4
+ACTION_ROWS = {ACT_RPM: 4, ACT_PID: 4, ACT_VEL: 4, ACT_ATTITUDE: 4, ACT_DSL: 7}
 N_FEAT, K_NN = 64, 8
 
 
@@ -32,7 +33,12 @@ class Params(ctypes.Structure):
         ("pos_kp", ctypes.c_double * 3), ("pos_ki", ctypes.c_double * 3),
         ("pos_kd", ctypes.c_double * 3), ("pos_i_clamp", ctypes.c_double),
         ("att_kp", ctypes.c_double * 3), ("att_ki", ctypes.c_double * 3),
-        ("att_kd", ctypes.c_double * 3), ("att_i_clamp", ctypes.c_double)]
+        ("att_kd", ctypes.c_double * 3), ("att_i_clamp", ctypes.c_double),
+        ("dsl_pos_kp", ctypes.c_double * 3), ("dsl_pos_ki", ctypes.c_double * 3),
+        ("dsl_pos_kd", ctypes.c_double * 3), ("dsl_pos_i_clamp", ctypes.c_double),
+        ("dsl_att_kp", ctypes.c_double * 3), ("dsl_att_ki", ctypes.c_double * 3),
+        ("dsl_att_kd", ctypes.c_double * 3), ("dsl_att_i_clamp", ctypes.c_double),
+        ("dsl_max_speed", ctypes.c_double), ("dsl_max_yaw_rate", ctypes.c_double)]
 
     def copy(self):
         o = Params()
@@ -49,7 +55,7 @@ class Net(ctypes.Structure):
 
 
 class _CState(ctypes.Structure):
-    _fields_ = [(n, ctypes.POINTER(ctypes.c_double)) for n in ("p", "q", "v", "w", "pid_int", "rpm")]
+    _fields_ = [(n, ctypes.POINTER(ctypes.c_double)) for n in ("p", "q", "v", "w", "pid_int", "rpm", "ctl")]
 
 
 _lib = None
@@ -80,6 +86,10 @@ def _load():
     lib.orc_downwash_pair.restype = ctypes.c_double
     lib.orc_pid.argtypes = [P, ctypes.POINTER(Derived), ctypes.c_double, _D, _D, _D, _D, _D, _D, _D]
     lib.orc_integrate.argtypes = [P, ctypes.c_double, _D, _D, _D, _D, _D, _D]
+    lib.orc_vel_ctrl.argtypes = [P, ctypes.POINTER(Derived), ctypes.c_double, _D, _D, _D, _D, _D, _D]
+    lib.orc_att_ctrl.argtypes = [P, ctypes.POINTER(Derived), ctypes.c_double, _D, _D, _D, _D, _D]
+    lib.orc_dsl_pid.argtypes = [P, ctypes.POINTER(Derived), ctypes.c_double, _D, _D, _D, _D, _D,
+                                _D, _D, _D]
     lib.orc_step.argtypes = [P, ctypes.c_double, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
                              ctypes.c_int, _I32, ctypes.c_int, ctypes.POINTER(_CState), _D,
                              ctypes.c_int, _D, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
@@ -205,6 +215,40 @@ def pid(P, dt_c, p, q, v, w, target, integ):
     return n, I
 
 
+def vel_ctrl(P, dt_c, q, v, w, cmd, integ):
+    """VEL action controller (readings in md_oracle.c); returns (rpm, integrals)."""
+    D = derive(P)
+    q, v, w, c = _vec(q, 4), _vec(v, 3), _vec(w, 3), _vec(cmd, 4)
+    I = _vec(integ, 6).copy()
+    n = np.zeros(4)
+    _load().orc_vel_ctrl(ctypes.byref(P), ctypes.byref(D), float(dt_c), _dp(q), _dp(v), _dp(w),
+                         _dp(c), _dp(I), _dp(n))
+    return n, I
+
+
+def att_ctrl(P, dt_c, q, w, cmd, integ):
+    """ATTITUDE action controller; returns (rpm, integrals)."""
+    D = derive(P)
+    q, w, c = _vec(q, 4), _vec(w, 3), _vec(cmd, 4)
+    I = _vec(integ, 6).copy()
+    n = np.zeros(4)
+    _load().orc_att_ctrl(ctypes.byref(P), ctypes.byref(D), float(dt_c), _dp(q), _dp(w), _dp(c),
+                         _dp(I), _dp(n))
+    return n, I
+
+
+def dsl_pid(P, dt_c, p, q, v, w, cmd, integ, sp):
+    """DSL-style PID; returns (rpm, integrals, setpoint)."""
+    D = derive(P)
+    p, q, v, w, c = _vec(p, 3), _vec(q, 4), _vec(v, 3), _vec(w, 3), _vec(cmd, 7)
+    I = _vec(integ, 6).copy()
+    S = _vec(sp, 4).copy()
+    n = np.zeros(4)
+    _load().orc_dsl_pid(ctypes.byref(P), ctypes.byref(D), float(dt_c), _dp(p), _dp(q), _dp(v),
+                        _dp(w), _dp(c), _dp(I), _dp(S), _dp(n))
+    return n, I, S
+
+
 def integrate(P, dt, Fw, tau, p, q, v, w):
     """Sec. "Physics Modes": semi-implicit Euler + exponential map."""
     Fw, tau = _vec(Fw, 3), _vec(tau, 3)
@@ -218,7 +262,7 @@ def integrate(P, dt, Fw, tau, p, q, v, w):
 # Batched step.
 # --------------------------------------------------------------------------
 
-STATE_ROWS = {"p": 3, "q": 4, "v": 3, "w": 3, "pid_int": 6, "rpm": 4}
+STATE_ROWS = {"p": 3, "q": 4, "v": 3, "w": 3, "pid_int": 6, "rpm": 4, "ctl": 4}
 
 
 def new_state(n):
@@ -229,8 +273,11 @@ def new_state(n):
 
 def _cstate(s):
     for k in STATE_ROWS:
+        if k == "ctl" and k not in s:
+            continue
         assert s[k].dtype == np.float64 and s[k].flags.c_contiguous, k
-    return _CState(*[s[k].ctypes.data_as(_D) for k in ("p", "q", "v", "w", "pid_int", "rpm")])
+    return _CState(*[s[k].ctypes.data_as(_D) if k in s else None
+                     for k in ("p", "q", "v", "w", "pid_int", "rpm", "ctl")])
 
 
 def step(P, dt, aero_mask, act_type, ctrl_decim, env_offsets, state, action,
@@ -241,7 +288,7 @@ def step(P, dt, aero_mask, act_type, ctrl_decim, env_offsets, state, action,
     n_envs = len(off) - 1
     n = int(off[-1])
     act = np.ascontiguousarray(np.asarray(action, dtype=np.float64))
-    need = (n_steps if action_per_step else 1) * 4 * n
+    need = (n_steps if action_per_step else 1) * ACTION_ROWS[act_type] * n
     assert act.size == need, (act.size, need)
     obs = np.zeros((n_obs_slots, 20, n)) if n_obs_slots > 0 else None
     cs = _cstate(state)

@@ -67,6 +67,22 @@ void orc_params_cf2x(orc_params *P)
     }
     P->pos_i_clamp = 2.0;
     P->att_i_clamp = 0.5;
+    /* Sec. "Control", DSLPIDControl: halved integral clamps and setpoint rate
+     * limits of 2.0 m/s and pi rad/s.  Reading: its retuned gains are not
+     * printed; the defaults repeat the PIDControl gains (parity unpinned for
+     * any other tuning). */
+    for (int c = 0; c < 3; ++c) {
+        P->dsl_pos_kp[c] = pkp[c];
+        P->dsl_pos_ki[c] = pki[c];
+        P->dsl_pos_kd[c] = pkd[c];
+        P->dsl_att_kp[c] = akp[c];
+        P->dsl_att_ki[c] = aki[c];
+        P->dsl_att_kd[c] = akd[c];
+    }
+    P->dsl_pos_i_clamp = 1.0;
+    P->dsl_att_i_clamp = 0.25;
+    P->dsl_max_speed = 2.0;
+    P->dsl_max_yaw_rate = M_PI;
 }
 
 /* Sec. "Drone Models": HOVER_RPM = sqrt(m g / (4 kf)); MAX_RPM from
@@ -224,16 +240,54 @@ static double clampd(double x, double lo, double hi)
     return x < lo ? lo : (x > hi ? hi : x);
 }
 
+/* Attitude PID and allocation shared by the controllers.  Attitude error
+ * e = (roll* - roll, pitch* - pitch, e_yaw); I += e dt_c clamped to +-clamp;
+ * tau = Kp e + Ki I + Kd (w*_z z_hat - w) where the yaw-rate target w*_z is 0
+ * for the waypoint controllers; then the exact allocation inverse (rows of
+ * the mixer are orthogonal), rotor forces clipped to [0, kf MAX_RPM^2]. */
+static void attitude_allocate(const orc_params *P, const orc_derived *D, double dt_c,
+                              const double rpy[3], const double w[3], double T, double roll_t,
+                              double pitch_t, double e_yaw, double wz_t, const double kp[3],
+                              const double ki[3], const double kd[3], double clamp,
+                              double integ_att[3], double n_out[4])
+{
+    const double ea[3] = {roll_t - rpy[0], pitch_t - rpy[1], e_yaw};
+    const double wt[3] = {0.0, 0.0, wz_t};
+    double tau[3];
+    for (int c = 0; c < 3; ++c) {
+        integ_att[c] = clampd(integ_att[c] + ea[c] * dt_c, -clamp, clamp);
+        tau[c] = kp[c] * ea[c] + ki[c] * integ_att[c] + kd[c] * (wt[c] - w[c]);
+    }
+    const double l = P->L / sqrt(2.0), kap = P->km / P->kf;
+    static const double sx[4] = {1, 1, -1, -1}, sy[4] = {-1, 1, 1, -1}, sz[4] = {-1, 1, -1, 1};
+    const double fmax = P->kf * D->max_rpm * D->max_rpm;
+    for (int i = 0; i < 4; ++i) {
+        double F = 0.25 * (T + sx[i] * tau[0] / l + sy[i] * tau[1] / l + sz[i] * tau[2] / kap);
+        F = clampd(F, 0.0, fmax);
+        n_out[i] = sqrt(F / P->kf);
+    }
+}
+
+/* Thrust and small-angle attitude target from a desired acceleration a*
+ * (gravity included): T = m |a*|, roll* = (a_x sin psi - a_y cos psi) / g,
+ * pitch* = (a_x cos psi + a_y sin psi) / g at the current yaw psi. */
+static void thrust_direction(const orc_params *P, const double acc[3], double yaw, double *T,
+                             double *roll_t, double *pitch_t)
+{
+    *T = P->m * sqrt(acc[0] * acc[0] + acc[1] * acc[1] + acc[2] * acc[2]);
+    const double sps = sin(yaw), cps = cos(yaw);
+    *roll_t = (acc[0] * sps - acc[1] * cps) / P->g;
+    *pitch_t = (acc[0] * cps + acc[1] * sps) / P->g;
+}
+
 /* Position loop: a* = Kp e + Ki int(e) + Kd (v* - v) + g z_hat with v* = 0;
  * T = m |a*|.  Readings: the integrals advance by e * dt_c and are clamped
  * before use; the small-angle attitude target is the near-hover inversion of
- * the thrust direction at the current yaw psi,
- *   roll*  = (a*_x sin psi - a*_y cos psi) / g,
- *   pitch* = (a*_x cos psi + a*_y sin psi) / g,  yaw* = waypoint yaw;
- * the attitude PID acts on (roll*-roll, pitch*-pitch, wrap(yaw*-yaw)) with
- * derivative term Kd (0 - omega); the allocation T,tau = M [kf n_i^2] is
- * inverted exactly (its rows are mutually orthogonal) and each rotor force is
- * clipped to [0, kf MAX_RPM^2] (parity unpinned when saturated). */
+ * the thrust direction at the current yaw (thrust_direction); the attitude
+ * PID acts on (roll*-roll, pitch*-pitch, wrap(yaw*-yaw)) with derivative
+ * term Kd (0 - omega); the allocation T,tau = M [kf n_i^2] is inverted exactly
+ * and each rotor force is clipped to [0, kf MAX_RPM^2] (parity unpinned when
+ * saturated). */
 void orc_pid(const orc_params *P, const orc_derived *D, double dt_c, const double p[3],
              const double q[4], const double v[3], const double w[3], const double target[4],
              double integ[6], double n_out[4])
@@ -245,31 +299,111 @@ void orc_pid(const orc_params *P, const orc_derived *D, double dt_c, const doubl
         acc[c] = P->pos_kp[c] * e[c] + P->pos_ki[c] * integ[c] + P->pos_kd[c] * (0.0 - v[c]);
     }
     acc[2] += P->g;
-    const double T = P->m * sqrt(acc[0] * acc[0] + acc[1] * acc[1] + acc[2] * acc[2]);
+    double rpy[3], T, rt, pt;
+    orc_euler_zyx(q, rpy);
+    thrust_direction(P, acc, rpy[2], &T, &rt, &pt);
+    attitude_allocate(P, D, dt_c, rpy, w, T, rt, pt, wrap_pi(target[3] - rpy[2]), 0.0, P->att_kp,
+                      P->att_ki, P->att_kd, P->att_i_clamp, integ + 3, n_out);
+}
 
+/* VEL action (Table "Action types": body-frame [v_x, v_y, v_z, w_z], PID inner
+ * loop).  Readings: the velocity is given in the heading frame (yaw-only
+ * rotation of the world frame), v* = R_z(psi) (v_x, v_y, v_z); the position
+ * loop is bypassed, a* = Kd (v* - v) + g z_hat (its position integrals are
+ * left unchanged); the yaw channel tracks the rate, e_yaw = 0 and w*_z = w_z
+ * command; roll and pitch as in the PID. */
+void orc_vel_ctrl(const orc_params *P, const orc_derived *D, double dt_c, const double q[4],
+                  const double v[3], const double w[3], const double cmd[4], double integ[6],
+                  double n_out[4])
+{
     double rpy[3];
     orc_euler_zyx(q, rpy);
-    const double sps = sin(rpy[2]), cps = cos(rpy[2]);
-    const double roll_t = (acc[0] * sps - acc[1] * cps) / P->g;
-    const double pitch_t = (acc[0] * cps + acc[1] * sps) / P->g;
-    double ea[3] = {roll_t - rpy[0], pitch_t - rpy[1], wrap_pi(target[3] - rpy[2])};
-    double tau[3];
-    for (int c = 0; c < 3; ++c) {
-        integ[3 + c] = clampd(integ[3 + c] + ea[c] * dt_c, -P->att_i_clamp, P->att_i_clamp);
-        tau[c] = P->att_kp[c] * ea[c] + P->att_ki[c] * integ[3 + c] + P->att_kd[c] * (0.0 - w[c]);
-    }
+    const double c = cos(rpy[2]), s = sin(rpy[2]);
+    const double vt[3] = {c * cmd[0] - s * cmd[1], s * cmd[0] + c * cmd[1], cmd[2]};
+    double acc[3];
+    for (int k = 0; k < 3; ++k) acc[k] = P->pos_kd[k] * (vt[k] - v[k]);
+    acc[2] += P->g;
+    double T, rt, pt;
+    thrust_direction(P, acc, rpy[2], &T, &rt, &pt);
+    attitude_allocate(P, D, dt_c, rpy, w, T, rt, pt, 0.0, cmd[3], P->att_kp, P->att_ki,
+                      P->att_kd, P->att_i_clamp, integ + 3, n_out);
+}
 
-    /* Allocation inverse.  Rows of M: (1,1,1,1), l(1,1,-1,-1), l(-1,1,1,-1),
-     * kappa(-1,1,-1,1), l = L/sqrt(2), kappa = km/kf; each row has squared
-     * norm 4 * scale^2, so M^-1 = M^T diag(1/(4 scale^2)). */
-    const double l = P->L / sqrt(2.0), kap = P->km / P->kf;
-    static const double sx[4] = {1, 1, -1, -1}, sy[4] = {-1, 1, 1, -1}, sz[4] = {-1, 1, -1, 1};
-    const double fmax = P->kf * D->max_rpm * D->max_rpm;
-    for (int i = 0; i < 4; ++i) {
-        double F = 0.25 * (T + sx[i] * tau[0] / l + sy[i] * tau[1] / l + sz[i] * tau[2] / kap);
-        F = clampd(F, 0.0, fmax);
-        n_out[i] = sqrt(F / P->kf);
+/* ATTITUDE action (Table "Action types": thrust + roll + pitch + yaw-rate,
+ * mixer to RPM).  Readings: thrust is the collective thrust in newtons, roll
+ * and pitch are Z-Y-X angle targets in radians, the yaw channel tracks the
+ * rate (e_yaw = 0, w*_z = command); the attitude PID and allocation as in
+ * the PID. */
+void orc_att_ctrl(const orc_params *P, const orc_derived *D, double dt_c, const double q[4],
+                  const double w[3], const double cmd[4], double integ[6], double n_out[4])
+{
+    double rpy[3];
+    orc_euler_zyx(q, rpy);
+    attitude_allocate(P, D, dt_c, rpy, w, cmd[0], cmd[1], cmd[2], 0.0, cmd[3], P->att_kp,
+                      P->att_ki, P->att_kd, P->att_i_clamp, integ + 3, n_out);
+}
+
+/* DSL-style PID (Sec. "Control", DSLPIDControl): the waypoint controller
+ * with its own gains, halved integral clamps, a position setpoint that moves
+ * toward the waypoint by at most dsl_max_speed * dt_c (in norm) per update, a
+ * yaw setpoint that turns toward the waypoint yaw by at most
+ * dsl_max_yaw_rate * dt_c, and a feed-forward acceleration added to the
+ * position-loop output before the thrust direction.  cmd = (x, y, z, yaw,
+ * a_ff x, y, z); sp holds the setpoint (x, y, z, yaw) between updates.
+ * Reading: v* = 0, as in the PID. */
+void orc_dsl_pid(const orc_params *P, const orc_derived *D, double dt_c, const double p[3],
+                 const double q[4], const double v[3], const double w[3], const double cmd[7],
+                 double integ[6], double sp[4], double n_out[4])
+{
+    double d[3], dn = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        d[c] = cmd[c] - sp[c];
+        dn += d[c] * d[c];
     }
+    dn = sqrt(dn);
+    const double step = P->dsl_max_speed * dt_c;
+    const double sc = (dn > step) ? step / dn : 1.0;
+    for (int c = 0; c < 3; ++c) sp[c] += sc * d[c];
+    const double ymax = P->dsl_max_yaw_rate * dt_c;
+    sp[3] = wrap_pi(sp[3] + clampd(wrap_pi(cmd[3] - sp[3]), -ymax, ymax));
+    double e[3], acc[3];
+    for (int c = 0; c < 3; ++c) {
+        e[c] = sp[c] - p[c];
+        integ[c] = clampd(integ[c] + e[c] * dt_c, -P->dsl_pos_i_clamp, P->dsl_pos_i_clamp);
+        acc[c] = P->dsl_pos_kp[c] * e[c] + P->dsl_pos_ki[c] * integ[c] +
+                 P->dsl_pos_kd[c] * (0.0 - v[c]) + cmd[4 + c];
+    }
+    acc[2] += P->g;
+    double rpy[3], T, rt, pt;
+    orc_euler_zyx(q, rpy);
+    thrust_direction(P, acc, rpy[2], &T, &rt, &pt);
+    attitude_allocate(P, D, dt_c, rpy, w, T, rt, pt, wrap_pi(sp[3] - rpy[2]), 0.0, P->dsl_att_kp,
+                      P->dsl_att_ki, P->dsl_att_kd, P->dsl_att_i_clamp, integ + 3, n_out);
+}
+
+int orc_action_rows(int act_type) { return act_type == ORC_ACT_DSL ? 7 : 4; }
+
+/* One controller update of drone i for the non-RPM action types. */
+static void controller(const orc_params *P, const orc_derived *D, int act_type, double dt_c, int N,
+                       int i, const double *act, const double p[3], const double q[4],
+                       const double v[3], const double w[3], orc_state *s, double n[4])
+{
+    double cmd[7], integ[6], sp[4];
+    const int rows = orc_action_rows(act_type);
+    for (int c = 0; c < rows; ++c) cmd[c] = act[c * N + i];
+    for (int c = 0; c < 6; ++c) integ[c] = s->pid_int[c * N + i];
+    if (act_type == ORC_ACT_PID) {
+        orc_pid(P, D, dt_c, p, q, v, w, cmd, integ, n);
+    } else if (act_type == ORC_ACT_VEL) {
+        orc_vel_ctrl(P, D, dt_c, q, v, w, cmd, integ, n);
+    } else if (act_type == ORC_ACT_ATTITUDE) {
+        orc_att_ctrl(P, D, dt_c, q, w, cmd, integ, n);
+    } else {
+        for (int c = 0; c < 4; ++c) sp[c] = s->ctl[c * N + i];
+        orc_dsl_pid(P, D, dt_c, p, q, v, w, cmd, integ, sp, n);
+        for (int c = 0; c < 4; ++c) s->ctl[c * N + i] = sp[c];
+    }
+    for (int c = 0; c < 6; ++c) s->pid_int[c * N + i] = integ[c];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -330,6 +464,7 @@ int orc_step(const orc_params *P, double dt, uint32_t aero_mask, int act_type, i
     if (n_drones < 0 || n_envs < 0 || n_steps < 0 || ctrl_decim < 1) return -1;
     if (env_offsets[0] != 0 || env_offsets[n_envs] != n_drones) return -1;
     if (aero_mask & ORC_AERO_SURROGATE) return -1; /* handled by the surrogate oracle */
+    if (act_type < ORC_ACT_RPM || act_type > ORC_ACT_DSL || (act_type == ORC_ACT_DSL && !s->ctl)) return -1;
     orc_derived D;
     orc_derive(P, &D);
     const int N = n_drones;
@@ -342,8 +477,9 @@ int orc_step(const orc_params *P, double dt, uint32_t aero_mask, int act_type, i
 #endif
     for (int k = 0; k < n_steps; ++k) {
         memcpy(p_pre, s->p, sizeof(double) * 3 * (size_t)N);
-        const double *act = action + (action_per_step ? (size_t)k * 4 * N : 0);
-        const int do_pid = (act_type == ORC_ACT_PID) && (((step0 + k) % ctrl_decim) == 0);
+        const int rows = orc_action_rows(act_type);
+        const double *act = action + (action_per_step ? (size_t)k * rows * N : 0);
+        const int do_pid = (act_type != ORC_ACT_RPM) && (((step0 + k) % ctrl_decim) == 0);
 #pragma omp parallel for schedule(dynamic, 16)
         for (int e = 0; e < n_envs; ++e) {
             for (int i = env_offsets[e]; i < env_offsets[e + 1]; ++i) {
@@ -358,11 +494,7 @@ int orc_step(const orc_params *P, double dt, uint32_t aero_mask, int act_type, i
                 if (act_type == ORC_ACT_RPM) {
                     for (int c = 0; c < 4; ++c) n[c] = clampd(act[c * N + i], 0.0, D.max_rpm);
                 } else if (do_pid) {
-                    double tgt[4], integ[6];
-                    for (int c = 0; c < 4; ++c) tgt[c] = act[c * N + i];
-                    for (int c = 0; c < 6; ++c) integ[c] = s->pid_int[c * N + i];
-                    orc_pid(P, &D, dt * ctrl_decim, p, q, v, w, tgt, integ, n);
-                    for (int c = 0; c < 6; ++c) s->pid_int[c * N + i] = integ[c];
+                    controller(P, &D, act_type, dt * ctrl_decim, N, i, act, p, q, v, w, s, n);
                 } else {
                     for (int c = 0; c < 4; ++c) n[c] = s->rpm[c * N + i];
                 }
@@ -763,8 +895,9 @@ int orc_step_surrogate(const orc_params *P, double dt, int act_type, int ctrl_de
             rc = -2;
             break;
         }
-        const double *act = action + (action_per_step ? (size_t)k * 4 * N : 0);
-        const int do_pid = (act_type == ORC_ACT_PID) && (((step0 + k) % ctrl_decim) == 0);
+        const int rows = orc_action_rows(act_type);
+        const double *act = action + (action_per_step ? (size_t)k * rows * N : 0);
+        const int do_pid = (act_type != ORC_ACT_RPM) && (((step0 + k) % ctrl_decim) == 0);
 #pragma omp parallel for schedule(dynamic, 16)
         for (int e = 0; e < n_envs; ++e) {
             double acts[2 * (128 + 128 + 128 + 6)];
@@ -779,11 +912,7 @@ int orc_step_surrogate(const orc_params *P, double dt, int act_type, int ctrl_de
                 if (act_type == ORC_ACT_RPM) {
                     for (int c = 0; c < 4; ++c) n[c] = clampd(act[c * N + i], 0.0, D.max_rpm);
                 } else if (do_pid) {
-                    double tgt[4], integ[6];
-                    for (int c = 0; c < 4; ++c) tgt[c] = act[c * N + i];
-                    for (int c = 0; c < 6; ++c) integ[c] = s->pid_int[c * N + i];
-                    orc_pid(P, &D, dt * ctrl_decim, p, q, v, w, tgt, integ, n);
-                    for (int c = 0; c < 6; ++c) s->pid_int[c * N + i] = integ[c];
+                    controller(P, &D, act_type, dt * ctrl_decim, N, i, act, p, q, v, w, s, n);
                 } else {
                     for (int c = 0; c < 4; ++c) n[c] = s->rpm[c * N + i];
                 }

@@ -36,6 +36,10 @@ typedef struct orc_params {
     double C_gnd, c_xy, c_z, C1, C2, C3, dw_dz_min;
     double pos_kp[3], pos_ki[3], pos_kd[3], pos_i_clamp;
     double att_kp[3], att_ki[3], att_kd[3], att_i_clamp;
+    /* DSL-style PID: own gains and clamps, setpoint rate limits */
+    double dsl_pos_kp[3], dsl_pos_ki[3], dsl_pos_kd[3], dsl_pos_i_clamp;
+    double dsl_att_kp[3], dsl_att_ki[3], dsl_att_kd[3], dsl_att_i_clamp;
+    double dsl_max_speed, dsl_max_yaw_rate;
 } orc_params;
 
 typedef struct orc_derived {
@@ -50,10 +54,11 @@ typedef struct orc_state {
     double *w;       /* [3][n] body angular velocity, rad/s               */
     double *pid_int; /* [6][n] position (0..2) and attitude (3..5) sums   */
     double *rpm;     /* [4][n] rotor speeds applied in the last step, RPM */
+    double *ctl;     /* [4][n] DSL rate-limited setpoint x, y, z, yaw (DSL only) */
 } orc_state;
 
 enum { ORC_AERO_GND = 1, ORC_AERO_DRAG = 2, ORC_AERO_DW = 4, ORC_AERO_SURROGATE = 8 };
-enum { ORC_ACT_RPM = 0, ORC_ACT_PID = 1 };
+enum { ORC_ACT_RPM = 0, ORC_ACT_PID = 1, ORC_ACT_VEL = 2, ORC_ACT_ATTITUDE = 3, ORC_ACT_DSL = 4 };
 
 void orc_params_cf2x(orc_params *P);
 void orc_derive(const orc_params *P, orc_derived *D);
@@ -71,6 +76,15 @@ double orc_downwash_pair(const orc_params *P, const double p_low[3], const doubl
 void orc_pid(const orc_params *P, const orc_derived *D, double dt_c, const double p[3],
              const double q[4], const double v[3], const double w[3], const double target[4],
              double integ[6], double n_out[4]);
+void orc_vel_ctrl(const orc_params *P, const orc_derived *D, double dt_c, const double q[4],
+                  const double v[3], const double w[3], const double cmd[4], double integ[6],
+                  double n_out[4]);
+void orc_att_ctrl(const orc_params *P, const orc_derived *D, double dt_c, const double q[4],
+                  const double w[3], const double cmd[4], double integ[6], double n_out[4]);
+void orc_dsl_pid(const orc_params *P, const orc_derived *D, double dt_c, const double p[3],
+                 const double q[4], const double v[3], const double w[3], const double cmd[7],
+                 double integ[6], double sp[4], double n_out[4]);
+int orc_action_rows(int act_type);
 void orc_integrate(const orc_params *P, double dt, const double Fw[3], const double tau[3],
                    double p[3], double q[4], double v[3], double w[3]);
 

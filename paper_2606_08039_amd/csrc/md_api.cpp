@@ -202,9 +202,23 @@ int slots_for(const md_ctx *ctx, const LaunchCfg &cfg) {
 }
 
 LaunchCfg default_cfg(const md_ctx *ctx) {
-    LaunchCfg c{1, 4, 1};
+    LaunchCfg c{1, 4, 1, 0};
     while (64 * c.waves < ctx->max_m && c.waves < 16) c.waves *= 2;
     return c;
+}
+
+md_status prepare_launch(md_ctx *ctx) {
+    if (!ctx->has_layout) {
+        ctx->err = "no layout bound";
+        return MD_E_LAYOUT;
+    }
+    BinSet *bs = nullptr;
+    if (ctx->mask & MD_AERO_SURROGATE) {
+        int waves = 1;
+        while (64 * waves < ctx->max_m) waves *= 2;
+        return build_bins(ctx, 64 * waves, &bs);
+    }
+    return build_bins(ctx, slots_for(ctx, ctx->cfg), &bs);
 }
 
 md_status launch(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
@@ -224,6 +238,7 @@ md_status launch(md_ctx *ctx, const md_state *s, const float *d_action, int acti
     a.step0 = step0;
     a.N = ctx->n_drones;
     a.bins = BinTables{bs->d_slot, bs->d_mmax};
+    a.tstride = (ctx->max_m + 1) | 1;  // odd: the column writes of a wave spread over banks
     hipError_t e = launch_step(a, ctx->mask, ctx->act, cfg, bs->n_bins, bs->slots, st);
     if (e != hipSuccess) {
         ctx->err = hip_msg("step kernel launch", e);

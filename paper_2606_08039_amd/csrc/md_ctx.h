@@ -19,8 +19,7 @@ struct BinSet {
     std::vector<int> h_mmax;
 };
 
-struct SurrogateState;  // md_surrogate.cpp
-struct GraphCache;      // md_graph.cpp
+struct SurrogateState;  // md_surrogate.hip
 
 std::string hip_msg(const char *what, hipError_t e);
 void derive(const md_params &p, md_derived &d);
@@ -42,11 +41,10 @@ struct md_ctx {
     int n_envs = 0, n_drones = 0, max_m = 0;
     std::vector<int32_t> off;
     std::map<int, md::BinSet> binsets;  // keyed by slots per bin
-    md::LaunchCfg cfg{1, 4, 1};
+    md::LaunchCfg cfg{1, 4, 1, 0};
     bool tuned = false;
     // optional subsystems
     md::SurrogateState *sur = nullptr;
-    md::GraphCache *graphs = nullptr;
     std::string err;
 };
 
@@ -59,6 +57,11 @@ LaunchCfg default_cfg(const md_ctx *ctx);
 md_status launch(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
                  float *d_obs, int n_obs_slots, int n_steps, int64_t step0, hipStream_t st,
                  const LaunchCfg &cfg);
+
+// Build the bin tables the next md_step will use (synchronous uploads).
+md_status prepare_launch(md_ctx *ctx);
+md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step, int n_steps,
+                   int64_t step0, hipStream_t st, const char *path, int force);
 
 // Subsystems with per-context resources.
 void destroy_extras(md_ctx *ctx);

@@ -51,13 +51,15 @@ struct StepArgs {
     long long step0;
     int N;
     BinTables bins;
+    int tstride;  // row stride (floats) of the pair-term matrix in LDS (sym sweep)
 };
 
 // Launch configuration chosen per (shape, mask) by the autotuner.
 struct LaunchCfg {
     int lpd;     // lanes per drone in the neighbour sweep: 1, 2 or 4
     int unroll;  // neighbour-loop unroll: 1, 2, 4 or 8
-    int waves;   // waves per workgroup for environments of <= 64 drones: 1, 2 or 4
+    int waves;   // waves per workgroup (bin size 64 * waves / lpd slots)
+    int sym;     // 1: evaluate each unordered pair once (lpd must be 1)
 };
 
 hipError_t launch_step(const StepArgs &a, uint32_t mask, int act, const LaunchCfg &cfg,

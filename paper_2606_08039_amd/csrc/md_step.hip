@@ -46,9 +46,41 @@ __device__ __forceinline__ float dw_sweep(const KConst &c, const float4 *buf, in
     return acc;
 }
 
-template <uint32_t MASK, int ACT, int LPD, int UNROLL>
+// Pair-symmetric downwash sweep: each unordered pair of an environment is
+// evaluated once, by lane i for partners (i + d) mod M, d = 1..(M-1)/2, plus
+// d = M/2 from the lower half when M is even.  The term goes to the lower
+// drone's row of the LDS matrix T (the other entry gets 0); after a barrier
+// each drone sums its row in ascending order.  The term depends only on
+// dxy^2 and |dz|, and fl(a - b) = -fl(b - a), so every entry and the sum are
+// bitwise those of the all-pairs sweep.
+template <bool DZMIN, int UNROLL>
+__device__ __forceinline__ void dw_pairs(const KConst &c, const float4 *buf, float *T, int ts, int slot,
+                                         int lo, int m, const Drone &d) {
+    const int li = slot - lo;
+    const int h = (m - 1) >> 1;
+#pragma unroll UNROLL
+    for (int k = 1; k <= h; ++k) {
+        int lj = li + k;
+        lj -= (lj >= m) ? m : 0;
+        const float4 pj = buf[lo + lj];
+        const float dz = pj.z - d.pz;
+        const float t = dw_term<DZMIN>(c, pj.x - d.px, pj.y - d.py, fabsf(dz));
+        T[slot * ts + lj] = dz > 0.f ? t : 0.f;
+        T[(lo + lj) * ts + li] = dz < 0.f ? t : 0.f;
+    }
+    if ((m & 1) == 0 && li < (m >> 1) && m > 0) {
+        const int lj = li + (m >> 1);
+        const float4 pj = buf[lo + lj];
+        const float dz = pj.z - d.pz;
+        const float t = dw_term<DZMIN>(c, pj.x - d.px, pj.y - d.py, fabsf(dz));
+        T[slot * ts + lj] = dz > 0.f ? t : 0.f;
+        T[(lo + lj) * ts + li] = dz < 0.f ? t : 0.f;
+    }
+}
+
+template <uint32_t MASK, int ACT, int LPD, int UNROLL, bool SYM>
 __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
-    extern __shared__ float4 lds_pos[];  // [2][2 * slots]: double-buffered, padded
+    extern __shared__ float4 lds_pos[];  // [2][2 * slots] positions; then T [slots][tstride] (SYM)
     const KConst &c = a.c;
     const int slots = blockDim.x / LPD;
     const int slot = threadIdx.x / LPD;
@@ -89,6 +121,8 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         d.qw = 1.f;
     }
 
+    float *tmat = (float *)(lds_pos + 4 * slots);
+    if (SYM && (MASK & 4u)) tmat[slot * a.tstride + (slot - lo)] = 0.f;  // the diagonal stays 0
     // Held waypoints (one action row for the whole launch) stay in registers:
     // re-reading them at every PID update would fetch them from HBM again,
     // since the observation stream evicts them from L2.
@@ -137,10 +171,19 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         // ---- downwash (Eq. 6): sweep the environment in ascending order
         if (MASK & 4u) {
             float acc = 0.f;
-            if (c.dz_min > 0.f)
+            if (SYM) {
+                if (c.dz_min > 0.f)
+                    dw_pairs<true, UNROLL>(c, buf, tmat, a.tstride, slot, lo, menv, d);
+                else
+                    dw_pairs<false, UNROLL>(c, buf, tmat, a.tstride, slot, lo, menv, d);
+                __syncthreads();
+                const float *row = tmat + slot * a.tstride;
+                for (int j = 0; j < menv; ++j) acc += row[j];
+            } else if (c.dz_min > 0.f) {
                 acc = dw_sweep<true, LPD, UNROLL>(c, buf, lo, sub, mmax, menv, uniform, d);
-            else
+            } else {
                 acc = dw_sweep<false, LPD, UNROLL>(c, buf, lo, sub, mmax, menv, uniform, d);
+            }
             if (LPD >= 2) {
                 const float o = __shfl_xor(acc, 1, 64);
                 acc = (sub & 1) ? (o + acc) : (acc + o);
@@ -187,14 +230,12 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     }
 }
 
-template <uint32_t MASK, int ACT, int LPD>
-hipError_t launch_u(const StepArgs &a, int unroll, int n_bins, int threads, size_t lds,
-                    hipStream_t st) {
+template <uint32_t MASK, int ACT, int LPD, bool SYM>
+hipError_t launch_u(const StepArgs &a, int unroll, int n_bins, int threads, size_t lds, hipStream_t st) {
     switch (unroll) {
-        case 1: hipLaunchKernelGGL((step_kernel<MASK, ACT, LPD, 1>), dim3(n_bins), dim3(threads), lds, st, a); break;
-        case 2: hipLaunchKernelGGL((step_kernel<MASK, ACT, LPD, 2>), dim3(n_bins), dim3(threads), lds, st, a); break;
-        case 4: hipLaunchKernelGGL((step_kernel<MASK, ACT, LPD, 4>), dim3(n_bins), dim3(threads), lds, st, a); break;
-        case 8: hipLaunchKernelGGL((step_kernel<MASK, ACT, LPD, 8>), dim3(n_bins), dim3(threads), lds, st, a); break;
+        case 1: hipLaunchKernelGGL((step_kernel<MASK, ACT, LPD, 1, SYM>), dim3(n_bins), dim3(threads), lds, st, a); break;
+        case 2: hipLaunchKernelGGL((step_kernel<MASK, ACT, LPD, 2, SYM>), dim3(n_bins), dim3(threads), lds, st, a); break;
+        case 4: hipLaunchKernelGGL((step_kernel<MASK, ACT, LPD, 4, SYM>), dim3(n_bins), dim3(threads), lds, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -204,13 +245,18 @@ template <uint32_t MASK, int ACT>
 hipError_t launch_l(const StepArgs &a, const LaunchCfg &cfg, int n_bins, int threads, size_t lds,
                     hipStream_t st) {
     if (!(MASK & 4u)) {
-        // no neighbour sweep: one lane per drone, no unrolled loop to tune
-        return launch_u<MASK, ACT, 1>(a, 1, n_bins, threads, lds, st);
+        // no neighbour sweep: one lane per drone, no loop to tune
+        hipLaunchKernelGGL((step_kernel<MASK, ACT, 1, 1, false>), dim3(n_bins), dim3(threads), lds, st, a);
+        return hipGetLastError();
+    }
+    if (cfg.sym) {
+        if (cfg.lpd != 1) return hipErrorInvalidValue;
+        return launch_u<MASK, ACT, 1, true>(a, cfg.unroll, n_bins, threads, lds, st);
     }
     switch (cfg.lpd) {
-        case 1: return launch_u<MASK, ACT, 1>(a, cfg.unroll, n_bins, threads, lds, st);
-        case 2: return launch_u<MASK, ACT, 2>(a, cfg.unroll, n_bins, threads, lds, st);
-        case 4: return launch_u<MASK, ACT, 4>(a, cfg.unroll, n_bins, threads, lds, st);
+        case 1: return launch_u<MASK, ACT, 1, false>(a, cfg.unroll, n_bins, threads, lds, st);
+        case 2: return launch_u<MASK, ACT, 2, false>(a, cfg.unroll, n_bins, threads, lds, st);
+        case 4: return launch_u<MASK, ACT, 4, false>(a, cfg.unroll, n_bins, threads, lds, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -237,7 +283,8 @@ hipError_t launch_step(const StepArgs &a, uint32_t mask, int act, const LaunchCf
     if (n_bins <= 0 || a.n_steps <= 0) return hipSuccess;
     const int lpd = (mask & 4u) ? cfg.lpd : 1;
     const int threads = slots * lpd;
-    const size_t lds = (mask & 4u) ? sizeof(float4) * 2 * 2 * (size_t)slots : 0;
+    size_t lds = (mask & 4u) ? sizeof(float4) * 2 * 2 * (size_t)slots : 0;
+    if ((mask & 4u) && cfg.sym) lds += sizeof(float) * (size_t)slots * (size_t)a.tstride;
     if (act == 0) return launch_m<0>(a, mask, cfg, n_bins, threads, lds, stream);
     return launch_m<1>(a, mask, cfg, n_bins, threads, lds, stream);
 }

@@ -199,86 +199,100 @@ __device__ __forceinline__ float silu(float z) { return z * __builtin_amdgcn_rcp
 
 __device__ __forceinline__ bf16x8 ldw(const bf16 *p) { return *(const bf16x8 *)p; }
 
-// One hidden layer for the wave's 4 drone tiles: hout[ot][dt] = SiLU(W hin + b)
-// as bfloat16, K = 128 (4 chunks of 32), inputs in the permuted fragment order.
-__device__ __forceinline__ void hidden_layer(const bf16 *W, const float *b, const bf16x4 hin[8][4],
-                                             bf16x4 hout[8][4], int lane) {
+__device__ __forceinline__ f32x4 ldb(const float *p) { return *(const f32x4 *)p; }
+
+// Drone tiles (16 drones each) evaluated together by one pass of the network.
+constexpr int DT = 2;
+
+// One hidden layer for DT drone tiles: hout[ot][dt] = SiLU(W hin + b) as
+// bfloat16, K = 128 (4 chunks of 32), inputs in the permuted fragment order.
+__device__ __forceinline__ void hidden_layer(const bf16 *W, const float *b, const bf16x4 hin[8][DT],
+                                             bf16x4 hout[8][DT], int lane) {
     const int r = lane & 15, g = lane >> 4;
 #pragma unroll
     for (int ot = 0; ot < 8; ++ot) {
-        f32x4 acc[4];
-#pragma unroll
-        for (int dt = 0; dt < 4; ++dt) acc[dt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const f32x4 bias = ldb(b + 16 * ot + 4 * g);  // the accumulators start at the bias
+        f32x4 acc[DT];
 #pragma unroll
         for (int kc = 0; kc < 4; ++kc) {
             const bf16x8 a = ldw(W + (16 * ot + r) * MLP_H + 32 * kc + 8 * g);
 #pragma unroll
-            for (int dt = 0; dt < 4; ++dt) {
+            for (int dt = 0; dt < DT; ++dt) {
                 const bf16x8 bv = __builtin_shufflevector(hin[2 * kc][dt], hin[2 * kc + 1][dt], 0, 1, 2, 3, 4, 5, 6, 7);
-                acc[dt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[dt], 0, 0, 0);
+                acc[dt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, kc == 0 ? bias : acc[dt], 0, 0, 0);
             }
         }
 #pragma unroll
-        for (int dt = 0; dt < 4; ++dt) {
+        for (int dt = 0; dt < DT; ++dt) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) hout[ot][dt][t] = (bf16)silu(acc[dt][t] + b[16 * ot + 4 * g + t]);
+            for (int t = 0; t < 4; ++t) hout[ot][dt][t] = (bf16)silu(acc[dt][t]);
         }
     }
 }
 
-// The network on the 64 drones of one wave: standardised bfloat16 inputs in
-// feat (row per drone), standardised outputs to out (row per drone, 6 used).
+// The network on the 64 drones of one wave, DT tiles of 16 drones per pass:
+// standardised bfloat16 inputs in feat (row per drone), standardised outputs
+// to out (row per drone, 6 used).  Passes reuse the activation registers;
+// the weights (L2-resident) are read once per pass.
 __device__ __forceinline__ void mlp_wave(const bf16 *feat, float *out, const bf16 *W, const float *b, int lane) {
     const int r = lane & 15, g = lane >> 4;
-    bf16x4 h1[8][4], h2[8][4];
-    // layer 1: K = 64, B fragments straight from the staged rows
-    {
-        bf16x8 x[2][4];
+#pragma unroll 1
+    for (int pass = 0; pass < 4 / DT; ++pass) {
+        const int t0 = pass * DT;
+        // an empty asm operand makes the weight pointers opaque per pass, so the
+        // (loop-invariant) weight loads are not hoisted out of the pass loop,
+        // which would hold all 84 KB of weights in registers
+        const bf16 *Wv = W;
+        const float *bv_ = b;
+        asm volatile("" : "+s"(Wv), "+s"(bv_));
+        bf16x4 h1[8][DT], h2[8][DT];
+        // layer 1: K = 64, B fragments straight from the staged rows
+        {
+            bf16x8 x[2][DT];
 #pragma unroll
-        for (int kc = 0; kc < 2; ++kc)
+            for (int kc = 0; kc < 2; ++kc)
 #pragma unroll
-            for (int dt = 0; dt < 4; ++dt)
-                x[kc][dt] = *(const bf16x8 *)(feat + (16 * dt + r) * FEAT_STRIDE + 32 * kc + 8 * g);
+                for (int dt = 0; dt < DT; ++dt)
+                    x[kc][dt] = *(const bf16x8 *)(feat + (16 * (t0 + dt) + r) * FEAT_STRIDE + 32 * kc + 8 * g);
 #pragma unroll
-        for (int ot = 0; ot < 8; ++ot) {
-            f32x4 acc[4];
+            for (int ot = 0; ot < 8; ++ot) {
+                const f32x4 bias = ldb(bv_ + BOFF1 + 16 * ot + 4 * g);
+                f32x4 acc[DT];
 #pragma unroll
-            for (int dt = 0; dt < 4; ++dt) acc[dt] = f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int kc = 0; kc < 2; ++kc) {
+                    const bf16x8 a = ldw(Wv + WOFF1 + (16 * ot + r) * MLP_IN + 32 * kc + 8 * g);
 #pragma unroll
-            for (int kc = 0; kc < 2; ++kc) {
-                const bf16x8 a = ldw(W + WOFF1 + (16 * ot + r) * MLP_IN + 32 * kc + 8 * g);
+                    for (int dt = 0; dt < DT; ++dt)
+                        acc[dt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, x[kc][dt], kc == 0 ? bias : acc[dt], 0, 0, 0);
+                }
 #pragma unroll
-                for (int dt = 0; dt < 4; ++dt)
-                    acc[dt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, x[kc][dt], acc[dt], 0, 0, 0);
+                for (int dt = 0; dt < DT; ++dt)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) h1[ot][dt][t] = (bf16)silu(acc[dt][t]);
             }
-#pragma unroll
-            for (int dt = 0; dt < 4; ++dt)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) h1[ot][dt][t] = (bf16)silu(acc[dt][t] + b[BOFF1 + 16 * ot + 4 * g + t]);
         }
+        hidden_layer(Wv + WOFF2, bv_ + BOFF2, h1, h2, lane);
+        hidden_layer(Wv + WOFF3, bv_ + BOFF3, h2, h1, lane);
+        // output layer: one 16-row tile (rows 0..5 used; bias rows 6..15 are 0)
+        const f32x4 bias = ldb(bv_ + BOFF4 + 4 * g);
+        f32x4 acc[DT];
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+            const bf16x8 a = ldw(Wv + WOFF4 + r * MLP_H + 32 * kc + 8 * g);
+#pragma unroll
+            for (int dt = 0; dt < DT; ++dt) {
+                const bf16x8 bv = __builtin_shufflevector(h1[2 * kc][dt], h1[2 * kc + 1][dt], 0, 1, 2, 3, 4, 5, 6, 7);
+                acc[dt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, kc == 0 ? bias : acc[dt], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int dt = 0; dt < DT; ++dt)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int o = 4 * g + t;
+                if (o < MLP_OUT) out[(16 * (t0 + dt) + r) * OUT_STRIDE + o] = acc[dt][t];
+            }
     }
-    hidden_layer(W + WOFF2, b + BOFF2, h1, h2, lane);
-    hidden_layer(W + WOFF3, b + BOFF3, h2, h1, lane);
-    // output layer: one 16-row tile (rows 0..5 used)
-    f32x4 acc[4];
-#pragma unroll
-    for (int dt = 0; dt < 4; ++dt) acc[dt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kc = 0; kc < 4; ++kc) {
-        const bf16x8 a = ldw(W + WOFF4 + r * MLP_H + 32 * kc + 8 * g);
-#pragma unroll
-        for (int dt = 0; dt < 4; ++dt) {
-            const bf16x8 bv = __builtin_shufflevector(h1[2 * kc][dt], h1[2 * kc + 1][dt], 0, 1, 2, 3, 4, 5, 6, 7);
-            acc[dt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[dt], 0, 0, 0);
-        }
-    }
-#pragma unroll
-    for (int dt = 0; dt < 4; ++dt)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int o = 4 * g + t;
-            if (o < MLP_OUT) out[(16 * dt + r) * OUT_STRIDE + o] = acc[dt][t] + b[BOFF4 + o];
-        }
 }
 
 __device__ __forceinline__ double wave_sum(double v) {

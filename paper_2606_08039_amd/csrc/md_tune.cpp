@@ -1,0 +1,346 @@
+// md_tune.cpp -- launch-configuration autotuner and captured rollouts.
+//
+// Autotuner: for the bound layout and the context's mask, time every valid
+// launch configuration (lanes per drone for the neighbour sweep, bin size in
+// waves, neighbour-loop unroll, all-pairs or pair-symmetric sweep) on scratch
+// copies of the caller's state, keep the fastest, and remember it in a small
+// JSON cache keyed by the layout signature.  Every configuration computes the
+// same physics; the pair-symmetric and the one-lane all-pairs sweeps are
+// bitwise identical, the multi-lane sweeps differ only in summation order.
+//
+// Graphs: n_launches consecutive md_step launches of steps_per_launch steps
+// each, captured once on a stream and replayed with hipGraphLaunch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "md_ctx.h"
+
+namespace md {
+
+static std::string signature(const md_ctx *ctx) {
+    // layout shape: drones, environments, largest environment and a hash of
+    // the environment-size sequence; plus mask and action type
+    uint64_t h = 1469598103934665603ull;
+    for (size_t e = 0; e + 1 < ctx->off.size(); ++e) {
+        h ^= (uint64_t)(ctx->off[e + 1] - ctx->off[e]);
+        h *= 1099511628211ull;
+    }
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "n%d_e%d_m%d_h%016llx_mask%u_act%d", ctx->n_drones, ctx->n_envs, ctx->max_m,
+                  (unsigned long long)h, ctx->mask, ctx->act);
+    return buf;
+}
+
+static bool cfg_valid(const md_ctx *ctx, const LaunchCfg &c) {
+    const int slots = 64 * c.waves / c.lpd;
+    if (slots < ctx->max_m || slots < 1) return false;
+    if (c.sym && c.lpd != 1) return false;
+    if (c.sym) {
+        const size_t lds = 16 * 4 * (size_t)slots + 4 * (size_t)slots * (size_t)((ctx->max_m + 1) | 1);
+        if (lds > 64 * 1024) return false;
+    }
+    if (64 * c.waves > 1024) return false;
+    return true;
+}
+
+static std::vector<LaunchCfg> candidates(const md_ctx *ctx) {
+    std::vector<LaunchCfg> out;
+    if (!(ctx->mask & MD_AERO_DW)) {
+        for (int w : {1, 2, 4})
+            if (64 * w >= ctx->max_m) out.push_back(LaunchCfg{1, 1, w, 0});
+        if (out.empty()) out.push_back(default_cfg(ctx));
+        return out;
+    }
+    for (int sym : {0, 1})
+        for (int lpd : {1, 2, 4})
+            for (int w : {1, 2, 4, 8, 16})
+                for (int u : {1, 2, 4}) {
+                    LaunchCfg c{lpd, u, w, sym};
+                    if (cfg_valid(ctx, c)) out.push_back(c);
+                }
+    return out;
+}
+
+static std::string cache_path(const char *path) {
+    if (path && *path) return path;
+    const char *env = std::getenv("MD_AUTOTUNE_CACHE");
+    if (env && *env) return env;
+    return "";
+}
+
+// Cache format: one JSON object per line inside a JSON array:
+// [{"sig": "...", "lpd": 1, "unroll": 4, "waves": 1, "sym": 1, "us": 123.4}, ...]
+static bool cache_lookup(const std::string &path, const std::string &sig, LaunchCfg &out) {
+    if (path.empty()) return false;
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line;
+    while (std::getline(f, line)) {
+        const std::string key = "\"sig\": \"" + sig + "\"";
+        if (line.find(key) == std::string::npos) continue;
+        int lpd = 0, unroll = 0, waves = 0, sym = 0;
+        auto grab = [&](const char *name, int &v) {
+            const std::string k = std::string("\"") + name + "\": ";
+            const size_t p = line.find(k);
+            if (p == std::string::npos) return false;
+            v = std::atoi(line.c_str() + p + k.size());
+            return true;
+        };
+        if (grab("lpd", lpd) && grab("unroll", unroll) && grab("waves", waves) && grab("sym", sym)) {
+            out = LaunchCfg{lpd, unroll, waves, sym};
+            return true;
+        }
+    }
+    return false;
+}
+
+static void cache_store(const std::string &path, const std::string &sig, const LaunchCfg &c, double us) {
+    if (path.empty()) return;
+    std::vector<std::string> keep;
+    {
+        std::ifstream f(path);
+        std::string line;
+        while (f && std::getline(f, line)) {
+            if (line.find("\"sig\"") == std::string::npos) continue;
+            if (line.find("\"sig\": \"" + sig + "\"") != std::string::npos) continue;
+            while (!line.empty() && (line.back() == ',' || line.back() == ' ')) line.pop_back();
+            keep.push_back(line);
+        }
+    }
+    char buf[400];
+    std::snprintf(buf, sizeof buf, "{\"sig\": \"%s\", \"lpd\": %d, \"unroll\": %d, \"waves\": %d, \"sym\": %d, \"us\": %.3f}",
+                  sig.c_str(), c.lpd, c.unroll, c.waves, c.sym, us);
+    keep.push_back(buf);
+    const std::string tmp = path + ".tmp";
+    {
+        std::ofstream f(tmp);
+        f << "[\n";
+        for (size_t i = 0; i < keep.size(); ++i) f << keep[i] << (i + 1 < keep.size() ? ",\n" : "\n");
+        f << "]\n";
+    }
+    std::rename(tmp.c_str(), path.c_str());
+}
+
+md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step, int n_steps,
+                   int64_t step0, hipStream_t st, const char *path, int force) {
+    const std::string sig = signature(ctx);
+    const std::string cp = cache_path(path);
+    LaunchCfg cached;
+    if (!force && cache_lookup(cp, sig, cached) && cfg_valid(ctx, cached)) {
+        ctx->cfg = cached;
+        ctx->tuned = true;
+        return MD_OK;
+    }
+    const size_t N = (size_t)ctx->n_drones;
+    if (N == 0 || n_steps <= 0) {
+        ctx->tuned = true;
+        return MD_OK;
+    }
+    // scratch copies of the state: the caller's state is never advanced
+    const size_t rows = 3 + 4 + 3 + 3 + 6 + 4;
+    float *scratch = nullptr, *work = nullptr;
+    hipError_t e = hipMalloc(&scratch, sizeof(float) * rows * N);
+    if (e == hipSuccess) e = hipMalloc(&work, sizeof(float) * rows * N);
+    if (e != hipSuccess) {
+        (void)hipFree(scratch);
+        ctx->err = hip_msg("autotune scratch", e);
+        return MD_E_OOM;
+    }
+    const float *src[6] = {s->p, s->q, s->v, s->w, s->pid_int, s->rpm};
+    const int nr[6] = {3, 4, 3, 3, 6, 4};
+    size_t o = 0;
+    md_state ws;
+    float **dst[6] = {&ws.p, &ws.q, &ws.v, &ws.w, &ws.pid_int, &ws.rpm};
+    for (int k = 0; k < 6; ++k) {
+        if (src[k])
+            e = hipMemcpyAsync(scratch + o, src[k], sizeof(float) * nr[k] * N, hipMemcpyDeviceToDevice, st);
+        else
+            e = hipMemsetAsync(scratch + o, 0, sizeof(float) * nr[k] * N, st);
+        *dst[k] = work + o;
+        o += nr[k] * N;
+        if (e != hipSuccess) break;
+    }
+    hipEvent_t a = nullptr, b = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    double best_us = 1e300;
+    LaunchCfg best = ctx->cfg;
+    md_status rc = MD_OK;
+    for (const LaunchCfg &c : candidates(ctx)) {
+        if (e != hipSuccess) break;
+        float t_best = 1e30f;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+            e = hipMemcpyAsync(work, scratch, sizeof(float) * rows * N, hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) break;
+            e = hipEventRecord(a, st);
+            rc = launch(ctx, &ws, d_action, action_per_step, nullptr, 0, n_steps, step0, st, c);
+            if (rc != MD_OK) break;
+            e = hipEventRecord(b, st);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (rep > 0) t_best = std::min(t_best, ms);  // first repetition warms up
+        }
+        if (rc != MD_OK) break;
+        if (e == hipSuccess && t_best * 1000.0 < best_us) {
+            best_us = t_best * 1000.0;
+            best = c;
+        }
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    (void)hipFree(scratch);
+    (void)hipFree(work);
+    if (rc != MD_OK) return rc;
+    if (e != hipSuccess) {
+        ctx->err = hip_msg("autotune", e);
+        return MD_E_HIP;
+    }
+    ctx->cfg = best;
+    ctx->tuned = true;
+    cache_store(cp, sig, best, best_us);
+    return MD_OK;
+}
+
+}  // namespace md
+
+struct md_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    md_ctx *ctx = nullptr;
+};
+
+extern "C" {
+
+md_status md_autotune(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step, int n_steps,
+                      int64_t step0, void *stream, const char *cache_path, int force) {
+    if (!ctx) return MD_E_INVALID_ARG;
+    if (!ctx->has_layout) {
+        ctx->err = "md_autotune: no layout bound";
+        return MD_E_LAYOUT;
+    }
+    if (!s || !d_action || n_steps < 0 || step0 < 0) {
+        ctx->err = "md_autotune: null state or action, or negative n_steps / step0";
+        return MD_E_INVALID_ARG;
+    }
+    if (ctx->mask & MD_AERO_SURROGATE) {
+        ctx->tuned = true;  // the surrogate kernel has one configuration
+        return MD_OK;
+    }
+    return md::autotune(ctx, s, d_action, action_per_step, n_steps, step0, (hipStream_t)stream, cache_path, force);
+}
+
+md_status md_get_launch_config(const md_ctx *ctx, md_launch_config *out) {
+    if (!ctx || !out) return MD_E_INVALID_ARG;
+    out->lanes_per_drone = ctx->cfg.lpd;
+    out->unroll = ctx->cfg.unroll;
+    out->waves_per_group = ctx->cfg.waves;
+    out->pair_symmetric = ctx->cfg.sym;
+    return MD_OK;
+}
+
+md_status md_set_launch_config(md_ctx *ctx, md_launch_config *cfg) {
+    if (!ctx || !cfg) return MD_E_INVALID_ARG;
+    if (!ctx->has_layout) {
+        ctx->err = "md_set_launch_config: bind a layout first";
+        return MD_E_LAYOUT;
+    }
+    md::LaunchCfg c{cfg->lanes_per_drone, cfg->unroll, cfg->waves_per_group, cfg->pair_symmetric ? 1 : 0};
+    const bool lpd_ok = c.lpd == 1 || c.lpd == 2 || c.lpd == 4;
+    const bool u_ok = c.unroll == 1 || c.unroll == 2 || c.unroll == 4;
+    const bool w_ok = c.waves == 1 || c.waves == 2 || c.waves == 4 || c.waves == 8 || c.waves == 16;
+    if (!lpd_ok || !u_ok || !w_ok || !md::cfg_valid(ctx, c)) {
+        ctx->err = "md_set_launch_config: invalid configuration for this layout";
+        return MD_E_INVALID_ARG;
+    }
+    ctx->cfg = c;
+    ctx->tuned = true;
+    return MD_OK;
+}
+
+md_status md_rollout_graph_create(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
+                                  float *d_obs, int n_obs_slots, int steps_per_launch, int n_launches,
+                                  int64_t step0, void *stream, md_graph **out) {
+    if (!ctx || !out) return MD_E_INVALID_ARG;
+    *out = nullptr;
+    if (steps_per_launch < 1 || n_launches < 1 || step0 < 0) {
+        ctx->err = "md_rollout_graph_create: steps_per_launch and n_launches must be >= 1";
+        return MD_E_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    // bin tables are uploaded synchronously on first use: do it before capture
+    md_status prc = md::prepare_launch(ctx);
+    if (prc != MD_OK) return prc;
+    hipStream_t cap = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        ctx->err = md::hip_msg("graph capture stream", e);
+        return MD_E_HIP;
+    }
+    md_graph *g = new (std::nothrow) md_graph();
+    if (!g) {
+        (void)hipStreamDestroy(cap);
+        return MD_E_OOM;
+    }
+    g->ctx = ctx;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    md_status rc = MD_OK;
+    if (e == hipSuccess) {
+        const long long N = ctx->n_drones;
+        for (int l = 0; l < n_launches && rc == MD_OK; ++l) {
+            const float *act = d_action + (action_per_step ? (long long)l * steps_per_launch * 4 * N : 0);
+            float *obs = d_obs;
+            int slots = n_obs_slots;
+            if (d_obs && n_obs_slots >= steps_per_launch * n_launches) {
+                obs = d_obs + (long long)l * steps_per_launch * 20 * N;
+                slots = steps_per_launch;
+            }
+            rc = md_step(ctx, s, act, action_per_step, obs, slots, steps_per_launch,
+                         step0 + (int64_t)l * steps_per_launch, cap);
+        }
+        hipError_t e2 = hipStreamEndCapture(cap, &g->graph);
+        if (e == hipSuccess) e = e2;
+    }
+    if (rc == MD_OK && e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cap);
+    (void)st;
+    if (rc != MD_OK || e != hipSuccess) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        if (rc == MD_OK) {
+            ctx->err = md::hip_msg("rollout graph capture", e);
+            rc = MD_E_HIP;
+        }
+        return rc;
+    }
+    *out = g;
+    return MD_OK;
+}
+
+md_status md_graph_launch(md_graph *g, void *stream) {
+    if (!g || !g->exec) return MD_E_INVALID_ARG;
+    hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        g->ctx->err = md::hip_msg("hipGraphLaunch", e);
+        return MD_E_HIP;
+    }
+    return MD_OK;
+}
+
+void md_graph_destroy(md_graph *g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+}  // extern "C"

@@ -324,3 +324,53 @@ def md_judge_stats(ctx):
 
 def md_judge_reset(ctx):
     check(lib().md_judge_reset(ctx), ctx)
+
+
+# ------------------------------------------------------------------ launch configuration, graphs
+
+class md_launch_config(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int) for n in ("lanes_per_drone", "unroll", "waves_per_group",
+                                            "pair_symmetric")]
+
+
+def md_get_launch_config(ctx):
+    c = md_launch_config()
+    check(lib().md_get_launch_config(ctx, ctypes.byref(c)), ctx)
+    return {k: getattr(c, k) for k, _ in md_launch_config._fields_}
+
+
+def md_set_launch_config(ctx, lanes_per_drone=1, unroll=4, waves_per_group=1, pair_symmetric=0):
+    c = md_launch_config(lanes_per_drone, unroll, waves_per_group, pair_symmetric)
+    check(lib().md_set_launch_config(ctx, ctypes.byref(c)), ctx)
+
+
+def md_autotune(ctx, state, action, action_per_step, n_steps=20, step0=0, stream=None,
+                cache_path=None, force=False):
+    ms = state.as_md_state() if hasattr(state, "as_md_state") else state
+    cp = cache_path.encode() if cache_path is not None else None
+    check(lib().md_autotune(ctx, ctypes.byref(ms), _VP(action.data_ptr()), int(bool(action_per_step)),
+                            int(n_steps), int(step0), _stream_ptr(stream), cp, int(bool(force))), ctx)
+    return md_get_launch_config(ctx)
+
+
+def md_rollout_graph_create(ctx, state, action, action_per_step, obs=None, n_obs_slots=0,
+                            steps_per_launch=1, n_launches=1, step0=0, stream=None):
+    ms = state.as_md_state() if hasattr(state, "as_md_state") else state
+    g = _VP()
+    check(lib().md_rollout_graph_create(ctx, ctypes.byref(ms), _VP(action.data_ptr()),
+                                        int(bool(action_per_step)),
+                                        _VP(obs.data_ptr()) if obs is not None else None,
+                                        int(n_obs_slots), int(steps_per_launch), int(n_launches),
+                                        int(step0), _stream_ptr(stream), ctypes.byref(g)), ctx)
+    g._md_state = ms  # the captured kernels hold these device pointers
+    return g
+
+
+def md_graph_launch(g, stream=None):
+    st = lib().md_graph_launch(g, _stream_ptr(stream))
+    if st != MD_OK:
+        raise MdError(st, "md_graph_launch")
+
+
+def md_graph_destroy(g):
+    lib().md_graph_destroy(g)

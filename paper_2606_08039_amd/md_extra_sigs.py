@@ -26,4 +26,12 @@ def signatures():
         "md_datagen": (_I32, [_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, _VP]),
         "md_judge_stats": (_I32, [_VP, _VP]),
         "md_judge_reset": (_I32, [_VP]),
+        "md_get_launch_config": (_I32, [_VP, _VP]),
+        "md_set_launch_config": (_I32, [_VP, _VP]),
+        "md_autotune": (_I32, [_VP, _VP, _VP, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _VP,
+                               ctypes.c_char_p, ctypes.c_int]),
+        "md_rollout_graph_create": (_I32, [_VP, _VP, _VP, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_int64, _VP, ctypes.POINTER(_VP)]),
+        "md_graph_launch": (_I32, [_VP, _VP]),
+        "md_graph_destroy": (None, [_VP]),
     }
