@@ -95,6 +95,8 @@ def _load():
                              ctypes.c_int, _D, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                              ctypes.c_int]
     lib.orc_step.restype = ctypes.c_int
+    lib.orc_step_rk4.argtypes = lib.orc_step.argtypes
+    lib.orc_step_rk4.restype = ctypes.c_int
     lib.orc_knn.argtypes = [ctypes.c_int, _I32, ctypes.c_int, _D, ctypes.c_int, _I32]
     lib.orc_features.argtypes = [P, ctypes.c_int, _I32, ctypes.c_int, ctypes.POINTER(_CState),
                                  _I32, ctypes.c_int, ctypes.c_int, _D]
@@ -281,9 +283,10 @@ def _cstate(s):
 
 
 def step(P, dt, aero_mask, act_type, ctrl_decim, env_offsets, state, action,
-         action_per_step, n_steps, step0=0, n_obs_slots=0, n_threads=0):
+         action_per_step, n_steps, step0=0, n_obs_slots=0, n_threads=0, integrator="euler"):
     """Advance ``state`` (dict of [c][N] float64 arrays, updated in place) by
-    n_steps; returns the observation array [slots][20][N] or None."""
+    n_steps with the semi-implicit Euler step or classic RK4; returns the
+    observation array [slots][20][N] or None."""
     off = np.ascontiguousarray(np.asarray(env_offsets, dtype=np.int32))
     n_envs = len(off) - 1
     n = int(off[-1])
@@ -292,10 +295,11 @@ def step(P, dt, aero_mask, act_type, ctrl_decim, env_offsets, state, action,
     assert act.size == need, (act.size, need)
     obs = np.zeros((n_obs_slots, 20, n)) if n_obs_slots > 0 else None
     cs = _cstate(state)
-    rc = _load().orc_step(ctypes.byref(P), float(dt), int(aero_mask), int(act_type),
-                          int(ctrl_decim), n_envs, _ip(off), n, ctypes.byref(cs), _dp(act),
-                          int(bool(action_per_step)), _dp(obs) if obs is not None else None,
-                          int(n_obs_slots), int(n_steps), int(step0), int(n_threads))
+    fn = _load().orc_step if integrator == "euler" else _load().orc_step_rk4
+    rc = fn(ctypes.byref(P), float(dt), int(aero_mask), int(act_type),
+            int(ctrl_decim), n_envs, _ip(off), n, ctypes.byref(cs), _dp(act),
+            int(bool(action_per_step)), _dp(obs) if obs is not None else None,
+            int(n_obs_slots), int(n_steps), int(step0), int(n_threads))
     if rc != 0:
         raise ValueError("orc_step failed (%d)" % rc)
     return obs

@@ -543,6 +543,178 @@ int orc_step(const orc_params *P, double dt, uint32_t aero_mask, int act_type, i
 }
 
 /* ------------------------------------------------------------------------ */
+/* Classic Runge-Kutta variant of the step.                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Time derivative of one drone's rigid-body state x = (p, v, q, w) with the
+ * rotor thrust T and body torque tau held over the step (zero-order hold of
+ * the rotor speeds n): p' = v, v' = F_w / m, q' = q (x) [0, w] / 2,
+ * w' = J^-1 (tau - w x J w), F_w = R (0,0,T) - m g z_hat plus the selected
+ * aerodynamic terms at this state.  p_all holds the same stage's positions
+ * of every drone (for the downwash of Eq. (6)).  Reading: R is taken from
+ * the normalised stage quaternion. */
+static void rk_deriv(const orc_params *P, const orc_derived *D, uint32_t mask, int N, int i, int e0,
+                     int e1, const double *p_all, const double x[13], const double n[4], double T,
+                     const double tau[3], double k[13])
+{
+    const double *p = x, *v = x + 3, *qr = x + 6, *w = x + 10;
+    const double nq = sqrt(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
+    const double q[4] = {qr[0] / nq, qr[1] / nq, qr[2] / nq, qr[3] / nq};
+    double R[9];
+    orc_quat_to_rot(q, R);
+    double Fw[3] = {R[2] * T, R[5] * T, R[8] * T - P->m * P->g};
+    if (mask & ORC_AERO_GND) Fw[2] += orc_ground_effect(P, D, n, p[2], q);
+    if (mask & ORC_AERO_DRAG) {
+        double Fd[3];
+        orc_drag(P, n, q, v, Fd);
+        for (int c = 0; c < 3; ++c) Fw[c] += Fd[c];
+    }
+    if (mask & ORC_AERO_DW) {
+        for (int j = e0; j < e1; ++j) {
+            if (j == i) continue;
+            const double pj[3] = {p_all[0 * N + j], p_all[1 * N + j], p_all[2 * N + j]};
+            Fw[2] += orc_downwash_pair(P, p, pj);
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        k[c] = v[c];
+        k[3 + c] = Fw[c] / P->m;
+    }
+    const double wq[4] = {0.0, w[0], w[1], w[2]};
+    double qd[4];
+    orc_quat_mul(qr, wq, qd);
+    for (int c = 0; c < 4; ++c) k[6 + c] = 0.5 * qd[c];
+    const double J[3] = {P->Ixx, P->Iyy, P->Izz};
+    const double Jw[3] = {J[0] * w[0], J[1] * w[1], J[2] * w[2]};
+    const double cr[3] = {w[1] * Jw[2] - w[2] * Jw[1], w[2] * Jw[0] - w[0] * Jw[2],
+                          w[0] * Jw[1] - w[1] * Jw[0]};
+    for (int c = 0; c < 3; ++c) k[10 + c] = (tau[c] - cr[c]) / J[c];
+}
+
+/* orc_step with the classic fourth-order Runge-Kutta integrator (the MuJoCo
+ * modes' integrator, Table "Physics modes") in place of the semi-implicit
+ * Euler step: rotor speeds, controllers and observations as in orc_step; per
+ * step x_{k+1} = x + dt/6 (k1 + 2 k2 + 2 k3 + k4) with stages at x,
+ * x + dt/2 k1, x + dt/2 k2, x + dt k3 evaluated synchronously for all drones
+ * (the downwash of each stage uses every drone's stage position); the
+ * quaternion is renormalised after the step. */
+int orc_step_rk4(const orc_params *P, double dt, uint32_t aero_mask, int act_type, int ctrl_decim,
+                 int n_envs, const int32_t *env_offsets, int n_drones, orc_state *s,
+                 const double *action, int action_per_step, double *obs, int n_obs_slots,
+                 int n_steps, int64_t step0, int n_threads)
+{
+    if (n_drones < 0 || n_envs < 0 || n_steps < 0 || ctrl_decim < 1) return -1;
+    if (env_offsets[0] != 0 || env_offsets[n_envs] != n_drones) return -1;
+    if (aero_mask & ORC_AERO_SURROGATE) return -1;
+    if (act_type < ORC_ACT_RPM || act_type > ORC_ACT_DSL || (act_type == ORC_ACT_DSL && !s->ctl)) return -1;
+    orc_derived D;
+    orc_derive(P, &D);
+    const int N = n_drones;
+    const size_t n1 = (size_t)(N > 0 ? N : 1);
+    double *X0 = (double *)malloc(sizeof(double) * 13 * n1);   /* state at the step start */
+    double *Xs = (double *)malloc(sizeof(double) * 13 * n1);   /* current stage state */
+    double *Ks = (double *)malloc(sizeof(double) * 13 * n1);   /* sum k1 + 2k2 + 2k3 + k4 */
+    double *Kc = (double *)malloc(sizeof(double) * 13 * n1);   /* current stage derivative */
+    double *ps = (double *)malloc(sizeof(double) * 3 * n1);    /* stage positions [3][N] */
+    double *nn = (double *)malloc(sizeof(double) * 4 * n1);
+    double *TT = (double *)malloc(sizeof(double) * 4 * n1);    /* T, tau per drone */
+    if (!X0 || !Xs || !Ks || !Kc || !ps || !nn || !TT) {
+        free(X0); free(Xs); free(Ks); free(Kc); free(ps); free(nn); free(TT);
+        return -2;
+    }
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    static const double stage_w[4] = {1.0, 2.0, 2.0, 1.0};
+    for (int k = 0; k < n_steps; ++k) {
+        const int rows = orc_action_rows(act_type);
+        const double *act = action + (action_per_step ? (size_t)k * rows * N : 0);
+        const int do_pid = (act_type != ORC_ACT_RPM) && (((step0 + k) % ctrl_decim) == 0);
+        /* rotor speeds, motor model; x0 */
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < N; ++i) {
+            double p[3], q[4], v[3], w[3], n[4];
+            for (int c = 0; c < 3; ++c) {
+                p[c] = s->p[c * N + i];
+                v[c] = s->v[c * N + i];
+                w[c] = s->w[c * N + i];
+            }
+            for (int c = 0; c < 4; ++c) q[c] = s->q[c * N + i];
+            if (act_type == ORC_ACT_RPM) {
+                for (int c = 0; c < 4; ++c) n[c] = clampd(act[c * N + i], 0.0, D.max_rpm);
+            } else if (do_pid) {
+                controller(P, &D, act_type, dt * ctrl_decim, N, i, act, p, q, v, w, s, n);
+            } else {
+                for (int c = 0; c < 4; ++c) n[c] = s->rpm[c * N + i];
+            }
+            for (int c = 0; c < 4; ++c) {
+                s->rpm[c * N + i] = n[c];
+                nn[(size_t)i * 4 + c] = n[c];
+            }
+            double F[4], T, tau[3];
+            orc_motor(P, n, F, &T, tau);
+            TT[(size_t)i * 4 + 0] = T;
+            for (int c = 0; c < 3; ++c) TT[(size_t)i * 4 + 1 + c] = tau[c];
+            double *x = X0 + (size_t)i * 13;
+            for (int c = 0; c < 3; ++c) {
+                x[c] = p[c];
+                x[3 + c] = v[c];
+                x[10 + c] = w[c];
+            }
+            for (int c = 0; c < 4; ++c) x[6 + c] = q[c];
+            for (int c = 0; c < 13; ++c) {
+                Xs[(size_t)i * 13 + c] = x[c];
+                Ks[(size_t)i * 13 + c] = 0.0;
+            }
+        }
+        for (int st = 0; st < 4; ++st) {
+            for (int i = 0; i < N; ++i)
+                for (int c = 0; c < 3; ++c) ps[c * N + i] = Xs[(size_t)i * 13 + c];
+#pragma omp parallel for schedule(dynamic, 16)
+            for (int e = 0; e < n_envs; ++e)
+                for (int i = env_offsets[e]; i < env_offsets[e + 1]; ++i)
+                    rk_deriv(P, &D, aero_mask, N, i, env_offsets[e], env_offsets[e + 1], ps,
+                             Xs + (size_t)i * 13, nn + (size_t)i * 4, TT[(size_t)i * 4],
+                             TT + (size_t)i * 4 + 1, Kc + (size_t)i * 13);
+            const double h = (st < 2) ? 0.5 * dt : dt;
+#pragma omp parallel for schedule(static)
+            for (int i = 0; i < N; ++i)
+                for (int c = 0; c < 13; ++c) {
+                    Ks[(size_t)i * 13 + c] += stage_w[st] * Kc[(size_t)i * 13 + c];
+                    if (st < 3) Xs[(size_t)i * 13 + c] = X0[(size_t)i * 13 + c] + h * Kc[(size_t)i * 13 + c];
+                }
+        }
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < N; ++i) {
+            double x[13];
+            for (int c = 0; c < 13; ++c) x[c] = X0[(size_t)i * 13 + c] + dt / 6.0 * Ks[(size_t)i * 13 + c];
+            const double nq = sqrt(x[6] * x[6] + x[7] * x[7] + x[8] * x[8] + x[9] * x[9]);
+            for (int c = 0; c < 4; ++c) x[6 + c] /= nq;
+            for (int c = 0; c < 3; ++c) {
+                s->p[c * N + i] = x[c];
+                s->v[c * N + i] = x[3 + c];
+                s->w[c * N + i] = x[10 + c];
+            }
+            for (int c = 0; c < 4; ++c) s->q[c * N + i] = x[6 + c];
+            if (obs && n_obs_slots > 0) {
+                double *o = obs + (size_t)(k % n_obs_slots) * 20 * N;
+                double rpy[3];
+                orc_euler_zyx(x + 6, rpy);
+                const double *n = nn + (size_t)i * 4;
+                const double row[20] = {x[0], x[1], x[2], x[6], x[7], x[8], x[9],
+                                        rpy[0], rpy[1], rpy[2], x[3], x[4], x[5],
+                                        x[10], x[11], x[12], n[0], n[1], n[2], n[3]};
+                for (int c = 0; c < 20; ++c) o[(size_t)c * N + i] = row[c];
+            }
+        }
+    }
+    free(X0); free(Xs); free(Ks); free(Kc); free(ps); free(nn); free(TT);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Surrogate support: neighbours, features, residual targets, MLP, Adam.     */
 /* ------------------------------------------------------------------------ */
 

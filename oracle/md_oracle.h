@@ -93,6 +93,11 @@ int orc_step(const orc_params *P, double dt, uint32_t aero_mask, int act_type, i
              const double *action, int action_per_step, double *obs, int n_obs_slots,
              int n_steps, int64_t step0, int n_threads);
 
+int orc_step_rk4(const orc_params *P, double dt, uint32_t aero_mask, int act_type, int ctrl_decim,
+                 int n_envs, const int32_t *env_offsets, int n_drones, orc_state *s,
+                 const double *action, int action_per_step, double *obs, int n_obs_slots,
+                 int n_steps, int64_t step0, int n_threads);
+
 /* ---- surrogate support ------------------------------------------------ */
 int orc_knn(int n_envs, const int32_t *env_offsets, int n_drones, const double *p, int k,
             int32_t *nbr);
