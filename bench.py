@@ -129,7 +129,7 @@ def cpu_baseline(w, with_obs, seconds_target=12.0):
         act = sub["action"][:steps] if w["action_per_step"] else sub["action"]
         n = int(sub["env_offsets"][-1])
         t0 = time.perf_counter()
-        orc.step(P, w["dt"], w["aero_mask"], orc.ACT_RPM if w["act_type"] == "rpm" else orc.ACT_PID,
+        orc.step(P, w["dt"], w["aero_mask"], {"rpm": 0, "pid": 1}[w["act_type"]],
                  w["ctrl_decim"], sub["env_offsets"], s, act.astype(np.float64),
                  w["action_per_step"], steps, n_obs_slots=1 if with_obs else 0,
                  n_threads=threads)
@@ -161,7 +161,7 @@ def surrogate_leg(args, w, p, with_obs):
     flat, norm, meta = surrogate.load(path)
     n = int(w["env_offsets"][-1])
     K = w["n_steps"]
-    act = md.MD_ACT_RPM if w["act_type"] == "rpm" else md.MD_ACT_PID
+    act = {"rpm": md.MD_ACT_RPM, "pid": md.MD_ACT_PID}[w["act_type"]]
     ctx = md.md_create(p, w["dt"], md.MD_AERO_SURROGATE, act, w["ctrl_decim"])
     try:
         md.md_bind_layout(ctx, w["env_offsets"])
@@ -231,7 +231,7 @@ def main():
     with_obs = (cfg["obs"] != "none") and not args.no_obs
     n = int(w["env_offsets"][-1])
     K = w["n_steps"]
-    act = md.MD_ACT_RPM if w["act_type"] == "rpm" else md.MD_ACT_PID
+    act = {"rpm": md.MD_ACT_RPM, "pid": md.MD_ACT_PID}[w["act_type"]]
 
     ctx = md.md_create(p, w["dt"], w["aero_mask"], act, w["ctrl_decim"])
     md.md_bind_layout(ctx, w["env_offsets"])

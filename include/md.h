@@ -51,9 +51,14 @@ typedef int32_t md_status;
 #define MD_AERO_DW 4u        /* pairwise downwash within an environment, Eq. 6 */
 #define MD_AERO_SURROGATE 8u /* learned residual replaces GND|DRAG|DW (exclusive with them) */
 
-/* Action types (Table "Action types"). */
-#define MD_ACT_RPM 0 /* action[4][N]: rotor speeds in rev/min, clipped to [0, MAX_RPM] */
-#define MD_ACT_PID 1 /* action[4][N]: waypoint x, y, z (m), yaw (rad) for the cascaded PID */
+/* Action types (Table "Action types"; controllers of Sec. "Control").  The
+ * controllers run every ctrl_decim steps and hold their rotor speeds. */
+#define MD_ACT_RPM 0      /* action[4][N]: rotor speeds in rev/min, clipped to [0, MAX_RPM] */
+#define MD_ACT_PID 1      /* action[4][N]: waypoint x, y, z (m), yaw (rad), cascaded PID */
+#define MD_ACT_VEL 2      /* action[4][N]: heading-frame velocity vx, vy, vz (m/s), yaw rate (rad/s) */
+#define MD_ACT_ATTITUDE 3 /* action[4][N]: collective thrust (N), roll, pitch (rad), yaw rate (rad/s) */
+#define MD_ACT_DSL 4      /* action[7][N]: waypoint x, y, z, yaw, feed-forward acceleration ax, ay, az;
+                             DSL-style PID with rate-limited setpoint (state block ctl) */
 
 /* Physical and controller constants, SI units, rotor speed in rev/min.
  * m mass; L arm length; kf, km thrust and reaction-torque coefficients per
@@ -68,6 +73,11 @@ typedef struct md_params {
     double C_gnd, c_xy, c_z, C1, C2, C3, dw_dz_min;
     double pos_kp[3], pos_ki[3], pos_kd[3], pos_i_clamp;
     double att_kp[3], att_ki[3], att_kd[3], att_i_clamp;
+    /* DSL-style PID: own gains and integral clamps, setpoint rate limits
+     * (m/s, rad/s) */
+    double dsl_pos_kp[3], dsl_pos_ki[3], dsl_pos_kd[3], dsl_pos_i_clamp;
+    double dsl_att_kp[3], dsl_att_ki[3], dsl_att_kd[3], dsl_att_i_clamp;
+    double dsl_max_speed, dsl_max_yaw_rate;
 } md_params;
 
 /* Quantities derived from md_params (Sec. "Drone Models"; h_clip under Eq. 4). */
@@ -79,10 +89,12 @@ typedef struct md_derived {
  * p[3] world position; q[4] body->world unit quaternion (w,x,y,z);
  * v[3] world velocity; w[3] body angular velocity; pid_int[6] PID integral
  * sums (position xyz, then roll/pitch/yaw; only read/written in PID mode,
- * may be NULL otherwise); rpm[4] rotor speeds applied in the last step
- * (the held command between PID updates). */
+ * may be NULL for RPM actions); rpm[4] rotor speeds applied in the last
+ * step (the held command between controller updates); ctl[4] the DSL
+ * controller's rate-limited setpoint x, y, z, yaw (MD_ACT_DSL only, may be
+ * NULL otherwise; initialise it to the drone's position and yaw). */
 typedef struct md_state {
-    float *p, *q, *v, *w, *pid_int, *rpm;
+    float *p, *q, *v, *w, *pid_int, *rpm, *ctl;
 } md_state;
 
 typedef struct md_ctx md_ctx;
@@ -122,13 +134,13 @@ md_status md_bind_layout(md_ctx *ctx, const int32_t *h_env_offsets, int n_envs, 
 
 /* Advance every drone n_steps physics steps of dt, asynchronously on stream.
  *   s: device state, updated in place (read once, written once per call);
- *   d_action: RPM mode -> [n_act][4][N] rotor speeds; PID mode -> [n_act][4][N]
- *     waypoints (x, y, z, yaw); n_act = n_steps if action_per_step else 1;
+ *   d_action: [n_act][rows][N] with rows as listed for the action type (4, or
+ *     7 for MD_ACT_DSL); n_act = n_steps if action_per_step else 1;
  *   d_obs: NULL, or [n_obs_slots][20][N] KIN observations: after step k the
  *     row block k mod n_obs_slots receives p[3], q[4], roll/pitch/yaw[3]
  *     (Z-Y-X), v[3], w[3], applied rotor speeds[4];
- *   step0: global index of the first step; PID updates run at steps with
- *     (step0 + k) mod ctrl_decim == 0.
+ *   step0: global index of the first step; controller updates run at steps
+ *     with (step0 + k) mod ctrl_decim == 0.
  * Sums over neighbours run in ascending drone order, so results do not depend
  * on how environments are packed.  Errors: MD_E_LAYOUT if no layout is bound,
  * MD_E_INVALID_ARG for null required pointers or n_steps < 0. */

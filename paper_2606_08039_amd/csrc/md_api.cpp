@@ -72,6 +72,18 @@ KConst make_kconst(const md_params &p, const md_derived &d, double dt, int decim
     }
     c.p_clamp = (float)p.pos_i_clamp;
     c.a_clamp = (float)p.att_i_clamp;
+    for (int k = 0; k < 3; ++k) {
+        c.dsl_pkp[k] = (float)p.dsl_pos_kp[k];
+        c.dsl_pki[k] = (float)p.dsl_pos_ki[k];
+        c.dsl_pkd[k] = (float)p.dsl_pos_kd[k];
+        c.dsl_akp[k] = (float)p.dsl_att_kp[k];
+        c.dsl_aki[k] = (float)p.dsl_att_ki[k];
+        c.dsl_akd[k] = (float)p.dsl_att_kd[k];
+    }
+    c.dsl_p_clamp = (float)p.dsl_pos_i_clamp;
+    c.dsl_a_clamp = (float)p.dsl_att_i_clamp;
+    c.dsl_step = (float)(p.dsl_max_speed * dt * decim);
+    c.dsl_ystep = (float)(p.dsl_max_yaw_rate * dt * decim);
     c.dt_c = (float)(dt * decim);
     c.g_inv = (float)(1.0 / p.g);
     c.l_inv = (float)(std::sqrt(2.0) / p.L);
@@ -229,9 +241,9 @@ md_status launch(md_ctx *ctx, const md_state *s, const float *d_action, int acti
     if (rc != MD_OK) return rc;
     StepArgs a;
     a.c = ctx->kc;
-    a.s = StatePtr{s->p, s->q, s->v, s->w, s->pid_int, s->rpm};
+    a.s = StatePtr{s->p, s->q, s->v, s->w, s->pid_int, s->rpm, s->ctl};
     a.action = d_action;
-    a.act_step_stride = action_per_step ? 4LL * ctx->n_drones : 0;
+    a.act_step_stride = action_per_step ? (long long)action_rows(ctx->act) * ctx->n_drones : 0;
     a.obs = (n_obs_slots > 0) ? d_obs : nullptr;
     a.n_obs_slots = n_obs_slots > 0 ? n_obs_slots : 1;
     a.n_steps = n_steps;
@@ -289,6 +301,20 @@ md_status md_default_params_cf2x(md_params *out) {
     }
     out->pos_i_clamp = 2.0;
     out->att_i_clamp = 0.5;
+    // DSL-style PID: the PIDControl gains (its retuned values are not printed),
+    // halved integral clamps, setpoint limits 2 m/s and pi rad/s
+    for (int k = 0; k < 3; ++k) {
+        out->dsl_pos_kp[k] = pkp[k];
+        out->dsl_pos_ki[k] = pki[k];
+        out->dsl_pos_kd[k] = pkd[k];
+        out->dsl_att_kp[k] = akp[k];
+        out->dsl_att_ki[k] = aki[k];
+        out->dsl_att_kd[k] = akd[k];
+    }
+    out->dsl_pos_i_clamp = 1.0;
+    out->dsl_att_i_clamp = 0.25;
+    out->dsl_max_speed = 2.0;
+    out->dsl_max_yaw_rate = M_PI;
     return MD_OK;
 }
 
@@ -305,7 +331,7 @@ md_status md_create(const md_params *p, float dt, uint32_t aero_mask, int act_ty
         g_create_err = "md_create: null params or output pointer";
         return MD_E_INVALID_ARG;
     }
-    if (!(dt > 0.f) || ctrl_decim < 1 || (act_type != MD_ACT_RPM && act_type != MD_ACT_PID) ||
+    if (!(dt > 0.f) || ctrl_decim < 1 || act_type < MD_ACT_RPM || act_type > MD_ACT_DSL ||
         (aero_mask & ~15u) != 0) {
         g_create_err = "md_create: invalid dt, ctrl_decim, act_type or aero_mask";
         return MD_E_INVALID_ARG;
@@ -410,8 +436,8 @@ md_status md_step(md_ctx *ctx, const md_state *s, const float *d_action, int act
         return MD_E_INVALID_ARG;
     }
     if (n_steps == 0 || ctx->n_drones == 0) return MD_OK;
-    if (!s->p || !s->q || !s->v || !s->w || !s->rpm || (ctx->act == MD_ACT_PID && !s->pid_int) ||
-        !d_action || (n_obs_slots > 0 && !d_obs)) {
+    if (!s->p || !s->q || !s->v || !s->w || !s->rpm || (ctx->act != MD_ACT_RPM && !s->pid_int) ||
+        (ctx->act == MD_ACT_DSL && !s->ctl) || !d_action || (n_obs_slots > 0 && !d_obs)) {
         ctx->err = "md_step: null state block, action or observation pointer";
         return MD_E_INVALID_ARG;
     }

@@ -19,6 +19,9 @@ struct KConst {
     float C2s, C3s;                       // sqrt(2 ln 2) C2, sqrt(2 ln 2) C3
     float pkp[3], pki[3], pkd[3], p_clamp;
     float akp[3], aki[3], akd[3], a_clamp;
+    float dsl_pkp[3], dsl_pki[3], dsl_pkd[3], dsl_p_clamp;
+    float dsl_akp[3], dsl_aki[3], dsl_akd[3], dsl_a_clamp;
+    float dsl_step, dsl_ystep;  // setpoint limits per controller update (m, rad)
     float dt_c, g_inv, l_inv, kappa_inv, fmax, kf_inv;
     float hover_inv;                      // 1 / HOVER_RPM (surrogate inputs)
     int decim;
@@ -26,8 +29,11 @@ struct KConst {
 
 // Six SoA device pointers of md_state.
 struct StatePtr {
-    float *p, *q, *v, *w, *pid_int, *rpm;
+    float *p, *q, *v, *w, *pid_int, *rpm, *ctl;
 };
+
+// Action rows per action type (MD_ACT_DSL carries a feed-forward acceleration).
+__host__ __device__ constexpr int action_rows(int act) { return act == 4 ? 7 : 4; }
 
 // One bin = one workgroup.  Per slot (drone slot inside the bin):
 //   x = global drone index or -1 for an idle slot,

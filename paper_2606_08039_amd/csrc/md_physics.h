@@ -88,44 +88,41 @@ __device__ __forceinline__ float clampf(float x, float lo, float hi) {
     return fminf(fmaxf(x, lo), hi);
 }
 
-// Cascaded PID of Sec. "Control" (position loop -> thrust and small-angle
-// attitude target -> attitude PID -> exact allocation inverse, rotor forces
-// clipped to [0, kf MAX_RPM^2]).
-__device__ __forceinline__ void pid_update(const KConst &c, const Drone &d, const float tgt[4],
-                                           float I[6], float n[4]) {
-    const float ex = tgt[0] - d.px, ey = tgt[1] - d.py, ez = tgt[2] - d.pz;
-    I[0] = clampf(I[0] + ex * c.dt_c, -c.p_clamp, c.p_clamp);
-    I[1] = clampf(I[1] + ey * c.dt_c, -c.p_clamp, c.p_clamp);
-    I[2] = clampf(I[2] + ez * c.dt_c, -c.p_clamp, c.p_clamp);
-    const float ax = c.pkp[0] * ex + c.pki[0] * I[0] - c.pkd[0] * d.vx;
-    const float ay = c.pkp[1] * ey + c.pki[1] * I[1] - c.pkd[1] * d.vy;
-    const float az = c.pkp[2] * ez + c.pki[2] * I[2] - c.pkd[2] * d.vz + c.g;
-    const float T = c.m * fsqrt(ax * ax + ay * ay + az * az);
+__device__ __forceinline__ float wrap_pi(float a) {
+    return a - kTwoPi * floorf((a + kPi) * (1.f / kTwoPi));
+}
 
+// Roll, pitch, yaw and the yaw's sine and cosine (straight from the atan2
+// arguments, no further transcendental).
+__device__ __forceinline__ void attitude_angles(const Drone &d, float &roll, float &pitch, float &yaw,
+                                                float &sps, float &cps) {
     const float w = d.qw, x = d.qx, y = d.qy, z = d.qz;
-    float sp = clampf(2.f * (w * y - z * x), -1.f, 1.f);
-    const float roll = atan2_poly(2.f * (w * x + y * z), 1.f - 2.f * (x * x + y * y));
-    const float pitch = asin_poly(sp);
+    const float sp = clampf(2.f * (w * y - z * x), -1.f, 1.f);
+    roll = atan2_poly(2.f * (w * x + y * z), 1.f - 2.f * (x * x + y * y));
+    pitch = asin_poly(sp);
     const float ys = 2.f * (w * z + x * y), yc = 1.f - 2.f * (y * y + z * z);
-    const float yaw = atan2_poly(ys, yc);
-    // sin and cos of the yaw straight from the atan2 arguments
+    yaw = atan2_poly(ys, yc);
     const float h2 = ys * ys + yc * yc;
     const float hinv = h2 > 0.f ? rsqrtf(h2) : 0.f;
-    const float sps = h2 > 0.f ? ys * hinv : 0.f;
-    const float cps = h2 > 0.f ? yc * hinv : 1.f;
+    sps = h2 > 0.f ? ys * hinv : 0.f;
+    cps = h2 > 0.f ? yc * hinv : 1.f;
+}
 
-    const float roll_t = (ax * sps - ay * cps) * c.g_inv;
-    const float pitch_t = (ax * cps + ay * sps) * c.g_inv;
-    float dyaw = tgt[3] - yaw;
-    dyaw = dyaw - kTwoPi * floorf((dyaw + kPi) * (1.f / kTwoPi));
+// Attitude PID and exact allocation inverse shared by the controllers:
+// e = (roll* - roll, pitch* - pitch, e_yaw), I += e dt_c clamped,
+// tau = Kp e + Ki I + Kd (w*_z z_hat - w); rotor forces clipped to
+// [0, kf MAX_RPM^2] (Sec. "Control").
+__device__ __forceinline__ void attitude_allocate(const KConst &c, const Drone &d, float roll, float pitch,
+                                                  float T, float roll_t, float pitch_t, float e_yaw,
+                                                  float wz_t, const float *kp, const float *ki,
+                                                  const float *kd, float clamp, float *Ia, float n[4]) {
     const float er = roll_t - roll, ep = pitch_t - pitch;
-    I[3] = clampf(I[3] + er * c.dt_c, -c.a_clamp, c.a_clamp);
-    I[4] = clampf(I[4] + ep * c.dt_c, -c.a_clamp, c.a_clamp);
-    I[5] = clampf(I[5] + dyaw * c.dt_c, -c.a_clamp, c.a_clamp);
-    const float tx = c.akp[0] * er + c.aki[0] * I[3] - c.akd[0] * d.wx;
-    const float ty = c.akp[1] * ep + c.aki[1] * I[4] - c.akd[1] * d.wy;
-    const float tz = c.akp[2] * dyaw + c.aki[2] * I[5] - c.akd[2] * d.wz;
-
+    Ia[0] = clampf(Ia[0] + er * c.dt_c, -clamp, clamp);
+    Ia[1] = clampf(Ia[1] + ep * c.dt_c, -clamp, clamp);
+    Ia[2] = clampf(Ia[2] + e_yaw * c.dt_c, -clamp, clamp);
+    const float tx = kp[0] * er + ki[0] * Ia[0] - kd[0] * d.wx;
+    const float ty = kp[1] * ep + ki[1] * Ia[1] - kd[1] * d.wy;
+    const float tz = kp[2] * e_yaw + ki[2] * Ia[2] + kd[2] * (wz_t - d.wz);
     const float a = tx * c.l_inv, b = ty * c.l_inv, e = tz * c.kappa_inv;
     const float F0 = 0.25f * (T + a - b - e);
     const float F1 = 0.25f * (T + a + b + e);
@@ -135,6 +132,70 @@ __device__ __forceinline__ void pid_update(const KConst &c, const Drone &d, cons
     n[1] = fsqrt(clampf(F1, 0.f, c.fmax) * c.kf_inv);
     n[2] = fsqrt(clampf(F2, 0.f, c.fmax) * c.kf_inv);
     n[3] = fsqrt(clampf(F3, 0.f, c.fmax) * c.kf_inv);
+}
+
+// Thrust T = m |a*| and the near-hover attitude target at the current yaw.
+__device__ __forceinline__ void thrust_direction(const KConst &c, float ax, float ay, float az, float sps,
+                                                 float cps, float &T, float &roll_t, float &pitch_t) {
+    T = c.m * fsqrt(ax * ax + ay * ay + az * az);
+    roll_t = (ax * sps - ay * cps) * c.g_inv;
+    pitch_t = (ax * cps + ay * sps) * c.g_inv;
+}
+
+// One controller update (Sec. "Control"; Table "Action types"):
+//   ACT 1 cascaded PID to waypoint (x, y, z, yaw);
+//   ACT 2 VEL: heading-frame velocity + yaw rate, a* = Kd (v* - v) + g;
+//   ACT 3 ATTITUDE: collective thrust, roll, pitch, yaw rate;
+//   ACT 4 DSL-style PID: rate-limited setpoint sp (x, y, z, yaw) toward the
+//         waypoint, own gains and clamps, feed-forward acceleration cmd[4..6].
+template <int ACT>
+__device__ __forceinline__ void control(const KConst &c, const Drone &d, const float *cmd, float I[6],
+                                        float sp[4], float n[4]) {
+    float roll, pitch, yaw, sps, cps;
+    attitude_angles(d, roll, pitch, yaw, sps, cps);
+    if (ACT == 1) {
+        const float ex = cmd[0] - d.px, ey = cmd[1] - d.py, ez = cmd[2] - d.pz;
+        I[0] = clampf(I[0] + ex * c.dt_c, -c.p_clamp, c.p_clamp);
+        I[1] = clampf(I[1] + ey * c.dt_c, -c.p_clamp, c.p_clamp);
+        I[2] = clampf(I[2] + ez * c.dt_c, -c.p_clamp, c.p_clamp);
+        const float ax = c.pkp[0] * ex + c.pki[0] * I[0] - c.pkd[0] * d.vx;
+        const float ay = c.pkp[1] * ey + c.pki[1] * I[1] - c.pkd[1] * d.vy;
+        const float az = c.pkp[2] * ez + c.pki[2] * I[2] - c.pkd[2] * d.vz + c.g;
+        float T, rt, pt;
+        thrust_direction(c, ax, ay, az, sps, cps, T, rt, pt);
+        attitude_allocate(c, d, roll, pitch, T, rt, pt, wrap_pi(cmd[3] - yaw), 0.f, c.akp, c.aki, c.akd,
+                          c.a_clamp, I + 3, n);
+    } else if (ACT == 2) {
+        const float vtx = cps * cmd[0] - sps * cmd[1], vty = sps * cmd[0] + cps * cmd[1];
+        const float ax = c.pkd[0] * (vtx - d.vx);
+        const float ay = c.pkd[1] * (vty - d.vy);
+        const float az = c.pkd[2] * (cmd[2] - d.vz) + c.g;
+        float T, rt, pt;
+        thrust_direction(c, ax, ay, az, sps, cps, T, rt, pt);
+        attitude_allocate(c, d, roll, pitch, T, rt, pt, 0.f, cmd[3], c.akp, c.aki, c.akd, c.a_clamp, I + 3, n);
+    } else if (ACT == 3) {
+        attitude_allocate(c, d, roll, pitch, cmd[0], cmd[1], cmd[2], 0.f, cmd[3], c.akp, c.aki, c.akd,
+                          c.a_clamp, I + 3, n);
+    } else {
+        const float dx = cmd[0] - sp[0], dy = cmd[1] - sp[1], dz = cmd[2] - sp[2];
+        const float dn = fsqrt(dx * dx + dy * dy + dz * dz);
+        const float sc = dn > c.dsl_step ? c.dsl_step * rcp(dn) : 1.f;
+        sp[0] += sc * dx;
+        sp[1] += sc * dy;
+        sp[2] += sc * dz;
+        sp[3] = wrap_pi(sp[3] + clampf(wrap_pi(cmd[3] - sp[3]), -c.dsl_ystep, c.dsl_ystep));
+        const float ex = sp[0] - d.px, ey = sp[1] - d.py, ez = sp[2] - d.pz;
+        I[0] = clampf(I[0] + ex * c.dt_c, -c.dsl_p_clamp, c.dsl_p_clamp);
+        I[1] = clampf(I[1] + ey * c.dt_c, -c.dsl_p_clamp, c.dsl_p_clamp);
+        I[2] = clampf(I[2] + ez * c.dt_c, -c.dsl_p_clamp, c.dsl_p_clamp);
+        const float ax = c.dsl_pkp[0] * ex + c.dsl_pki[0] * I[0] - c.dsl_pkd[0] * d.vx + cmd[4];
+        const float ay = c.dsl_pkp[1] * ey + c.dsl_pki[1] * I[1] - c.dsl_pkd[1] * d.vy + cmd[5];
+        const float az = c.dsl_pkp[2] * ez + c.dsl_pki[2] * I[2] - c.dsl_pkd[2] * d.vz + cmd[6] + c.g;
+        float T, rt, pt;
+        thrust_direction(c, ax, ay, az, sps, cps, T, rt, pt);
+        attitude_allocate(c, d, roll, pitch, T, rt, pt, wrap_pi(sp[3] - yaw), 0.f, c.dsl_akp, c.dsl_aki,
+                          c.dsl_akd, c.dsl_a_clamp, I + 3, n);
+    }
 }
 
 // Motor model and X mixer (Eq. 1-3).  Contraction into fused multiply-adds is

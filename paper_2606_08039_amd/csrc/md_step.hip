@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         d.wy = a.s.w[N + di];
         d.wz = a.s.w[2 * N + di];
         for (int k = 0; k < 4; ++k) n[k] = a.s.rpm[k * N + di];
-        if (ACT == 1) {
+        if (ACT >= 1) {
             for (int k = 0; k < 6; ++k) I[k] = a.s.pid_int[k * N + di];
         }
     } else {
@@ -127,11 +127,16 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     // re-reading them at every PID update would fetch them from HBM again,
     // since the observation stream evicts them from L2.
     const bool held = a.act_step_stride == 0;
-    float tgt_held[4] = {0.f, 0.f, 0.f, 0.f};
-    if (ACT == 1 && held && valid)
-        for (int k = 0; k < 4; ++k) tgt_held[k] = a.action[(long long)k * N + di];
+    constexpr int ROWS = action_rows(ACT);
+    float tgt_held[ROWS];
+    float sp[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < ROWS; ++k) tgt_held[k] = 0.f;
+    if (ACT >= 1 && held && valid)
+        for (int k = 0; k < ROWS; ++k) tgt_held[k] = a.action[(long long)k * N + di];
+    if (ACT == 4 && valid)
+        for (int k = 0; k < 4; ++k) sp[k] = a.s.ctl[k * N + di];
     // PID phase and observation slot advance as counters (no per-step division)
-    int phase = (ACT == 1) ? (int)(a.step0 % (long long)c.decim) : 0;
+    int phase = (ACT >= 1) ? (int)(a.step0 % (long long)c.decim) : 0;
     int oslot = 0;
     for (int step = 0; step < a.n_steps; ++step) {
         float4 *buf = lds_pos + (step & 1) * (2 * slots);
@@ -147,9 +152,9 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
             }
         } else {
             if (phase == 0 && valid) {
-                float tgt[4];
-                for (int k = 0; k < 4; ++k) tgt[k] = held ? tgt_held[k] : act[(long long)k * N + di];
-                pid_update(c, d, tgt, I, n);
+                float cmd[ROWS];
+                for (int k = 0; k < ROWS; ++k) cmd[k] = held ? tgt_held[k] : act[(long long)k * N + di];
+                control<ACT>(c, d, cmd, I, sp, n);
             }
             phase = (phase + 1 == c.decim) ? 0 : phase + 1;
         }
@@ -224,9 +229,11 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         a.s.w[N + di] = d.wy;
         a.s.w[2 * N + di] = d.wz;
         for (int k = 0; k < 4; ++k) a.s.rpm[k * N + di] = n[k];
-        if (ACT == 1) {
+        if (ACT >= 1) {
             for (int k = 0; k < 6; ++k) a.s.pid_int[k * N + di] = I[k];
         }
+        if (ACT == 4)
+            for (int k = 0; k < 4; ++k) a.s.ctl[k * N + di] = sp[k];
     }
 }
 
@@ -285,8 +292,13 @@ hipError_t launch_step(const StepArgs &a, uint32_t mask, int act, const LaunchCf
     const int threads = slots * lpd;
     size_t lds = (mask & 4u) ? sizeof(float4) * 2 * 2 * (size_t)slots : 0;
     if ((mask & 4u) && cfg.sym) lds += sizeof(float) * (size_t)slots * (size_t)a.tstride;
-    if (act == 0) return launch_m<0>(a, mask, cfg, n_bins, threads, lds, stream);
-    return launch_m<1>(a, mask, cfg, n_bins, threads, lds, stream);
+    switch (act) {
+        case 0: return launch_m<0>(a, mask, cfg, n_bins, threads, lds, stream);
+        case 1: return launch_m<1>(a, mask, cfg, n_bins, threads, lds, stream);
+        case 2: return launch_m<2>(a, mask, cfg, n_bins, threads, lds, stream);
+        case 3: return launch_m<3>(a, mask, cfg, n_bins, threads, lds, stream);
+        default: return launch_m<4>(a, mask, cfg, n_bins, threads, lds, stream);
+    }
 }
 
 }  // namespace md

@@ -326,15 +326,20 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
     if (valid) {
         load_drone(a.s, N, di, d);
         for (int k = 0; k < 4; ++k) n[k] = a.s.rpm[k * N + di];
-        if (ACT == 1)
+        if (ACT >= 1)
             for (int k = 0; k < 6; ++k) I[k] = a.s.pid_int[k * N + di];
     }
     const bool held = a.act_step_stride == 0;
-    float tgt_held[4] = {0.f, 0.f, 0.f, 0.f};
-    if (ACT == 1 && held && valid)
-        for (int k = 0; k < 4; ++k) tgt_held[k] = a.action[(long long)k * N + di];
+    constexpr int ROWS = action_rows(ACT);
+    float tgt_held[ROWS];
+    float sp[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < ROWS; ++k) tgt_held[k] = 0.f;
+    if (ACT >= 1 && held && valid)
+        for (int k = 0; k < ROWS; ++k) tgt_held[k] = a.action[(long long)k * N + di];
+    if (ACT == 4 && valid)
+        for (int k = 0; k < 4; ++k) sp[k] = a.s.ctl[k * N + di];
     double jerr = 0.0, jref = 0.0, jterr = 0.0, jn = 0.0, jfb = 0.0;
-    int phase = (ACT == 1) ? (int)(a.step0 % (long long)c.decim) : 0;
+    int phase = (ACT >= 1) ? (int)(a.step0 % (long long)c.decim) : 0;
     int oslot = 0;
     for (int step = 0; step < a.n_steps; ++step) {
         float4 *pos = posb + (step & 1) * 2 * S;
@@ -348,9 +353,9 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
                 for (int k = 0; k < 4; ++k) n[k] = clampf(act[(long long)k * N + di], 0.f, c.max_rpm);
         } else {
             if (phase == 0 && valid) {
-                float tgt[4];
-                for (int k = 0; k < 4; ++k) tgt[k] = held ? tgt_held[k] : act[(long long)k * N + di];
-                pid_update(c, d, tgt, I, n);
+                float cmd[ROWS];
+                for (int k = 0; k < ROWS; ++k) cmd[k] = held ? tgt_held[k] : act[(long long)k * N + di];
+                control<ACT>(c, d, cmd, I, sp, n);
             }
             phase = (phase + 1 == c.decim) ? 0 : phase + 1;
         }
@@ -436,8 +441,10 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
         a.s.w[N + di] = d.wy;
         a.s.w[2 * N + di] = d.wz;
         for (int k = 0; k < 4; ++k) a.s.rpm[k * N + di] = n[k];
-        if (ACT == 1)
+        if (ACT >= 1)
             for (int k = 0; k < 6; ++k) a.s.pid_int[k * N + di] = I[k];
+        if (ACT == 4)
+            for (int k = 0; k < 4; ++k) a.s.ctl[k * N + di] = sp[k];
     }
     if (sa.judge != nullptr) {
         const double s0 = wave_sum(jerr), s1 = wave_sum(jref), s2 = wave_sum(jterr), s3 = wave_sum(jn),
@@ -513,10 +520,13 @@ size_t sur_lds_bytes(int S) {
 
 hipError_t launch_sur_step(const SurArgs &sa, int act, int n_bins, int S, hipStream_t st) {
     const size_t lds = sur_lds_bytes(S);
-    if (act == 0)
-        hipLaunchKernelGGL(sur_step_kernel<0>, dim3(n_bins), dim3(S), lds, st, sa);
-    else
-        hipLaunchKernelGGL(sur_step_kernel<1>, dim3(n_bins), dim3(S), lds, st, sa);
+    switch (act) {
+        case 0: hipLaunchKernelGGL(sur_step_kernel<0>, dim3(n_bins), dim3(S), lds, st, sa); break;
+        case 1: hipLaunchKernelGGL(sur_step_kernel<1>, dim3(n_bins), dim3(S), lds, st, sa); break;
+        case 2: hipLaunchKernelGGL(sur_step_kernel<2>, dim3(n_bins), dim3(S), lds, st, sa); break;
+        case 3: hipLaunchKernelGGL(sur_step_kernel<3>, dim3(n_bins), dim3(S), lds, st, sa); break;
+        default: hipLaunchKernelGGL(sur_step_kernel<4>, dim3(n_bins), dim3(S), lds, st, sa); break;
+    }
     return hipGetLastError();
 }
 
@@ -617,9 +627,9 @@ md_status surrogate_step(md_ctx *ctx, const md_state *s, const float *d_action, 
     if (rc != MD_OK) return rc;
     SurArgs sa;
     sa.s.c = ctx->kc;
-    sa.s.s = StatePtr{s->p, s->q, s->v, s->w, s->pid_int, s->rpm};
+    sa.s.s = StatePtr{s->p, s->q, s->v, s->w, s->pid_int, s->rpm, s->ctl};
     sa.s.action = d_action;
-    sa.s.act_step_stride = action_per_step ? 4LL * ctx->n_drones : 0;
+    sa.s.act_step_stride = action_per_step ? (long long)action_rows(ctx->act) * ctx->n_drones : 0;
     sa.s.obs = (n_obs_slots > 0) ? d_obs : nullptr;
     sa.s.n_obs_slots = n_obs_slots > 0 ? n_obs_slots : 1;
     sa.s.n_steps = n_steps;
@@ -653,7 +663,7 @@ md_status datagen(md_ctx *ctx, const md_state *s, uint32_t mask, float *d_X, flo
     if (rc != MD_OK) return rc;
     GenArgs g;
     g.c = ctx->kc;
-    g.s = StatePtr{s->p, s->q, s->v, s->w, s->pid_int, s->rpm};
+    g.s = StatePtr{s->p, s->q, s->v, s->w, s->pid_int, s->rpm, s->ctl};
     g.N = ctx->n_drones;
     g.bins = BinTables{bs->d_slot, bs->d_mmax};
     g.mask = mask;

@@ -145,7 +145,7 @@ md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int ac
         return MD_OK;
     }
     // scratch copies of the state: the caller's state is never advanced
-    const size_t rows = 3 + 4 + 3 + 3 + 6 + 4;
+    const size_t rows = 3 + 4 + 3 + 3 + 6 + 4 + 4;
     float *scratch = nullptr, *work = nullptr;
     hipError_t e = hipMalloc(&scratch, sizeof(float) * rows * N);
     if (e == hipSuccess) e = hipMalloc(&work, sizeof(float) * rows * N);
@@ -154,12 +154,12 @@ md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int ac
         ctx->err = hip_msg("autotune scratch", e);
         return MD_E_OOM;
     }
-    const float *src[6] = {s->p, s->q, s->v, s->w, s->pid_int, s->rpm};
-    const int nr[6] = {3, 4, 3, 3, 6, 4};
+    const float *src[7] = {s->p, s->q, s->v, s->w, s->pid_int, s->rpm, s->ctl};
+    const int nr[7] = {3, 4, 3, 3, 6, 4, 4};
     size_t o = 0;
     md_state ws;
-    float **dst[6] = {&ws.p, &ws.q, &ws.v, &ws.w, &ws.pid_int, &ws.rpm};
-    for (int k = 0; k < 6; ++k) {
+    float **dst[7] = {&ws.p, &ws.q, &ws.v, &ws.w, &ws.pid_int, &ws.rpm, &ws.ctl};
+    for (int k = 0; k < 7; ++k) {
         if (src[k])
             e = hipMemcpyAsync(scratch + o, src[k], sizeof(float) * nr[k] * N, hipMemcpyDeviceToDevice, st);
         else
@@ -296,7 +296,8 @@ md_status md_rollout_graph_create(md_ctx *ctx, const md_state *s, const float *d
     if (e == hipSuccess) {
         const long long N = ctx->n_drones;
         for (int l = 0; l < n_launches && rc == MD_OK; ++l) {
-            const float *act = d_action + (action_per_step ? (long long)l * steps_per_launch * 4 * N : 0);
+            const float *act =
+                d_action + (action_per_step ? (long long)l * steps_per_launch * md::action_rows(ctx->act) * N : 0);
             float *obs = d_obs;
             int slots = n_obs_slots;
             if (d_obs && n_obs_slots >= steps_per_launch * n_launches) {

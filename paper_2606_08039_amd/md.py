@@ -17,9 +17,10 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "md.h")
 MD_OK = 0
 MD_E_INVALID_ARG, MD_E_HIP, MD_E_OOM, MD_E_UNSUPPORTED, MD_E_LAYOUT = -1, -2, -3, -4, -5
 MD_AERO_GND, MD_AERO_DRAG, MD_AERO_DW, MD_AERO_SURROGATE = 1, 2, 4, 8
-MD_ACT_RPM, MD_ACT_PID = 0, 1
+MD_ACT_RPM, MD_ACT_PID, MD_ACT_VEL, MD_ACT_ATTITUDE, MD_ACT_DSL = 0, 1, 2, 3, 4
+ACTION_ROWS = {MD_ACT_RPM: 4, MD_ACT_PID: 4, MD_ACT_VEL: 4, MD_ACT_ATTITUDE: 4, MD_ACT_DSL: 7}
 OBS_DIM = 20
-STATE_ROWS = (("p", 3), ("q", 4), ("v", 3), ("w", 3), ("pid_int", 6), ("rpm", 4))
+STATE_ROWS = (("p", 3), ("q", 4), ("v", 3), ("w", 3), ("pid_int", 6), ("rpm", 4), ("ctl", 4))
 
 
 class MdError(RuntimeError):
@@ -35,7 +36,12 @@ class md_params(ctypes.Structure):
         ("pos_kp", ctypes.c_double * 3), ("pos_ki", ctypes.c_double * 3),
         ("pos_kd", ctypes.c_double * 3), ("pos_i_clamp", ctypes.c_double),
         ("att_kp", ctypes.c_double * 3), ("att_ki", ctypes.c_double * 3),
-        ("att_kd", ctypes.c_double * 3), ("att_i_clamp", ctypes.c_double)]
+        ("att_kd", ctypes.c_double * 3), ("att_i_clamp", ctypes.c_double),
+        ("dsl_pos_kp", ctypes.c_double * 3), ("dsl_pos_ki", ctypes.c_double * 3),
+        ("dsl_pos_kd", ctypes.c_double * 3), ("dsl_pos_i_clamp", ctypes.c_double),
+        ("dsl_att_kp", ctypes.c_double * 3), ("dsl_att_ki", ctypes.c_double * 3),
+        ("dsl_att_kd", ctypes.c_double * 3), ("dsl_att_i_clamp", ctypes.c_double),
+        ("dsl_max_speed", ctypes.c_double), ("dsl_max_yaw_rate", ctypes.c_double)]
 
 
 class md_derived(ctypes.Structure):
@@ -43,7 +49,7 @@ class md_derived(ctypes.Structure):
 
 
 class md_state(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_void_p) for n in ("p", "q", "v", "w", "pid_int", "rpm")]
+    _fields_ = [(n, ctypes.c_void_p) for n in ("p", "q", "v", "w", "pid_int", "rpm", "ctl")]
 
 
 _lib = None
@@ -194,7 +200,7 @@ class DeviceState:
         return d
 
     def as_md_state(self):
-        return md_state(*[self.t[k].data_ptr() for k in ("p", "q", "v", "w", "pid_int", "rpm")])
+        return md_state(*[self.t[k].data_ptr() for k in ("p", "q", "v", "w", "pid_int", "rpm", "ctl")])
 
 
 # ------------------------------------------------------------------ surrogate network

@@ -7,7 +7,7 @@ caller -- and it imports nothing else from this package, so both the HIP path
 and the CPU oracle consume exactly the same float32 buffers.
 
 State arrays are float32, component-major ``[c][N]``:
-``p[3], q[4] (w,x,y,z), v[3], w[3], pid_int[6], rpm[4]``.
+``p[3], q[4] (w,x,y,z), v[3], w[3], pid_int[6], rpm[4], ctl[4]``.
 
 Workloads (dt = 1/240 s):
 
@@ -30,7 +30,7 @@ Workloads (dt = 1/240 s):
 """
 import numpy as np
 
-STATE_ROWS = (("p", 3), ("q", 4), ("v", 3), ("w", 3), ("pid_int", 6), ("rpm", 4))
+STATE_ROWS = (("p", 3), ("q", 4), ("v", 3), ("w", 3), ("pid_int", 6), ("rpm", 4), ("ctl", 4))
 DT = 1.0 / 240.0
 
 
@@ -137,6 +137,42 @@ def formation(n_envs=8192, n_steps=1000, seed=4):
     w = lattice(n_envs=n_envs, shape=(4, 4, 2), n_steps=n_steps, seed=seed)
     w["name"] = "formation"
     return w
+
+
+def commanded(kind, hover_thrust, n_envs=1024, n_steps=480, seed=5):
+    """E envs x 1 drone placed and oriented as in pid_field, with held
+    commands for the VEL, ATTITUDE or DSL action types (ground effect + drag):
+      vel       heading-frame velocity U[-1,1]^2 x U[-0.5,0.5] m/s, yaw rate U[-1,1] rad/s;
+      attitude  thrust hover_thrust*(1+U[-0.2,0.2]) N, roll and pitch U[-0.3,0.3] rad,
+                yaw rate U[-1,1] rad/s;
+      dsl       waypoints U[-2,2]^2 x U[0.2,2] m, yaw U[-pi,pi), feed-forward
+                acceleration U[-0.5,0.5]^3 m/s^2; the setpoint block starts at the
+                drone's position and yaw."""
+    rng = np.random.default_rng(seed)
+    n = n_envs
+    s = empty_state(n)
+    s["p"][0:2] = rng.uniform(-1.0, 1.0, size=(2, n))
+    s["p"][2] = rng.uniform(0.3, 1.5, size=n)
+    yaw = rng.uniform(-np.pi, np.pi, size=n)
+    cw, sz = _yaw_quat(yaw)
+    s["q"][0], s["q"][3] = cw, sz
+    if kind == "vel":
+        cmd = np.stack([rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.uniform(-0.5, 0.5, n),
+                        rng.uniform(-1, 1, n)])
+    elif kind == "attitude":
+        cmd = np.stack([hover_thrust * (1 + rng.uniform(-0.2, 0.2, n)), rng.uniform(-0.3, 0.3, n),
+                        rng.uniform(-0.3, 0.3, n), rng.uniform(-1, 1, n)])
+    elif kind == "dsl":
+        cmd = np.stack([rng.uniform(-2, 2, n), rng.uniform(-2, 2, n), rng.uniform(0.2, 2, n),
+                        rng.uniform(-np.pi, np.pi, n), rng.uniform(-0.5, 0.5, n),
+                        rng.uniform(-0.5, 0.5, n), rng.uniform(-0.5, 0.5, n)])
+        s["ctl"][0:3] = s["p"]
+        s["ctl"][3] = yaw
+    else:
+        raise ValueError(kind)
+    return dict(name="commanded_" + kind, env_offsets=np.arange(n + 1, dtype=np.int32), state=s,
+                action=cmd.astype(np.float32)[None], action_per_step=False, aero_mask=1 | 2,
+                act_type=kind, ctrl_decim=5, n_steps=n_steps, dt=DT)
 
 
 def permute_envs(w, perm):

@@ -13,7 +13,10 @@ from paper_2606_08039_amd import md
 
 TOL = 1e-5
 BLOCKS = ("p", "q", "v", "w", "rpm")
-ACT = {"rpm": md.MD_ACT_RPM, "pid": md.MD_ACT_PID}
+ACT = {"rpm": md.MD_ACT_RPM, "pid": md.MD_ACT_PID, "vel": md.MD_ACT_VEL,
+       "attitude": md.MD_ACT_ATTITUDE, "dsl": md.MD_ACT_DSL}
+ORC_ACT = {"rpm": orc.ACT_RPM, "pid": orc.ACT_PID, "vel": orc.ACT_VEL,
+           "attitude": orc.ACT_ATTITUDE, "dsl": orc.ACT_DSL}
 
 
 def params():
@@ -74,6 +77,7 @@ def obs_to_state(o, prev=None):
     s = {"p": o[0:3], "q": o[3:7], "v": o[10:13], "w": o[13:16], "rpm": o[16:20]}
     n = o.shape[1]
     s["pid_int"] = prev["pid_int"] if prev is not None else np.zeros((6, n), dtype=o.dtype)
+    s["ctl"] = prev["ctl"] if prev is not None and "ctl" in prev else np.zeros((4, n), dtype=o.dtype)
     return s
 
 
@@ -96,7 +100,7 @@ def oracle_one_step(w, s32, k, env_subset=None, mask=None, n_steps=1, obs_slots=
         sub_off = np.asarray(off, dtype=np.int32)
     a = act[k:k + n_steps] if w["action_per_step"] else act[0:1]
     obs = orc.step(P, w["dt"], w["aero_mask"] if mask is None else mask,
-                   orc.ACT_RPM if w["act_type"] == "rpm" else orc.ACT_PID, w["ctrl_decim"],
+                   ORC_ACT[w["act_type"]], w["ctrl_decim"],
                    sub_off, s, np.ascontiguousarray(a, dtype=np.float64), w["action_per_step"],
                    n_steps, step0=k, n_obs_slots=obs_slots)
     return s, obs, idx

@@ -120,7 +120,7 @@ def _oracle_sur_step(w, s32, k, flat, norm, dz_ood=1e-3, env_subset=None):
         s = {kk: np.ascontiguousarray(v[:, idx]) for kk, v in s.items()}
         act = act[:, :, idx]
     a = act[k:k + 1] if w["action_per_step"] else act[0:1]
-    _, aero, fb = orc.step_surrogate(P, w["dt"], orc.ACT_RPM if w["act_type"] == "rpm" else orc.ACT_PID,
+    _, aero, fb = orc.step_surrogate(P, w["dt"], pu.ORC_ACT[w["act_type"]],
                                      w["ctrl_decim"], sub_off, s, np.ascontiguousarray(a, dtype=np.float64),
                                      w["action_per_step"], 1, net, step0=k)
     return s, aero, fb, idx
