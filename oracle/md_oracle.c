@@ -718,10 +718,15 @@ int orc_step_rk4(const orc_params *P, double dt, uint32_t aero_mask, int act_typ
 /* Surrogate support: neighbours, features, residual targets, MLP, Adam.     */
 /* ------------------------------------------------------------------------ */
 
-/* k nearest same-environment neighbours by 3-D distance, ascending, ties to
- * the lower index, padded with -1.  The distance that decides the order is
- * formed in binary32 exactly as the GPU forms it (dx*dx + dy*dy, then + dz*dz,
- * each operation rounded), so both sides take the same integer decision. */
+/* k nearest same-environment neighbours by horizontal distance, ascending,
+ * ties to the lower index, padded with -1.  Reading: the metric is the
+ * lateral one because the only pairwise term, the downwash of Eq. (6),
+ * varies with the lateral offset on the scale of beta (centimetres) and with
+ * the vertical one on the scale of metres, so the neighbours that matter are
+ * the laterally closest; this also puts a drone's column partner in the same
+ * input slot for every sample.  The squared distance that decides the order
+ * is formed in binary32 exactly as the GPU forms it (dx*dx + dy*dy, each
+ * operation rounded), so both sides take the same integer decision. */
 typedef struct { float d2; int32_t j; } orc_cand;
 
 static int cand_cmp(const void *a, const void *b)
@@ -754,17 +759,14 @@ int orc_knn(int n_envs, const int32_t *env_offsets, int n_drones, const double *
             if (!c) continue;
             for (int i = env_offsets[e]; i < env_offsets[e + 1]; ++i) {
                 int nc = 0;
-                const float xi = (float)p[0 * N + i], yi = (float)p[1 * N + i], zi = (float)p[2 * N + i];
+                const float xi = (float)p[0 * N + i], yi = (float)p[1 * N + i];
                 for (int j = env_offsets[e]; j < env_offsets[e + 1]; ++j) {
                     if (j == i) continue;
                     volatile float dx = (float)p[0 * N + j] - xi;
                     volatile float dy = (float)p[1 * N + j] - yi;
-                    volatile float dz = (float)p[2 * N + j] - zi;
                     volatile float a = dx * dx;
                     volatile float b = dy * dy;
-                    volatile float cz = dz * dz;
-                    volatile float s1 = a + b;
-                    volatile float d2 = s1 + cz;
+                    volatile float d2 = a + b;
                     c[nc].d2 = d2;
                     c[nc].j = j;
                     ++nc;
@@ -799,7 +801,10 @@ static void features_one(const orc_derived *D, int N, int i, const double *p_pre
             x[10 + 6 * t + 3 + c] = v_pre[c * N + j] - v_pre[c * N + i];
         }
     }
-    x[10 + 6 * k] = p_pre[2 * N + i];
+    const double z = p_pre[2 * N + i];
+    const double g = D->h_clip / (z > D->h_clip ? z : D->h_clip);
+    x[10 + 6 * k] = z;
+    x[11 + 6 * k] = g * g;
 }
 
 /* Surrogate inputs of one drone (raw, before any scaling), n_feat = 64:
@@ -809,7 +814,8 @@ static void features_one(const orc_derived *D, int N, int i, const double *p_pre
  *   [10..57] for each of the k = 8 nearest neighbours: p_j - p_i, v_j - v_i
  *            (world frame), zeros for a missing neighbour
  *   [58]    p_z
- *   [59..]  zero padding.
+ *   [59]    ground proximity (h_clip / max(p_z, h_clip))^2, in (0, 1]
+ *   [60..]  zero padding.
  * Rotor speeds are the state's rpm. */
 int orc_features(const orc_params *P, int n_envs, const int32_t *env_offsets, int n_drones,
                  const orc_state *s, const int32_t *nbr, int k, int n_feat, double *X)

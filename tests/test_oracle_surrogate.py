@@ -23,18 +23,22 @@ def test_knn_matches_brute_force_sort():
     # plant exact ties: two drones at the same offset from a third
     p[:, 10] = p[:, 9] + [0.25, 0, 0]
     p[:, 11] = p[:, 9] + [-0.25, 0, 0]
+    # a drone straight above another is its nearest neighbour whatever the height
+    p[:, 20] = p[:, 19] + [1e-3, 0, 0.9]
     nbr = orc.knn(off, p, 8)
     pf = p.astype(np.float32)
     for e in range(len(off) - 1):
         for i in range(off[e], off[e + 1]):
             js = np.array([j for j in range(off[e], off[e + 1]) if j != i], dtype=np.int64)
             d = pf[:, js] - pf[:, [i]]
-            d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]  # float32, same order
+            d2 = d[0] * d[0] + d[1] * d[1]  # horizontal, float32
+            assert d2.dtype == np.float32
             order = js[np.lexsort((js, d2))][:8]
             expect = np.full(8, -1)
             expect[: len(order)] = order
             np.testing.assert_array_equal(nbr[i], expect)
     assert nbr[9][0] == 10 and nbr[9][1] == 11  # tie broken to the lower index
+    assert nbr[19][0] == 20 and nbr[20][0] == 19
 
 
 def test_features_match_library_rotations():
@@ -66,7 +70,10 @@ def test_features_match_library_rotations():
                 np.testing.assert_allclose(blk[:3], p[:, j] - p[:, i], rtol=1e-15)
                 np.testing.assert_allclose(blk[3:], s["v"][:, j] - s["v"][:, i], rtol=1e-15)
     np.testing.assert_array_equal(X[:, 58], p[2])
-    assert np.all(X[:, 59:] == 0)
+    # ground proximity: 1 at or below the clip height, (h_clip / z)^2 above
+    np.testing.assert_allclose(X[:, 59], np.minimum(1.0, (D.h_clip / p[2]) ** 2) * (p[2] > 0)
+                               + (p[2] <= 0), rtol=1e-15)
+    assert np.all(X[:, 60:] == 0)
 
 
 def test_aero_residual_is_body_frame_sum_of_terms():
