@@ -55,7 +55,20 @@ class Net(ctypes.Structure):
 
 
 class _CState(ctypes.Structure):
-    _fields_ = [(n, ctypes.POINTER(ctypes.c_double)) for n in ("p", "q", "v", "w", "pid_int", "rpm", "ctl")]
+    _fields_ = [(n, ctypes.POINTER(ctypes.c_double)) for n in ("p", "q", "v", "w", "pid_int", "rpm", "ctl",
+                                                               "rpm_cmd", "act_hist")] + \
+        [("act_count", ctypes.POINTER(ctypes.c_int32))]
+
+
+class _CDr(ctypes.Structure):
+    _fields_ = [("scale", ctypes.POINTER(ctypes.c_double)), ("tau_mot", ctypes.POINTER(ctypes.c_double)),
+                ("delay", ctypes.POINTER(ctypes.c_int32))]
+
+
+# Domain randomisation factor rows (orc_dr.scale) and the latency ring depth.
+DR_ROWS = ("m", "J", "L", "kf", "km", "drag", "C_gnd", "C1", "max_rpm", "g",
+           "bias0", "bias1", "bias2", "bias3")
+DR_HIST = 32
 
 
 _lib = None
@@ -96,6 +109,8 @@ def _load():
                              ctypes.c_int]
     lib.orc_step.restype = ctypes.c_int
     lib.orc_step_rk4.argtypes = lib.orc_step.argtypes
+    lib.orc_step_dr.argtypes = lib.orc_step.argtypes + [ctypes.POINTER(_CDr)]
+    lib.orc_step_dr.restype = ctypes.c_int
     lib.orc_step_rk4.restype = ctypes.c_int
     lib.orc_knn.argtypes = [ctypes.c_int, _I32, ctypes.c_int, _D, ctypes.c_int, _I32]
     lib.orc_features.argtypes = [P, ctypes.c_int, _I32, ctypes.c_int, ctypes.POINTER(_CState),
@@ -278,15 +293,35 @@ def _cstate(s):
         if k == "ctl" and k not in s:
             continue
         assert s[k].dtype == np.float64 and s[k].flags.c_contiguous, k
-    return _CState(*[s[k].ctypes.data_as(_D) if k in s else None
-                     for k in ("p", "q", "v", "w", "pid_int", "rpm", "ctl")])
+    for k in ("rpm_cmd", "act_hist"):
+        if k in s:
+            assert s[k].dtype == np.float64 and s[k].flags.c_contiguous, k
+    if "act_count" in s:
+        assert s["act_count"].dtype == np.int32 and s["act_count"].flags.c_contiguous
+    return _CState(*([s[k].ctypes.data_as(_D) if k in s else None
+                      for k in ("p", "q", "v", "w", "pid_int", "rpm", "ctl", "rpm_cmd", "act_hist")] +
+                     [s["act_count"].ctypes.data_as(_I32) if "act_count" in s else None]))
+
+
+def dr_state(state, act_type):
+    """Add the blocks the randomised step needs to a state dict: the held
+    controller command (= the state's rotor speeds), an empty action ring and
+    zero counts."""
+    n = state["p"].shape[1]
+    state["rpm_cmd"] = state["rpm"].copy()
+    state["act_hist"] = np.zeros((DR_HIST, ACTION_ROWS[act_type], n))
+    state["act_count"] = np.zeros(n, dtype=np.int32)
+    return state
 
 
 def step(P, dt, aero_mask, act_type, ctrl_decim, env_offsets, state, action,
-         action_per_step, n_steps, step0=0, n_obs_slots=0, n_threads=0, integrator="euler"):
+         action_per_step, n_steps, step0=0, n_obs_slots=0, n_threads=0, integrator="euler",
+         dr=None):
     """Advance ``state`` (dict of [c][N] float64 arrays, updated in place) by
     n_steps with the semi-implicit Euler step or classic RK4; returns the
-    observation array [slots][20][N] or None."""
+    observation array [slots][20][N] or None.  dr: None, or a dict with
+    "scale" [len(DR_ROWS)][N] and optional "tau_mot" [N] (s) and "delay" [N]
+    (int steps) for the domain-randomised Euler step (orc_step_dr)."""
     off = np.ascontiguousarray(np.asarray(env_offsets, dtype=np.int32))
     n_envs = len(off) - 1
     n = int(off[-1])
@@ -295,11 +330,22 @@ def step(P, dt, aero_mask, act_type, ctrl_decim, env_offsets, state, action,
     assert act.size == need, (act.size, need)
     obs = np.zeros((n_obs_slots, 20, n)) if n_obs_slots > 0 else None
     cs = _cstate(state)
-    fn = _load().orc_step if integrator == "euler" else _load().orc_step_rk4
-    rc = fn(ctypes.byref(P), float(dt), int(aero_mask), int(act_type),
+    args = (ctypes.byref(P), float(dt), int(aero_mask), int(act_type),
             int(ctrl_decim), n_envs, _ip(off), n, ctypes.byref(cs), _dp(act),
             int(bool(action_per_step)), _dp(obs) if obs is not None else None,
             int(n_obs_slots), int(n_steps), int(step0), int(n_threads))
+    if dr is not None:
+        assert integrator == "euler"
+        sc = np.ascontiguousarray(dr["scale"], dtype=np.float64)
+        assert sc.shape == (len(DR_ROWS), n), sc.shape
+        tau = np.ascontiguousarray(dr["tau_mot"], dtype=np.float64) if dr.get("tau_mot") is not None else None
+        dl = np.ascontiguousarray(dr["delay"], dtype=np.int32) if dr.get("delay") is not None else None
+        cdr = _CDr(_dp(sc), _dp(tau) if tau is not None else None,
+                   dl.ctypes.data_as(_I32) if dl is not None else None)
+        rc = _load().orc_step_dr(*args, ctypes.byref(cdr))
+    else:
+        fn = _load().orc_step if integrator == "euler" else _load().orc_step_rk4
+        rc = fn(*args)
     if rc != 0:
         raise ValueError("orc_step failed (%d)" % rc)
     return obs

@@ -385,12 +385,10 @@ int orc_action_rows(int act_type) { return act_type == ORC_ACT_DSL ? 7 : 4; }
 
 /* One controller update of drone i for the non-RPM action types. */
 static void controller(const orc_params *P, const orc_derived *D, int act_type, double dt_c, int N,
-                       int i, const double *act, const double p[3], const double q[4],
+                       int i, const double cmd[7], const double p[3], const double q[4],
                        const double v[3], const double w[3], orc_state *s, double n[4])
 {
-    double cmd[7], integ[6], sp[4];
-    const int rows = orc_action_rows(act_type);
-    for (int c = 0; c < rows; ++c) cmd[c] = act[c * N + i];
+    double integ[6], sp[4];
     for (int c = 0; c < 6; ++c) integ[c] = s->pid_int[c * N + i];
     if (act_type == ORC_ACT_PID) {
         orc_pid(P, D, dt_c, p, q, v, w, cmd, integ, n);
@@ -447,27 +445,68 @@ void orc_integrate(const orc_params *P, double dt, const double Fw[3], const dou
 /* Whole batched step.                                                       */
 /* ------------------------------------------------------------------------ */
 
-/* One call advances every drone n_steps times.  Per step (all drones use the
- * pre-step positions of the others for the downwash, i.e. synchronously):
- *   rotor speeds (RPM action clipped to [0, MAX_RPM], or the PID every
- *   ctrl_decim steps with phase (step0 + k) mod ctrl_decim = 0, held between),
- *   motor model, F_w = R (0,0,T) - m g z_hat, optional ground effect, drag and
- *   downwash (each env's drones in ascending index), Newton-Euler, exp map,
- *   optional KIN observation [p, q, roll/pitch/yaw, v, omega, n] to slot
- *   k mod n_obs_slots.  Layouts: action [n_act][4][N] with n_act = n_steps
- *   when action_per_step else 1; obs [slot][20][N]. */
-int orc_step(const orc_params *P, double dt, uint32_t aero_mask, int act_type, int ctrl_decim,
-             int n_envs, const int32_t *env_offsets, int n_drones, orc_state *s,
-             const double *action, int action_per_step, double *obs, int n_obs_slots,
-             int n_steps, int64_t step0, int n_threads)
+/* One drone's physical parameter block under domain randomisation (Table
+ * "Recommended domain-randomization ranges"): the nominal block with mass,
+ * inertia (one factor for the three principal moments), arm length, kf, km,
+ * drag (one factor for c_xy and c_z), C_gnd, C1 and g multiplied by the
+ * drone's factors, and MAX_RPM = factor x the nominal MAX_RPM.  Readings:
+ * the controllers keep the nominal constants (the randomised dynamics are
+ * what they must be robust to); h_clip stays nominal; the downwash on a drone
+ * uses that drone's C1. */
+static void dr_params(const orc_params *P, const orc_derived *D, const orc_dr *dr, int N, int i,
+                      orc_params *Pi, double *max_rpm_i)
+{
+    *Pi = *P;
+    *max_rpm_i = D->max_rpm;
+    if (!dr) return;
+    const double *s = dr->scale;
+    Pi->m *= s[ORC_DR_M * N + i];
+    Pi->Ixx *= s[ORC_DR_J * N + i];
+    Pi->Iyy *= s[ORC_DR_J * N + i];
+    Pi->Izz *= s[ORC_DR_J * N + i];
+    Pi->L *= s[ORC_DR_L * N + i];
+    Pi->kf *= s[ORC_DR_KF * N + i];
+    Pi->km *= s[ORC_DR_KM * N + i];
+    Pi->c_xy *= s[ORC_DR_DRAG * N + i];
+    Pi->c_z *= s[ORC_DR_DRAG * N + i];
+    Pi->C_gnd *= s[ORC_DR_GND * N + i];
+    Pi->C1 *= s[ORC_DR_C1 * N + i];
+    Pi->g *= s[ORC_DR_G * N + i];
+    *max_rpm_i = D->max_rpm * s[ORC_DR_MAXRPM * N + i];
+}
+
+/* Semi-implicit Euler step shared by orc_step (dr = NULL) and orc_step_dr.
+ *
+ * Actuator chain under domain randomisation, per step and drone:
+ *   1. action latency: the step's action rows enter a ring of ORC_DR_HIST
+ *      slots indexed by the global step; the rows used are those issued
+ *      min(delay, issued - 1) steps earlier, issued counting the actions
+ *      entered since the ring was cleared (so a fresh episode uses its first
+ *      action until the delay has elapsed);
+ *   2. command: the RPM action, or the controller's output at controller
+ *      steps (held in rpm_cmd in between);
+ *   3. per-motor bias b_k and clip: c_k = clip(b_k cmd_k, 0, MAX_RPM_i);
+ *   4. first-order motor lag with time constant tau (zero-order hold of c
+ *      over the step, exact discretisation): n <- n + (1 - e^{-dt/tau})(c - n),
+ *      or n = c for tau = 0;
+ *   5. the drone's own parameter block for Eq. 1-7.
+ * With all factors 1, tau = 0 and no delay the step equals orc_step. */
+static int step_impl(const orc_params *P, double dt, uint32_t aero_mask, int act_type, int ctrl_decim,
+                     int n_envs, const int32_t *env_offsets, int n_drones, orc_state *s,
+                     const double *action, int action_per_step, double *obs, int n_obs_slots,
+                     int n_steps, int64_t step0, int n_threads, const orc_dr *dr)
 {
     if (n_drones < 0 || n_envs < 0 || n_steps < 0 || ctrl_decim < 1) return -1;
     if (env_offsets[0] != 0 || env_offsets[n_envs] != n_drones) return -1;
     if (aero_mask & ORC_AERO_SURROGATE) return -1; /* handled by the surrogate oracle */
     if (act_type < ORC_ACT_RPM || act_type > ORC_ACT_DSL || (act_type == ORC_ACT_DSL && !s->ctl)) return -1;
+    if (dr && (!dr->scale || (act_type != ORC_ACT_RPM && !s->rpm_cmd) ||
+               (dr->delay && (!s->act_hist || !s->act_count))))
+        return -1;
     orc_derived D;
     orc_derive(P, &D);
     const int N = n_drones;
+    const int rows = orc_action_rows(act_type);
     double *p_pre = (double *)malloc(sizeof(double) * 3 * (size_t)(N > 0 ? N : 1));
     if (!p_pre) return -2;
 #ifdef _OPENMP
@@ -477,37 +516,66 @@ int orc_step(const orc_params *P, double dt, uint32_t aero_mask, int act_type, i
 #endif
     for (int k = 0; k < n_steps; ++k) {
         memcpy(p_pre, s->p, sizeof(double) * 3 * (size_t)N);
-        const int rows = orc_action_rows(act_type);
         const double *act = action + (action_per_step ? (size_t)k * rows * N : 0);
         const int do_pid = (act_type != ORC_ACT_RPM) && (((step0 + k) % ctrl_decim) == 0);
+        const int64_t slot = (step0 + k) % ORC_DR_HIST;
 #pragma omp parallel for schedule(dynamic, 16)
         for (int e = 0; e < n_envs; ++e) {
             for (int i = env_offsets[e]; i < env_offsets[e + 1]; ++i) {
-                double p[3], q[4], v[3], w[3], n[4];
+                orc_params Pi;
+                double max_rpm_i;
+                dr_params(P, &D, dr, N, i, &Pi, &max_rpm_i);
+                double p[3], q[4], v[3], w[3], n[4], a[7];
                 for (int c = 0; c < 3; ++c) {
                     p[c] = s->p[c * N + i];
                     v[c] = s->v[c * N + i];
                     w[c] = s->w[c * N + i];
                 }
                 for (int c = 0; c < 4; ++c) q[c] = s->q[c * N + i];
+                for (int c = 0; c < rows; ++c) a[c] = act[c * N + i];
+                if (dr && dr->delay) {
+                    for (int c = 0; c < rows; ++c) s->act_hist[((size_t)slot * rows + c) * N + i] = a[c];
+                    int32_t cnt = s->act_count[i] + 1;
+                    if (cnt > ORC_DR_HIST) cnt = ORC_DR_HIST;
+                    s->act_count[i] = cnt;
+                    int32_t d = dr->delay[i];
+                    if (d > cnt - 1) d = cnt - 1;
+                    const int64_t from = (slot - d + ORC_DR_HIST) % ORC_DR_HIST;
+                    for (int c = 0; c < rows; ++c) a[c] = s->act_hist[((size_t)from * rows + c) * N + i];
+                }
 
+                double cmd[4];
                 if (act_type == ORC_ACT_RPM) {
-                    for (int c = 0; c < 4; ++c) n[c] = clampd(act[c * N + i], 0.0, D.max_rpm);
+                    for (int c = 0; c < 4; ++c) cmd[c] = a[c];
                 } else if (do_pid) {
-                    controller(P, &D, act_type, dt * ctrl_decim, N, i, act, p, q, v, w, s, n);
+                    controller(P, &D, act_type, dt * ctrl_decim, N, i, a, p, q, v, w, s, cmd);
+                    if (dr)
+                        for (int c = 0; c < 4; ++c) s->rpm_cmd[c * N + i] = cmd[c];
                 } else {
-                    for (int c = 0; c < 4; ++c) n[c] = s->rpm[c * N + i];
+                    for (int c = 0; c < 4; ++c) cmd[c] = dr ? s->rpm_cmd[c * N + i] : s->rpm[c * N + i];
+                }
+                if (!dr) {
+                    for (int c = 0; c < 4; ++c)
+                        n[c] = (act_type == ORC_ACT_RPM) ? clampd(cmd[c], 0.0, D.max_rpm) : cmd[c];
+                } else {
+                    const double tau_m = dr->tau_mot ? dr->tau_mot[i] : 0.0;
+                    const double alpha = tau_m > 0.0 ? 1.0 - exp(-dt / tau_m) : 1.0;
+                    for (int c = 0; c < 4; ++c) {
+                        const double cc = clampd(dr->scale[(ORC_DR_BIAS + c) * N + i] * cmd[c], 0.0, max_rpm_i);
+                        const double n0 = s->rpm[c * N + i];
+                        n[c] = tau_m > 0.0 ? n0 + alpha * (cc - n0) : cc;
+                    }
                 }
                 for (int c = 0; c < 4; ++c) s->rpm[c * N + i] = n[c];
 
                 double F[4], T, tau[3], R[9];
-                orc_motor(P, n, F, &T, tau);
+                orc_motor(&Pi, n, F, &T, tau);
                 orc_quat_to_rot(q, R);
-                double Fw[3] = {R[2] * T, R[5] * T, R[8] * T - P->m * P->g};
-                if (aero_mask & ORC_AERO_GND) Fw[2] += orc_ground_effect(P, &D, n, p[2], q);
+                double Fw[3] = {R[2] * T, R[5] * T, R[8] * T - Pi.m * Pi.g};
+                if (aero_mask & ORC_AERO_GND) Fw[2] += orc_ground_effect(&Pi, &D, n, p[2], q);
                 if (aero_mask & ORC_AERO_DRAG) {
                     double Fd[3];
-                    orc_drag(P, n, q, v, Fd);
+                    orc_drag(&Pi, n, q, v, Fd);
                     for (int c = 0; c < 3; ++c) Fw[c] += Fd[c];
                 }
                 if (aero_mask & ORC_AERO_DW) {
@@ -515,10 +583,10 @@ int orc_step(const orc_params *P, double dt, uint32_t aero_mask, int act_type, i
                     for (int j = env_offsets[e]; j < env_offsets[e + 1]; ++j) {
                         if (j == i) continue;
                         const double pj[3] = {p_pre[0 * N + j], p_pre[1 * N + j], p_pre[2 * N + j]};
-                        Fw[2] += orc_downwash_pair(P, pi_, pj);
+                        Fw[2] += orc_downwash_pair(&Pi, pi_, pj);
                     }
                 }
-                orc_integrate(P, dt, Fw, tau, p, q, v, w);
+                orc_integrate(&Pi, dt, Fw, tau, p, q, v, w);
                 for (int c = 0; c < 3; ++c) {
                     s->p[c * N + i] = p[c];
                     s->v[c * N + i] = v[c];
@@ -540,6 +608,34 @@ int orc_step(const orc_params *P, double dt, uint32_t aero_mask, int act_type, i
     }
     free(p_pre);
     return 0;
+}
+
+/* One call advances every drone n_steps times.  Per step (all drones use the
+ * pre-step positions of the others for the downwash, i.e. synchronously):
+ *   rotor speeds (RPM action clipped to [0, MAX_RPM], or the PID every
+ *   ctrl_decim steps with phase (step0 + k) mod ctrl_decim = 0, held between),
+ *   motor model, F_w = R (0,0,T) - m g z_hat, optional ground effect, drag and
+ *   downwash (each env's drones in ascending index), Newton-Euler, exp map,
+ *   optional KIN observation [p, q, roll/pitch/yaw, v, omega, n] to slot
+ *   k mod n_obs_slots.  Layouts: action [n_act][4][N] with n_act = n_steps
+ *   when action_per_step else 1; obs [slot][20][N]. */
+int orc_step(const orc_params *P, double dt, uint32_t aero_mask, int act_type, int ctrl_decim,
+             int n_envs, const int32_t *env_offsets, int n_drones, orc_state *s,
+             const double *action, int action_per_step, double *obs, int n_obs_slots,
+             int n_steps, int64_t step0, int n_threads)
+{
+    return step_impl(P, dt, aero_mask, act_type, ctrl_decim, n_envs, env_offsets, n_drones, s, action,
+                     action_per_step, obs, n_obs_slots, n_steps, step0, n_threads, NULL);
+}
+
+int orc_step_dr(const orc_params *P, double dt, uint32_t aero_mask, int act_type, int ctrl_decim,
+                int n_envs, const int32_t *env_offsets, int n_drones, orc_state *s,
+                const double *action, int action_per_step, double *obs, int n_obs_slots,
+                int n_steps, int64_t step0, int n_threads, const orc_dr *dr)
+{
+    if (!dr) return -1;
+    return step_impl(P, dt, aero_mask, act_type, ctrl_decim, n_envs, env_offsets, n_drones, s, action,
+                     action_per_step, obs, n_obs_slots, n_steps, step0, n_threads, dr);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -645,7 +741,9 @@ int orc_step_rk4(const orc_params *P, double dt, uint32_t aero_mask, int act_typ
             if (act_type == ORC_ACT_RPM) {
                 for (int c = 0; c < 4; ++c) n[c] = clampd(act[c * N + i], 0.0, D.max_rpm);
             } else if (do_pid) {
-                controller(P, &D, act_type, dt * ctrl_decim, N, i, act, p, q, v, w, s, n);
+                double cmd[7];
+                for (int c = 0; c < rows; ++c) cmd[c] = act[c * N + i];
+                controller(P, &D, act_type, dt * ctrl_decim, N, i, cmd, p, q, v, w, s, n);
             } else {
                 for (int c = 0; c < 4; ++c) n[c] = s->rpm[c * N + i];
             }
@@ -1090,7 +1188,9 @@ int orc_step_surrogate(const orc_params *P, double dt, int act_type, int ctrl_de
                 if (act_type == ORC_ACT_RPM) {
                     for (int c = 0; c < 4; ++c) n[c] = clampd(act[c * N + i], 0.0, D.max_rpm);
                 } else if (do_pid) {
-                    controller(P, &D, act_type, dt * ctrl_decim, N, i, act, p, q, v, w, s, n);
+                    double cmd[7];
+                    for (int c = 0; c < rows; ++c) cmd[c] = act[c * N + i];
+                    controller(P, &D, act_type, dt * ctrl_decim, N, i, cmd, p, q, v, w, s, n);
                 } else {
                     for (int c = 0; c < 4; ++c) n[c] = s->rpm[c * N + i];
                 }

@@ -15,6 +15,10 @@
  *   - HOVER_RPM / MAX_RPM                : Sec. "Drone Models", Table "Drone model parameters"
  *   - cascaded PID                       : Sec. "Control", Eq. (9), Table "Default PIDControl gains"
  *   - KIN observation                    : Sec. "Observation types"
+ *   - VEL / ATTITUDE / DSL-style PID     : Table "Action types", Sec. "Control"
+ *   - classic RK4 variant                : Table "Physics modes"
+ *   - domain randomisation               : Sec. "Domain randomization",
+ *                                          Table "Recommended domain-randomization ranges"
  * Readings of silent / ambiguous passages are noted at each routine.
  *
  * Parity status: every routine is pinned by CPU tests (closed forms,
@@ -55,7 +59,25 @@ typedef struct orc_state {
     double *pid_int; /* [6][n] position (0..2) and attitude (3..5) sums   */
     double *rpm;     /* [4][n] rotor speeds applied in the last step, RPM */
     double *ctl;     /* [4][n] DSL rate-limited setpoint x, y, z, yaw (DSL only) */
+    /* domain randomisation only (orc_step_dr): */
+    double *rpm_cmd;    /* [4][n] controller output held between updates (controller actions) */
+    double *act_hist;   /* [ORC_DR_HIST][rows][n] action ring (with action latency) */
+    int32_t *act_count; /* [n] actions entered since the ring was cleared (with latency) */
 } orc_state;
+
+/* Domain randomisation (Table "Recommended domain-randomization ranges"):
+ * per-drone multiplicative factors, motor lag and action latency. */
+enum {
+    ORC_DR_M, ORC_DR_J, ORC_DR_L, ORC_DR_KF, ORC_DR_KM, ORC_DR_DRAG, ORC_DR_GND, ORC_DR_C1,
+    ORC_DR_MAXRPM, ORC_DR_G, ORC_DR_BIAS, /* 4 rows: per-motor bias */
+    ORC_DR_NSCALE = ORC_DR_BIAS + 4
+};
+#define ORC_DR_HIST 32
+typedef struct orc_dr {
+    const double *scale;   /* [ORC_DR_NSCALE][n] */
+    const double *tau_mot; /* [n] motor time constant, s (0 = no lag); nullable */
+    const int32_t *delay;  /* [n] action latency in steps, 0..ORC_DR_HIST-1; nullable */
+} orc_dr;
 
 enum { ORC_AERO_GND = 1, ORC_AERO_DRAG = 2, ORC_AERO_DW = 4, ORC_AERO_SURROGATE = 8 };
 enum { ORC_ACT_RPM = 0, ORC_ACT_PID = 1, ORC_ACT_VEL = 2, ORC_ACT_ATTITUDE = 3, ORC_ACT_DSL = 4 };
@@ -92,6 +114,11 @@ int orc_step(const orc_params *P, double dt, uint32_t aero_mask, int act_type, i
              int n_envs, const int32_t *env_offsets, int n_drones, orc_state *s,
              const double *action, int action_per_step, double *obs, int n_obs_slots,
              int n_steps, int64_t step0, int n_threads);
+
+int orc_step_dr(const orc_params *P, double dt, uint32_t aero_mask, int act_type, int ctrl_decim,
+                int n_envs, const int32_t *env_offsets, int n_drones, orc_state *s,
+                const double *action, int action_per_step, double *obs, int n_obs_slots,
+                int n_steps, int64_t step0, int n_threads, const orc_dr *dr);
 
 int orc_step_rk4(const orc_params *P, double dt, uint32_t aero_mask, int act_type, int ctrl_decim,
                  int n_envs, const int32_t *env_offsets, int n_drones, orc_state *s,
