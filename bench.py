@@ -43,8 +43,9 @@ OBS_BYTES = 80             # 20 float32 per drone-step
 STATE_BYTES = 2 * 4 * 23   # state read + written once per launch (p,q,v,w,pid_int,rpm)
 
 
-KERNEL_SOURCES = ("paper_2606_08039_amd/csrc/md_step.hip", "paper_2606_08039_amd/csrc/md_physics.h",
-                  "paper_2606_08039_amd/csrc/md_internal.h", "paper_2606_08039_amd/csrc/md_api.cpp")
+KERNEL_SOURCES = ("paper_2606_08039_amd/csrc/md_step.hip", "paper_2606_08039_amd/csrc/md_sweep.h",
+                  "paper_2606_08039_amd/csrc/md_physics.h", "paper_2606_08039_amd/csrc/md_internal.h",
+                  "paper_2606_08039_amd/csrc/md_api.cpp")
 
 
 def kernel_source_hash():
@@ -149,34 +150,51 @@ def cpu_baseline(w, with_obs, seconds_target=12.0):
                       % (envs, ds // steps, steps, threads, dtm)}
 
 
-def surrogate_leg(args, w, p, with_obs):
-    """The same rollouts with the learned residual in place of Eq. 4-6
-    (fallback near the downwash singularity, 1/64 of drone-steps judged
-    against the plain terms)."""
+def timed_rollouts(args, w, p, with_obs, mask=None, integrator=None, surrogate_weights=None,
+                   tune=True, config=None, dr=None):
+    """Warm up, then time args.steps rollouts (one md_step call of w["n_steps"]
+    physics steps each) on torch's current stream, which is also the stream
+    the step kernels are launched on.  Returns wall seconds, the per-launch
+    kernel times (HIP events around each launch), the launch configuration
+    and the judge statistics of a surrogate context."""
     import torch
-    from paper_2606_08039_amd import md, surrogate
-    path = args.weights or surrogate.DEFAULT_WEIGHTS
-    if not os.path.exists(path):
-        return {"value": None, "note": "no trained weights at %s" % os.path.relpath(path, ROOT)}
-    flat, norm, meta = surrogate.load(path)
+    from paper_2606_08039_amd import md
     n = int(w["env_offsets"][-1])
     K = w["n_steps"]
     act = {"rpm": md.MD_ACT_RPM, "pid": md.MD_ACT_PID}[w["act_type"]]
-    ctx = md.md_create(p, w["dt"], md.MD_AERO_SURROGATE, act, w["ctrl_decim"])
+    ctx = md.md_create(p, w["dt"], w["aero_mask"] if mask is None else mask, act, w["ctrl_decim"])
     try:
+        if integrator is not None:
+            md.md_set_integrator(ctx, integrator)
         md.md_bind_layout(ctx, w["env_offsets"])
-        md.md_load_surrogate(ctx, flat, norm, 1e-3, 64)
+        if surrogate_weights is not None:
+            flat, norm = surrogate_weights
+            md.md_load_surrogate(ctx, flat, norm, 1e-3, 64)
         state = md.DeviceState.from_numpy(w["state"])
+        dr_t = None
+        if dr is not None:
+            dr_t = {k: (torch.from_numpy(v).cuda() if v is not None else None) for k, v in dr.items()}
+            state.add_dr_blocks(act)
+            md.md_set_domain_randomization(ctx, dr_t["scale"], dr_t["tau_mot"], dr_t["delay"])
         action = torch.from_numpy(np.ascontiguousarray(w["action"], dtype=np.float32)).cuda()
         obs = torch.empty((K, 20, n), dtype=torch.float32, device="cuda") if with_obs else None
         n_slots = K if with_obs else 0
         stream = torch.cuda.current_stream()
+        cfg = None
+        if config is not None and surrogate_weights is None:
+            md.md_set_launch_config(ctx, **config)
+            cfg = md.md_get_launch_config(ctx)
+        elif tune and not args.no_tune and surrogate_weights is None:
+            # untimed: choose the launch configuration on scratch copies of the state
+            cfg = md.md_autotune(ctx, state, action, w["action_per_step"], n_steps=min(K, 50),
+                                 stream=stream, cache_path="")
         step0 = 0
         for _ in range(args.warmup):
             md.md_step(ctx, state, action, w["action_per_step"], obs, n_slots, K, step0, stream)
             step0 += K
         torch.cuda.synchronize()
-        md.md_judge_reset(ctx)
+        if surrogate_weights is not None:
+            md.md_judge_reset(ctx)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(args.steps)]
         t0 = time.perf_counter()
@@ -187,19 +205,66 @@ def surrogate_leg(args, w, p, with_obs):
             step0 += K
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        kms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-        j = md.md_judge_stats(ctx)
+        kernel_ms = [a.elapsed_time(b) for a, b in ev]
+        judge = md.md_judge_stats(ctx) if surrogate_weights is not None else None
+        # untimed sanity check of the final state
+        fin = torch.isfinite(torch.cat([state.t[k] for k in ("p", "q", "v", "w")])).all(dim=0)
+        speed = torch.linalg.vector_norm(state.t["v"], dim=0)
+        check_state = {"nonfinite_drones": int((~fin).sum()),
+                       "max_speed": float(torch.where(fin, speed, torch.zeros_like(speed)).max()),
+                       "below_ground": int((state.t["p"][2] < 0).sum())}
     finally:
         md.md_destroy(ctx)
+    return wall, kernel_ms, cfg, judge, check_state
+
+
+def surrogate_leg(args, w, p, with_obs):
+    """The same rollouts with the learned residual in place of Eq. 4-6
+    (fallback near the downwash singularity, 1/64 of drone-steps judged
+    against the plain terms)."""
+    from paper_2606_08039_amd import md, surrogate
+    path = args.weights or surrogate.DEFAULT_WEIGHTS
+    if not os.path.exists(path):
+        return {"value": None, "note": "no trained weights at %s" % os.path.relpath(path, ROOT)}
+    flat, norm, meta = surrogate.load(path)
+    n = int(w["env_offsets"][-1])
+    K = w["n_steps"]
+    wall, kernel_ms, _, j, chk = timed_rollouts(args, w, p, with_obs, mask=md.MD_AERO_SURROGATE,
+                                                surrogate_weights=(flat, norm))
+    kms = float(np.mean(kernel_ms))
     ds = float(n) * K * args.steps
     mfma_flop = 86016.0 * n * K
     return {"value": ds / wall, "unit": "drone-steps/s", "ms_per_step": wall / args.steps * 1e3,
             "kernel_ms_avg": kms,
             "mfma_tflops": mfma_flop / (kms * 1e-3) / 1e12,
             "judge_force_rel_err": j["force_rel_err"], "judged_drone_steps": j["n_judged"],
+            "judge_nonfinite": j["n_nonfinite"], "final_state": chk,
             "fallback_fraction": j["n_fallback"] / max(j["n_drone_steps"], 1.0),
             "held_out_force_rel_err": meta.get("eps_held_out"),
             "weights": os.path.relpath(path, ROOT)}
+
+
+def dr_leg(args, w, p, with_obs):
+    """The same rollouts with per-drone domain randomisation (Table
+    "Recommended domain-randomization ranges": factors, motor lag, action
+    latency through the history ring)."""
+    from paper_2606_08039_amd import workloads as wl
+    n = int(w["env_offsets"][-1])
+    wall, kernel_ms, cfg, _, chk = timed_rollouts(args, w, p, with_obs, dr=wl.domain_randomization(w, 50))
+    return {"value": float(n) * w["n_steps"] * args.steps / wall, "unit": "drone-steps/s",
+            "ms_per_step": wall / args.steps * 1e3, "kernel_ms_avg": float(np.mean(kernel_ms)),
+            "launch_config": cfg, "final_state": chk}
+
+
+def rk4_leg(args, w, p, with_obs):
+    """The same rollouts with the classic Runge-Kutta integrator (four force
+    evaluations, four neighbour sweeps per physics step)."""
+    from paper_2606_08039_amd import md
+    n = int(w["env_offsets"][-1])
+    wall, kernel_ms, cfg, _, chk = timed_rollouts(args, w, p, with_obs, integrator=md.MD_INTEG_RK4)
+    return {"value": float(n) * w["n_steps"] * args.steps / wall, "unit": "drone-steps/s",
+            "ms_per_step": wall / args.steps * 1e3, "kernel_ms_avg": float(np.mean(kernel_ms)),
+            "launch_config": cfg, "final_state": chk}
 
 
 def main():
@@ -211,6 +276,12 @@ def main():
     ap.add_argument("--no-obs", action="store_true", help="skip the KIN-20 writes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-aero leg")
+    ap.add_argument("--no-rk4", action="store_true", help="skip the Runge-Kutta leg")
+    ap.add_argument("--no-dr", action="store_true", help="skip the domain-randomisation leg")
+    ap.add_argument("--no-tune", action="store_true", help="default launch configuration, no autotuning")
+    ap.add_argument("--config", default=None,
+                    help="launch configuration lanes_per_drone,unroll,waves_per_group,pair_symmetric "
+                         "for the plain leg (instead of autotuning)")
     ap.add_argument("--weights", default=None, help="surrogate weights file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
@@ -231,37 +302,14 @@ def main():
     with_obs = (cfg["obs"] != "none") and not args.no_obs
     n = int(w["env_offsets"][-1])
     K = w["n_steps"]
-    act = {"rpm": md.MD_ACT_RPM, "pid": md.MD_ACT_PID}[w["act_type"]]
 
-    ctx = md.md_create(p, w["dt"], w["aero_mask"], act, w["ctrl_decim"])
-    md.md_bind_layout(ctx, w["env_offsets"])
-    state = md.DeviceState.from_numpy(w["state"])
-    action = torch.from_numpy(np.ascontiguousarray(w["action"], dtype=np.float32)).cuda()
-    obs = torch.empty((K, 20, n), dtype=torch.float32, device="cuda") if with_obs else None
-    n_slots = K if with_obs else 0
-    stream = torch.cuda.current_stream()
+    config = None
+    if args.config:
+        v = [int(x) for x in args.config.split(",")]
+        config = dict(lanes_per_drone=v[0], unroll=v[1], waves_per_group=v[2], pair_symmetric=v[3])
+    wall, kernel_ms, launch_cfg, _, check_state = timed_rollouts(args, w, p, with_obs, tune=not args.no_tune,
+                                                                 config=config)
 
-    step0 = 0
-    for _ in range(args.warmup):
-        md.md_step(ctx, state, action, w["action_per_step"], obs, n_slots, K, step0, stream)
-        step0 += K
-    torch.cuda.synchronize()
-
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ev[i][0].record(stream)
-        md.md_step(ctx, state, action, w["action_per_step"], obs, n_slots, K, step0, stream)
-        ev[i][1].record(stream)
-        step0 += K
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kernel_ms = [a.elapsed_time(b) for a, b in ev]
-    md.md_destroy(ctx)
-
-    wall = t1 - t0
     ds = float(n) * K * args.steps
     value = ds / wall
     flop, bytes_ = algorithmic_counts(w, with_obs)
@@ -295,6 +343,8 @@ def main():
         "roofline_alu": {"bound": "alu", "achieved": round(alu, 3), "peak": FP32_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": round(alu / FP32_PEAK_TFLOPS, 4)},
         "kernel_ms_avg": kavg * 1e3,
+        "launch_config": launch_cfg,
+        "final_state": check_state,
         "algorithmic_bytes_per_launch": bytes_,
         "algorithmic_flop_per_launch": flop,
     }
@@ -302,6 +352,12 @@ def main():
         out["surrogate"] = surrogate_leg(args, w, p, with_obs)
         if out["surrogate"].get("value"):
             out["surrogate"]["speed_vs_plain"] = out["surrogate"]["value"] / value
+    if not args.no_rk4:
+        out["rk4"] = rk4_leg(args, w, p, with_obs)
+        out["rk4"]["speed_vs_euler"] = out["rk4"]["value"] / value
+    if not args.no_dr:
+        out["domain_randomization"] = dr_leg(args, w, p, with_obs)
+        out["domain_randomization"]["speed_vs_plain"] = out["domain_randomization"]["value"] / value
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)

@@ -92,9 +92,18 @@ typedef struct md_derived {
  * may be NULL for RPM actions); rpm[4] rotor speeds applied in the last
  * step (the held command between controller updates); ctl[4] the DSL
  * controller's rate-limited setpoint x, y, z, yaw (MD_ACT_DSL only, may be
- * NULL otherwise; initialise it to the drone's position and yaw). */
+ * NULL otherwise; initialise it to the drone's position and yaw).
+ * With domain randomisation (md_set_domain_randomization) three more blocks:
+ * rpm_cmd[4] the controller output held between updates (controller actions
+ * only; rpm then holds the lagged actual speeds), act_hist
+ * [MD_DR_HIST][rows][n_drones] the action-latency ring and act_count
+ * (int32 [n_drones]) the number of actions entered into it, saturating at
+ * MD_DR_HIST (both only with per-drone delays; zero act_count to start an
+ * episode).  They may be NULL otherwise. */
 typedef struct md_state {
     float *p, *q, *v, *w, *pid_int, *rpm, *ctl;
+    float *rpm_cmd, *act_hist;
+    int32_t *act_count;
 } md_state;
 
 typedef struct md_ctx md_ctx;
@@ -147,6 +156,64 @@ md_status md_bind_layout(md_ctx *ctx, const int32_t *h_env_offsets, int n_envs, 
 md_status md_step(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
                   float *d_obs, int n_obs_slots, int n_steps, int64_t step0, void *stream);
 
+/* Domain randomisation (Sec. "Domain randomization", Table "Recommended
+ * domain-randomization ranges"), per drone, for the semi-implicit Euler step.
+ *   scale [MD_DR_NSCALE][n_drones] factors on the nominal constants: mass,
+ *     inertia (all three moments), arm length, kf, km, drag (c_xy and c_z),
+ *     C_gnd, C1 (the downwash a drone receives), MAX_RPM, g, and four
+ *     per-motor bias factors on the commanded rotor speeds;
+ *   tau_mot [n_drones] motor time constant in s (0: no lag), nullable;
+ *   delay [n_drones] action latency in steps, 0..MD_DR_HIST-1, nullable.
+ * Per step and drone: the step's action rows enter the act_hist ring at slot
+ * (step0 + k) mod MD_DR_HIST and the rows used are those entered
+ * min(delay, act_count - 1) steps earlier; the command (the RPM action, or
+ * the controller's output at controller steps, held in rpm_cmd) is
+ * multiplied by the bias, clipped to [0, factor x MAX_RPM] and passed
+ * through the lag n <- n + (1 - e^{-dt/tau})(c - n) (n = c for tau = 0);
+ * Eq. 1-7 then use the drone's constants.  Controllers keep the nominal
+ * constants; h_clip stays nominal.  All factors 1, tau 0 and delay 0
+ * reproduce the plain step.  The arrays are device memory owned by the
+ * caller and read by every later md_step until the next call; NULL turns
+ * randomisation off.  Errors: MD_E_INVALID_ARG for a null scale,
+ * MD_E_UNSUPPORTED with MD_AERO_SURROGATE or MD_INTEG_RK4. */
+#define MD_DR_M 0
+#define MD_DR_J 1
+#define MD_DR_L 2
+#define MD_DR_KF 3
+#define MD_DR_KM 4
+#define MD_DR_DRAG 5
+#define MD_DR_GND 6
+#define MD_DR_C1 7
+#define MD_DR_MAXRPM 8
+#define MD_DR_G 9
+#define MD_DR_BIAS 10 /* rows 10..13: motors 0..3 */
+#define MD_DR_NSCALE 14
+#define MD_DR_HIST 32
+typedef struct md_dr {
+    const float *scale;
+    const float *tau_mot;
+    const int32_t *delay;
+} md_dr;
+md_status md_set_domain_randomization(md_ctx *ctx, const md_dr *dr);
+
+/* Integrator of md_step (default MD_INTEG_EULER).  MD_INTEG_RK4 is the
+ * classic fourth-order Runge-Kutta step, the integrator of the paper's MuJoCo
+ * physics modes (Table "Physics modes"): rotor speeds, thrust and torques are
+ * held over the step; the rigid-body state x = (p, v, q, w) with
+ * p' = v, v' = F(x) / m, q' = q (x) [0, w] / 2, w' = J^-1 (tau - w x J w)
+ * advances by dt/6 (k1 + 2 k2 + 2 k3 + k4); the aerodynamic terms of Eq. 4-6
+ * are evaluated at every stage (the downwash from every drone's stage
+ * position), rotations from the normalised stage quaternion, and the
+ * quaternion is renormalised after the step.  Observations, controllers and
+ * all other arguments of md_step behave as with MD_INTEG_EULER.  Errors:
+ * MD_E_INVALID_ARG for an unknown value, MD_E_UNSUPPORTED with
+ * MD_AERO_SURROGATE or domain randomisation.  Switching to MD_INTEG_RK4 resets a launch
+ * configuration with lanes_per_drone > 1 to the default. */
+#define MD_INTEG_EULER 0
+#define MD_INTEG_RK4 1
+md_status md_set_integrator(md_ctx *ctx, int integrator);
+md_status md_get_integrator(const md_ctx *ctx, int *out);
+
 /* ------------------------------------------------------------------------
  * Launch configuration, autotuning and captured rollouts.
  * ---------------------------------------------------------------------- */
@@ -165,16 +232,18 @@ typedef struct md_launch_config {
 
 md_status md_get_launch_config(const md_ctx *ctx, md_launch_config *out);
 /* MD_E_INVALID_ARG if the configuration cannot hold the bound layout's
- * largest environment or its LDS need exceeds 64 KB. */
+ * largest environment or its LDS need exceeds 64 KB, or if lanes_per_drone
+ * is not 1 for MD_INTEG_RK4 with the downwash term. */
 md_status md_set_launch_config(md_ctx *ctx, md_launch_config *cfg);
 
 /* Time every valid launch configuration for the bound layout on scratch
  * copies of s (s itself is not modified) over n_steps steps of d_action,
  * and select the fastest.  The choice is remembered in the JSON file
  * cache_path (NULL: the MD_AUTOTUNE_CACHE environment variable; empty: no
- * cache) under a signature of the layout, mask and action type; a cached
+ * cache) under a signature of the layout, mask, action type and integrator; a cached
  * choice is reused unless force is non-zero.  Synchronous; allocates two
- * temporary state copies. */
+ * temporary state copies.  With the environment variable
+ * MD_AUTOTUNE_VERBOSE=1 every candidate's time is printed to stderr. */
 md_status md_autotune(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
                       int n_steps, int64_t step0, void *stream, const char *cache_path, int force);
 
@@ -197,7 +266,7 @@ void md_graph_destroy(md_graph *g);
 /* ------------------------------------------------------------------------
  * Learned aerodynamic residual (surrogate for Eq. 4-6).
  *
- * Network: 64 inputs (59 features, zero padded) -> 128 -> 128 -> 128 -> 6,
+ * Network: 64 inputs (60 features, zero padded) -> 128 -> 128 -> 128 -> 6,
  * SiLU on the hidden layers; bfloat16 operands with fp32 accumulation (the
  * matrix products run on MFMA).  Inputs are standardised in fp32,
  * x' = (x - x_mean) * x_inv_std, then rounded to bfloat16; the 6 outputs are
@@ -256,7 +325,7 @@ md_status md_mlp_adam(md_mlp *m, float lr, float beta1, float beta2, float eps, 
  * host fp32, layouts as for md_mlp_set_params / md_mlp_set_norm) into a
  * context created with MD_AERO_SURROGATE.  The library keeps bfloat16
  * copies on the device (about 85 KB).  Fallback: a drone with a same-env
- * neighbour among its 8 nearest that sits above it by less than dz_ood
+ * neighbour among its 8 laterally nearest that sits above it by less than dz_ood
  * metres (0 < dz < dz_ood, where Eq. 6 is singular) takes the plain ground
  * effect + drag + downwash for that step.  Judge: every judge_stride-th
  * drone-step (a power of two; 0 = off) also evaluates the plain terms and
@@ -269,8 +338,9 @@ md_status md_load_surrogate_mlp(md_ctx *ctx, const md_mlp *m, float dz_ood, int 
 /* Training samples at the current state (bound layout, current device):
  * d_X [N][64] fp32 raw surrogate inputs (v_body[3], world up axis in the
  * body frame[3], rpm/HOVER_RPM[4], for the 8 nearest same-environment
- * neighbours by 3-D distance (ascending, ties to the lower index, zeros when
- * missing) p_j - p_i[3] and v_j - v_i[3], z[1], zeros[5]);
+ * neighbours by horizontal distance (ascending, ties to the lower index,
+ * zeros when missing) p_j - p_i[3] and v_j - v_i[3], z[1], ground proximity
+ * (h_clip / max(z, h_clip))^2 [1], zeros[4]);
  * d_Y [N][6] fp32: the aerodynamic force of the effects in aero_mask (a
  * subset of GND|DRAG|DW) in the body frame, then the torque (identically 0
  * for these centre-of-mass forces); d_nbr (nullable) [N][8] int32 neighbour
@@ -282,10 +352,13 @@ md_status md_datagen(md_ctx *ctx, const md_state *s, uint32_t aero_mask, float *
  * n_judged judged drone-steps; force_err2 = sum |F_surrogate - F_plain|^2;
  * force_ref2 = sum |F_plain|^2; torque_err2 = sum |tau_surrogate|^2 (plain
  * torque is 0); n_fallback drone-steps that took the plain terms;
- * n_drone_steps all drone-steps stepped; force_rel_err = sqrt(err2 / ref2). */
+ * n_drone_steps all drone-steps stepped; force_rel_err = sqrt(err2 / ref2)
+ * (NaN when nothing was judged); n_nonfinite judged drone-steps whose
+ * surrogate or plain force was not finite (left out of the sums and of
+ * n_judged). */
 typedef struct md_judge {
     double n_judged, force_err2, force_ref2, torque_err2, n_fallback, n_drone_steps;
-    double force_rel_err;
+    double force_rel_err, n_nonfinite;
 } md_judge;
 md_status md_judge_stats(md_ctx *ctx, md_judge *out);
 md_status md_judge_reset(md_ctx *ctx);

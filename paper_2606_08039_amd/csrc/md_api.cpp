@@ -241,7 +241,8 @@ md_status launch(md_ctx *ctx, const md_state *s, const float *d_action, int acti
     if (rc != MD_OK) return rc;
     StepArgs a;
     a.c = ctx->kc;
-    a.s = StatePtr{s->p, s->q, s->v, s->w, s->pid_int, s->rpm, s->ctl};
+    a.s = StatePtr{s->p, s->q, s->v, s->w, s->pid_int, s->rpm, s->ctl, s->rpm_cmd, s->act_hist, s->act_count};
+    a.dr = ctx->dr;
     a.action = d_action;
     a.act_step_stride = action_per_step ? (long long)action_rows(ctx->act) * ctx->n_drones : 0;
     a.obs = (n_obs_slots > 0) ? d_obs : nullptr;
@@ -250,8 +251,10 @@ md_status launch(md_ctx *ctx, const md_state *s, const float *d_action, int acti
     a.step0 = step0;
     a.N = ctx->n_drones;
     a.bins = BinTables{bs->d_slot, bs->d_mmax};
-    a.tstride = (ctx->max_m + 1) | 1;  // odd: the column writes of a wave spread over banks
-    hipError_t e = launch_step(a, ctx->mask, ctx->act, cfg, bs->n_bins, bs->slots, st);
+    a.tstride = pair_stride(ctx->max_m);
+    hipError_t e = (ctx->integ == MD_INTEG_RK4) ? launch_step_rk4(a, ctx->mask, ctx->act, cfg, bs->n_bins, bs->slots, st)
+                   : ctx->dr_on                ? launch_step_dr(a, ctx->mask, ctx->act, cfg, bs->n_bins, bs->slots, st)
+                                               : launch_step(a, ctx->mask, ctx->act, cfg, bs->n_bins, bs->slots, st);
     if (e != hipSuccess) {
         ctx->err = hip_msg("step kernel launch", e);
         return MD_E_HIP;
@@ -424,6 +427,52 @@ md_status md_bind_layout(md_ctx *ctx, const int32_t *h_env_offsets, int n_envs, 
     return md::build_bins(ctx, md::slots_for(ctx, ctx->cfg), &bs);
 }
 
+md_status md_set_integrator(md_ctx *ctx, int integrator) {
+    if (!ctx) return MD_E_INVALID_ARG;
+    if (integrator != MD_INTEG_EULER && integrator != MD_INTEG_RK4) {
+        ctx->err = "md_set_integrator: unknown integrator";
+        return MD_E_INVALID_ARG;
+    }
+    if (integrator == MD_INTEG_RK4 && ((ctx->mask & MD_AERO_SURROGATE) || ctx->dr_on)) {
+        ctx->err = "md_set_integrator: the learned residual and domain randomisation run with the "
+                   "semi-implicit Euler step only";
+        return MD_E_UNSUPPORTED;
+    }
+    ctx->integ = integrator;
+    if (ctx->has_layout && !md::cfg_valid(ctx, ctx->cfg)) {
+        // the Runge-Kutta kernel sweeps neighbours with one lane per drone
+        ctx->cfg = md::default_cfg(ctx);
+        ctx->tuned = false;
+    }
+    return MD_OK;
+}
+
+md_status md_set_domain_randomization(md_ctx *ctx, const md_dr *dr) {
+    if (!ctx) return MD_E_INVALID_ARG;
+    if (!dr) {
+        ctx->dr_on = false;
+        ctx->dr = md::DrPtr{nullptr, nullptr, nullptr};
+        return MD_OK;
+    }
+    if (!dr->scale) {
+        ctx->err = "md_set_domain_randomization: null scale array";
+        return MD_E_INVALID_ARG;
+    }
+    if ((ctx->mask & MD_AERO_SURROGATE) || ctx->integ == MD_INTEG_RK4) {
+        ctx->err = "md_set_domain_randomization: supported with the plain semi-implicit Euler step only";
+        return MD_E_UNSUPPORTED;
+    }
+    ctx->dr = md::DrPtr{dr->scale, dr->tau_mot, dr->delay};
+    ctx->dr_on = true;
+    return MD_OK;
+}
+
+md_status md_get_integrator(const md_ctx *ctx, int *out) {
+    if (!ctx || !out) return MD_E_INVALID_ARG;
+    *out = ctx->integ;
+    return MD_OK;
+}
+
 md_status md_step(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
                   float *d_obs, int n_obs_slots, int n_steps, int64_t step0, void *stream) {
     if (!ctx) return MD_E_INVALID_ARG;
@@ -439,6 +488,12 @@ md_status md_step(md_ctx *ctx, const md_state *s, const float *d_action, int act
     if (!s->p || !s->q || !s->v || !s->w || !s->rpm || (ctx->act != MD_ACT_RPM && !s->pid_int) ||
         (ctx->act == MD_ACT_DSL && !s->ctl) || !d_action || (n_obs_slots > 0 && !d_obs)) {
         ctx->err = "md_step: null state block, action or observation pointer";
+        return MD_E_INVALID_ARG;
+    }
+    if (ctx->dr_on && ((ctx->act != MD_ACT_RPM && !s->rpm_cmd) ||
+                       (ctx->dr.delay && (!s->act_hist || !s->act_count)))) {
+        ctx->err = "md_step: domain randomisation needs rpm_cmd (controller actions) and, with delays, "
+                   "act_hist and act_count";
         return MD_E_INVALID_ARG;
     }
     if (ctx->mask & MD_AERO_SURROGATE) return md::surrogate_step(ctx, s, d_action, action_per_step, d_obs,

@@ -33,6 +33,9 @@ struct md_ctx {
     uint32_t mask = 0;
     int act = 0;
     int decim = 1;
+    int integ = MD_INTEG_EULER;
+    bool dr_on = false;
+    md::DrPtr dr{nullptr, nullptr, nullptr};
     int device = 0;
     int n_cu = 0;
     md::KConst kc{};
@@ -60,6 +63,7 @@ md_status launch(md_ctx *ctx, const md_state *s, const float *d_action, int acti
 
 // Build the bin tables the next md_step will use (synchronous uploads).
 md_status prepare_launch(md_ctx *ctx);
+bool cfg_valid(const md_ctx *ctx, const LaunchCfg &c);
 md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step, int n_steps,
                    int64_t step0, hipStream_t st, const char *path, int force);
 

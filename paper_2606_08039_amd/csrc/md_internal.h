@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "md.h"
+
 namespace md {
 
 // Per-context float32 constants, precomputed on the host in double and passed
@@ -27,9 +29,18 @@ struct KConst {
     int decim;
 };
 
-// Six SoA device pointers of md_state.
+// SoA device pointers of md_state.
 struct StatePtr {
     float *p, *q, *v, *w, *pid_int, *rpm, *ctl;
+    float *rpm_cmd, *act_hist;  // domain randomisation: held command, action ring
+    int32_t *act_count;         // domain randomisation: ring fill per drone
+};
+
+// Domain randomisation inputs (md_dr), device pointers.
+struct DrPtr {
+    const float *scale;     // [MD_DR_NSCALE][N]
+    const float *tau_mot;   // [N] or null
+    const int32_t *delay;   // [N] or null
 };
 
 // Action rows per action type (MD_ACT_DSL carries a feed-forward acceleration).
@@ -58,7 +69,14 @@ struct StepArgs {
     int N;
     BinTables bins;
     int tstride;  // row stride (floats) of the pair-term matrix in LDS (sym sweep)
+    DrPtr dr;     // domain randomisation (used by the DR instantiation only)
 };
+
+// Row stride (floats) of the pair-term matrix of the pair-symmetric sweep: a
+// multiple of 4 (rows are summed with 16-byte LDS reads) that holds the
+// largest environment; the odd lane stride ts + 1 of its row and column
+// writes spreads a wave over the LDS banks.
+__host__ __device__ constexpr int pair_stride(int max_m) { return ((max_m + 3) / 4) * 4 > 0 ? ((max_m + 3) / 4) * 4 : 4; }
 
 // Launch configuration chosen per (shape, mask) by the autotuner.
 struct LaunchCfg {
@@ -70,5 +88,11 @@ struct LaunchCfg {
 
 hipError_t launch_step(const StepArgs &a, uint32_t mask, int act, const LaunchCfg &cfg,
                        int n_bins, int slots, hipStream_t stream);
+// Same contract with per-drone domain randomisation (a.dr).
+hipError_t launch_step_dr(const StepArgs &a, uint32_t mask, int act, const LaunchCfg &cfg,
+                          int n_bins, int slots, hipStream_t stream);
+// Same contract with the classic Runge-Kutta integrator (lanes per drone 1).
+hipError_t launch_step_rk4(const StepArgs &a, uint32_t mask, int act, const LaunchCfg &cfg,
+                           int n_bins, int slots, hipStream_t stream);
 
 }  // namespace md

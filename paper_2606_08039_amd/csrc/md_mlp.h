@@ -9,7 +9,7 @@
 
 namespace md {
 
-constexpr int MLP_IN = 64;    // 59 features, zero padded
+constexpr int MLP_IN = 64;    // 60 features, zero padded
 constexpr int MLP_H = 128;    // three hidden layers
 constexpr int MLP_OUT = 6;    // body-frame force (3) and torque (3)
 constexpr int MLP_NPARAMS = 42118;

@@ -1,0 +1,329 @@
+// md_step_kernel.h -- the persistent, ragged-batched explicit quadrotor step
+// (gfx950), instantiated without domain randomisation in md_step.hip and
+// with it in md_step_dr.hip.
+//
+// One workgroup runs one bin: a set of whole environments packed into its
+// slots.  A drone's state lives in registers for all n_steps of the launch;
+// HBM sees the state once in and once out, the per-step actions (RPM mode)
+// and the per-step observation rows.  Positions are published to LDS every
+// step (double buffered, one barrier per step) so that each drone can sweep
+// its environment for the pairwise downwash of Eq. 6.
+//
+// Physics per step (paper: Sec. "Quadrotor Dynamics", Sec. "Physics Modes"):
+//   rotor speeds   RPM action clipped to [0, MAX_RPM] or a controller (Sec. "Control")
+//   motor model    F_i = kf n_i^2, X-mixer torques, yaw reaction torques     (Eq. 1-3)
+//   ground effect  C_gnd T (r_p / 4 max(z, h_clip))^2 while the body z axis points up (Eq. 4)
+//   drag           R (-diag(c_xy, c_xy, c_z) (sum 2 pi n_i / 60) R^T v)    (Eq. 5)
+//   downwash       sum over higher drones j of -C1 (r_p/4dz)^2 exp(-(dxy/beta)^2/2) (Eq. 6)
+//   integrator     semi-implicit Euler, body-rate exponential map, renormalise (Eq. 7)
+//
+// Domain randomisation (DR = true; Sec. "Domain randomization", Table
+// "Recommended domain-randomization ranges"): each drone carries its own
+// physical constants (mass, inertia, arm length, kf, km, drag, C_gnd, C1, g,
+// MAX_RPM as factors of the nominal ones) in registers for the launch, and
+// an actuator chain before the motor model: action latency through a ring of
+// MD_DR_HIST past actions, per-motor bias, clip to the drone's MAX_RPM, and a
+// first-order motor lag n <- n + (1 - e^{-dt/tau})(c - n).  Controllers keep
+// the nominal constants.
+#pragma once
+
+#include "md_sweep.h"
+
+namespace md {
+namespace {
+
+using namespace phys;
+
+// The drone's own constants: the nominal block with the randomised fields
+// replaced (the others stay uniform across the wave).
+__device__ __forceinline__ void dr_constants(const KConst &c, const DrPtr &dr, int N, int di, KConst &cl,
+                                             float bias[4]) {
+    const float sm = dr.scale[MD_DR_M * N + di], sJ = dr.scale[MD_DR_J * N + di];
+    const float sg = dr.scale[MD_DR_G * N + di];
+    cl.m = c.m * sm;
+    cl.m_inv = 1.f / cl.m;
+    cl.mg = cl.m * (c.g * sg);
+    cl.Jx = c.Jx * sJ;
+    cl.Jy = c.Jy * sJ;
+    cl.Jz = c.Jz * sJ;
+    cl.Jx_inv = 1.f / cl.Jx;
+    cl.Jy_inv = 1.f / cl.Jy;
+    cl.Jz_inv = 1.f / cl.Jz;
+    cl.l_arm = c.l_arm * dr.scale[MD_DR_L * N + di];
+    cl.kf = c.kf * dr.scale[MD_DR_KF * N + di];
+    cl.km = c.km * dr.scale[MD_DR_KM * N + di];
+    const float sd = dr.scale[MD_DR_DRAG * N + di];
+    cl.c_xy = c.c_xy * sd;
+    cl.c_z = c.c_z * sd;
+    cl.K_gnd = c.K_gnd * dr.scale[MD_DR_GND * N + di];
+    cl.K1 = c.K1 * dr.scale[MD_DR_C1 * N + di];
+    cl.max_rpm = c.max_rpm * dr.scale[MD_DR_MAXRPM * N + di];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) bias[k] = dr.scale[(MD_DR_BIAS + k) * N + di];
+}
+
+template <uint32_t MASK, int ACT, int LPD, int UNROLL, bool SYM, bool DR>
+__global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
+    extern __shared__ float4 lds_pos[];  // [2][2 * slots] positions; then T [slots][tstride] (SYM)
+    const KConst &c = a.c;
+    const int slots = blockDim.x / LPD;
+    const int slot = threadIdx.x / LPD;
+    const int sub = threadIdx.x - slot * LPD;
+    const int2 tab = a.bins.slot[blockIdx.x * slots + slot];
+    const int di = tab.x;
+    const bool valid = di >= 0;
+    const int lo = tab.y >> 16;
+    const int menv = tab.y & 0xffff;
+    const int mm_word = a.bins.bin_mmax[blockIdx.x];
+    const int mmax = mm_word & 0xffff;
+    const bool uniform = (mm_word >> 16) != 0;
+    const int N = a.N;
+    const bool writer = valid && (sub == 0);
+
+    Drone d{};
+    float I[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float n[4] = {0.f, 0.f, 0.f, 0.f};
+    if (valid) {
+        d.px = a.s.p[di];
+        d.py = a.s.p[N + di];
+        d.pz = a.s.p[2 * N + di];
+        d.qw = a.s.q[di];
+        d.qx = a.s.q[N + di];
+        d.qy = a.s.q[2 * N + di];
+        d.qz = a.s.q[3 * N + di];
+        d.vx = a.s.v[di];
+        d.vy = a.s.v[N + di];
+        d.vz = a.s.v[2 * N + di];
+        d.wx = a.s.w[di];
+        d.wy = a.s.w[N + di];
+        d.wz = a.s.w[2 * N + di];
+        for (int k = 0; k < 4; ++k) n[k] = a.s.rpm[k * N + di];
+        if (ACT >= 1) {
+            for (int k = 0; k < 6; ++k) I[k] = a.s.pid_int[k * N + di];
+        }
+    } else {
+        d.qw = 1.f;
+    }
+    // Physical constants of this drone (the nominal ones unless DR).
+    KConst cl = c;
+    float bias[4] = {1.f, 1.f, 1.f, 1.f};
+    float lag = 1.f;            // 1 - e^{-dt/tau}
+    bool has_lag = false;
+    int delay = 0, issued = 0;  // action latency (steps) and ring fill
+    float cmdh[4] = {0.f, 0.f, 0.f, 0.f};  // controller output held between updates
+    const bool ring = DR && a.dr.delay != nullptr;
+    if (DR && valid) {
+        dr_constants(c, a.dr, N, di, cl, bias);
+        const float tau = a.dr.tau_mot ? a.dr.tau_mot[di] : 0.f;
+        has_lag = tau > 0.f;
+        lag = has_lag ? 1.f - expf(-c.dt / tau) : 1.f;
+        if (ring) {
+            delay = a.dr.delay[di];
+            issued = a.s.act_count[di];
+        }
+        if (ACT >= 1)
+            for (int k = 0; k < 4; ++k) cmdh[k] = a.s.rpm_cmd[k * N + di];
+    }
+
+    float *tmat = (float *)(lds_pos + 4 * slots);
+    if (SYM && (MASK & 4u) && valid) {
+        // the diagonal and the padding up to the next multiple of 4 stay 0
+        tmat[slot * a.tstride + (slot - lo)] = 0.f;
+        for (int j = menv; j < ((menv + 3) & ~3); ++j) tmat[slot * a.tstride + j] = 0.f;
+    }
+    // Held waypoints (one action row for the whole launch) stay in registers:
+    // re-reading them at every controller update would fetch them from HBM
+    // again, since the observation stream evicts them from L2.
+    const bool held = a.act_step_stride == 0;
+    constexpr int ROWS = action_rows(ACT);
+    float tgt_held[ROWS];
+    float sp[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < ROWS; ++k) tgt_held[k] = 0.f;
+    if (ACT >= 1 && held && valid)
+        for (int k = 0; k < ROWS; ++k) tgt_held[k] = a.action[(long long)k * N + di];
+    if (ACT == 4 && valid)
+        for (int k = 0; k < 4; ++k) sp[k] = a.s.ctl[k * N + di];
+    // controller phase, observation slot and ring slot advance as counters
+    int phase = (ACT >= 1) ? (int)(a.step0 % (long long)c.decim) : 0;
+    int oslot = 0;
+    int hslot = (int)(a.step0 % (long long)MD_DR_HIST);
+    for (int step = 0; step < a.n_steps; ++step) {
+        float4 *buf = lds_pos + (step & 1) * (2 * slots);
+        if (MASK & 4u) {
+            if (sub == 0) buf[slot] = make_float4(d.px, d.py, d.pz, 0.f);
+            __syncthreads();
+        }
+        // ---- rotor speeds
+        const float *act = a.action + a.act_step_stride * step;
+        if (!DR) {
+            if (ACT == 0) {
+                if (valid) {
+                    for (int k = 0; k < 4; ++k) n[k] = clampf(act[(long long)k * N + di], 0.f, c.max_rpm);
+                }
+            } else {
+                if (phase == 0 && valid) {
+                    float cmd[ROWS];
+                    for (int k = 0; k < ROWS; ++k) cmd[k] = held ? tgt_held[k] : act[(long long)k * N + di];
+                    control<ACT>(c, d, cmd, I, sp, n);
+                }
+                phase = (phase + 1 == c.decim) ? 0 : phase + 1;
+            }
+        } else {
+            // action rows of this step, through the latency ring
+            const bool need = (ACT == 0) || (phase == 0) || ring;
+            float row[ROWS];
+            if (valid && need) {
+                for (int k = 0; k < ROWS; ++k)
+                    row[k] = (ACT >= 1 && held) ? tgt_held[k] : act[(long long)k * N + di];
+                if (ring) {
+                    float *h = a.s.act_hist;
+                    for (int k = 0; k < ROWS; ++k) h[((long long)hslot * ROWS + k) * N + di] = row[k];
+                    issued = min(issued + 1, MD_DR_HIST);
+                    const int dd = min(delay, issued - 1);
+                    const int from = hslot - dd + (hslot < dd ? MD_DR_HIST : 0);
+                    for (int k = 0; k < ROWS; ++k) row[k] = h[((long long)from * ROWS + k) * N + di];
+                }
+            }
+            float cmd4[4];
+            if (ACT == 0) {
+                for (int k = 0; k < 4; ++k) cmd4[k] = row[k];
+            } else {
+                if (phase == 0 && valid) control<ACT>(c, d, row, I, sp, cmdh);
+                phase = (phase + 1 == c.decim) ? 0 : phase + 1;
+                for (int k = 0; k < 4; ++k) cmd4[k] = cmdh[k];
+            }
+            if (valid) {
+                for (int k = 0; k < 4; ++k) {
+                    const float cc = clampf(bias[k] * cmd4[k], 0.f, cl.max_rpm);
+                    n[k] = has_lag ? n[k] + lag * (cc - n[k]) : cc;
+                }
+            }
+            hslot = (hslot + 1 == MD_DR_HIST) ? 0 : hslot + 1;
+        }
+        // ---- motor model and mixer (Eq. 1-3)
+        float T, tx, ty, tz;
+        motor(cl, n, T, tx, ty, tz);
+        const Rot R = rot_of(d);
+        float Fx = R.r02 * T, Fy = R.r12 * T, Fz = R.r22 * T - cl.mg;
+        // ---- ground effect (Eq. 4)
+        if (MASK & 1u) Fz += ground_effect(cl, d, R, T);
+        // ---- blade drag (Eq. 5)
+        if (MASK & 2u) {
+            float dx, dy, dz;
+            drag(cl, d, R, n, dx, dy, dz);
+            Fx += dx;
+            Fy += dy;
+            Fz += dz;
+        }
+        // ---- downwash (Eq. 6): sweep the environment in ascending order
+        if (MASK & 4u) {
+            const float acc = dw_sum<LPD, UNROLL, SYM>(c, buf, tmat, a.tstride, slot, sub, lo, mmax, menv,
+                                                       uniform, d);
+            Fz -= cl.K1 * acc;
+        }
+        // ---- Newton-Euler + exponential map (Eq. 7)
+        integrate(cl, d, Fx, Fy, Fz, tx, ty, tz);
+        // ---- KIN observation
+        if (a.obs != nullptr && writer) {
+            float roll, pitch, yaw;
+            euler_zyx(d, roll, pitch, yaw);
+            float *o = a.obs + (long long)oslot * 20 * N + di;
+            const float orow[20] = {d.px, d.py, d.pz, d.qw, d.qx, d.qy, d.qz, roll, pitch, yaw,
+                                    d.vx, d.vy, d.vz, d.wx, d.wy, d.wz, n[0], n[1], n[2], n[3]};
+#pragma unroll
+            for (int k = 0; k < 20; ++k) o[(long long)k * N] = orow[k];
+        }
+        oslot = (oslot + 1 == a.n_obs_slots) ? 0 : oslot + 1;
+    }
+
+    if (writer) {
+        a.s.p[di] = d.px;
+        a.s.p[N + di] = d.py;
+        a.s.p[2 * N + di] = d.pz;
+        a.s.q[di] = d.qw;
+        a.s.q[N + di] = d.qx;
+        a.s.q[2 * N + di] = d.qy;
+        a.s.q[3 * N + di] = d.qz;
+        a.s.v[di] = d.vx;
+        a.s.v[N + di] = d.vy;
+        a.s.v[2 * N + di] = d.vz;
+        a.s.w[di] = d.wx;
+        a.s.w[N + di] = d.wy;
+        a.s.w[2 * N + di] = d.wz;
+        for (int k = 0; k < 4; ++k) a.s.rpm[k * N + di] = n[k];
+        if (ACT >= 1) {
+            for (int k = 0; k < 6; ++k) a.s.pid_int[k * N + di] = I[k];
+        }
+        if (ACT == 4)
+            for (int k = 0; k < 4; ++k) a.s.ctl[k * N + di] = sp[k];
+        if (DR && ACT >= 1)
+            for (int k = 0; k < 4; ++k) a.s.rpm_cmd[k * N + di] = cmdh[k];
+        if (ring) a.s.act_count[di] = issued;
+    }
+}
+
+template <uint32_t MASK, int ACT, int LPD, bool SYM, bool DR>
+hipError_t launch_u(const StepArgs &a, int unroll, int n_bins, int threads, size_t lds, hipStream_t st) {
+    switch (unroll) {
+        case 1: hipLaunchKernelGGL((step_kernel<MASK, ACT, LPD, 1, SYM, DR>), dim3(n_bins), dim3(threads), lds, st, a); break;
+        case 2: hipLaunchKernelGGL((step_kernel<MASK, ACT, LPD, 2, SYM, DR>), dim3(n_bins), dim3(threads), lds, st, a); break;
+        case 4: hipLaunchKernelGGL((step_kernel<MASK, ACT, LPD, 4, SYM, DR>), dim3(n_bins), dim3(threads), lds, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <uint32_t MASK, int ACT, bool DR>
+hipError_t launch_l(const StepArgs &a, const LaunchCfg &cfg, int n_bins, int threads, size_t lds,
+                    hipStream_t st) {
+    if (!(MASK & 4u)) {
+        // no neighbour sweep: one lane per drone, no loop to tune
+        hipLaunchKernelGGL((step_kernel<MASK, ACT, 1, 1, false, DR>), dim3(n_bins), dim3(threads), lds, st, a);
+        return hipGetLastError();
+    }
+    if (cfg.sym) {
+        if (cfg.lpd != 1) return hipErrorInvalidValue;
+        return launch_u<MASK, ACT, 1, true, DR>(a, cfg.unroll, n_bins, threads, lds, st);
+    }
+    switch (cfg.lpd) {
+        case 1: return launch_u<MASK, ACT, 1, false, DR>(a, cfg.unroll, n_bins, threads, lds, st);
+        case 2: return launch_u<MASK, ACT, 2, false, DR>(a, cfg.unroll, n_bins, threads, lds, st);
+        case 4: return launch_u<MASK, ACT, 4, false, DR>(a, cfg.unroll, n_bins, threads, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int ACT, bool DR>
+hipError_t launch_m(const StepArgs &a, uint32_t mask, const LaunchCfg &cfg, int n_bins,
+                    int threads, size_t lds, hipStream_t st) {
+    switch (mask & 7u) {
+        case 0: return launch_l<0, ACT, DR>(a, cfg, n_bins, threads, lds, st);
+        case 1: return launch_l<1, ACT, DR>(a, cfg, n_bins, threads, lds, st);
+        case 2: return launch_l<2, ACT, DR>(a, cfg, n_bins, threads, lds, st);
+        case 3: return launch_l<3, ACT, DR>(a, cfg, n_bins, threads, lds, st);
+        case 4: return launch_l<4, ACT, DR>(a, cfg, n_bins, threads, lds, st);
+        case 5: return launch_l<5, ACT, DR>(a, cfg, n_bins, threads, lds, st);
+        case 6: return launch_l<6, ACT, DR>(a, cfg, n_bins, threads, lds, st);
+        default: return launch_l<7, ACT, DR>(a, cfg, n_bins, threads, lds, st);
+    }
+}
+
+template <bool DR>
+hipError_t launch_step_t(const StepArgs &a, uint32_t mask, int act, const LaunchCfg &cfg, int n_bins,
+                         int slots, hipStream_t stream) {
+    if (n_bins <= 0 || a.n_steps <= 0) return hipSuccess;
+    const int lpd = (mask & 4u) ? cfg.lpd : 1;
+    const int threads = slots * lpd;
+    size_t lds = (mask & 4u) ? sizeof(float4) * 2 * 2 * (size_t)slots : 0;
+    if ((mask & 4u) && cfg.sym) lds += sizeof(float) * (size_t)slots * (size_t)a.tstride;
+    switch (act) {
+        case 0: return launch_m<0, DR>(a, mask, cfg, n_bins, threads, lds, stream);
+        case 1: return launch_m<1, DR>(a, mask, cfg, n_bins, threads, lds, stream);
+        case 2: return launch_m<2, DR>(a, mask, cfg, n_bins, threads, lds, stream);
+        case 3: return launch_m<3, DR>(a, mask, cfg, n_bins, threads, lds, stream);
+        default: return launch_m<4, DR>(a, mask, cfg, n_bins, threads, lds, stream);
+    }
+}
+
+}  // namespace
+}  // namespace md

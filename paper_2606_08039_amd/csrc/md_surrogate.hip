@@ -4,7 +4,7 @@
 //   datagen_kernel   features + the plain residual (Eq. 4-6 in the body frame)
 //                    at the current state: the surrogate's training samples;
 //   sur_step_kernel  the persistent step with Eq. 4-6 replaced by the network:
-//                    per drone, 8 nearest same-environment neighbours, 59 features,
+//                    per drone, 8 laterally nearest same-environment neighbours, 60 features,
 //                    fp32 standardisation, bfloat16 rounding, then the 64-128-128-128-6
 //                    network on MFMA (v_mfma_f32_16x16x32_bf16) for the wave's 64
 //                    drones at once; a drone whose neighbour sits just above it
@@ -43,7 +43,7 @@ constexpr int WOFF1 = 0, WOFF2 = WOFF1 + MLP_H * MLP_IN, WOFF3 = WOFF2 + MLP_H *
               WOFF4 = WOFF3 + MLP_H * MLP_H, WTOTAL = WOFF4 + W4_ROWS * MLP_H;
 constexpr int BOFF1 = 0, BOFF2 = 128, BOFF3 = 256, BOFF4 = 384, BTOTAL = 400;
 
-enum { J_ERR2 = 0, J_REF2, J_TERR2, J_N, J_FALLBACK, J_STEPS, J_COUNT };
+enum { J_ERR2 = 0, J_REF2, J_TERR2, J_N, J_FALLBACK, J_STEPS, J_NONFINITE, J_COUNT };
 
 struct SurrogateState {
     bf16 *W = nullptr;      // permuted bf16 weights [WTOTAL]
@@ -96,13 +96,17 @@ __device__ __forceinline__ void load_drone(const StatePtr &s, int N, int di, Dro
     d.wz = s.w[2 * N + di];
 }
 
-// k nearest neighbours by 3-D distance among the environment's slots
+// k nearest neighbours by horizontal distance among the environment's slots
 // [lo, lo + m) other than self, ascending, ties to the lower slot (= lower
-// drone index).  The squared distance is formed as (dx*dx + dy*dy) + dz*dz
-// with every operation rounded (no fused multiply-add), the order the oracle
-// uses, so both sides take the same integer decisions.
+// drone index).  Lateral metric: the downwash (Eq. 6) varies with the lateral
+// offset on the centimetre scale of beta and with the height difference on
+// the metre scale, so the laterally closest drones are the ones that matter,
+// and a drone's column partner always lands in the first input slot.  The
+// squared distance is formed as dx*dx + dy*dy with every operation rounded
+// (no fused multiply-add), as the oracle forms it, so both sides take the
+// same integer decisions.
 __device__ __forceinline__ void knn8(const float4 *pos, int lo, int m, int mmax, int self, float px,
-                                     float py, float pz, int bj[KNN]) {
+                                     float py, int bj[KNN]) {
 #pragma clang fp contract(off)
     float bd[KNN];
 #pragma unroll
@@ -113,9 +117,9 @@ __device__ __forceinline__ void knn8(const float4 *pos, int lo, int m, int mmax,
     for (int jj = 0; jj < mmax; ++jj) {
         const int j = lo + jj;
         const float4 pj = pos[j];
-        const float dx = pj.x - px, dy = pj.y - py, dz = pj.z - pz;
-        const float a = dx * dx, b = dy * dy, cz = dz * dz;
-        float d2 = (a + b) + cz;
+        const float dx = pj.x - px, dy = pj.y - py;
+        const float a = dx * dx, b = dy * dy;
+        float d2 = a + b;
         d2 = (jj < m && j != self) ? d2 : __builtin_inff();
         bool c[KNN];
 #pragma unroll
@@ -131,7 +135,8 @@ __device__ __forceinline__ void knn8(const float4 *pos, int lo, int m, int mmax,
 }
 
 // Raw surrogate inputs (see md.h): v_body, world up in the body frame, n/HOVER,
-// 8 x (dp, dv) of the nearest neighbours (world frame, zero if missing), z, 0-pad.
+// 8 x (dp, dv) of the nearest neighbours (world frame, zero if missing), z,
+// ground proximity (h_clip / max(z, h_clip))^2, 0-pad.
 // Returns whether a neighbour sits above within (0, dz_ood).
 __device__ __forceinline__ bool features(const KConst &c, const Drone &d, const Rot &R, const float n[4],
                                          const float4 *pos, const float4 *vel, const int bj[KNN],
@@ -164,8 +169,10 @@ __device__ __forceinline__ bool features(const KConst &c, const Drone &d, const 
         ood |= h && dz > 0.f && dz < dz_ood;
     }
     f[58] = d.pz;
+    const float gp = c.h_clip / fmaxf(d.pz, c.h_clip);
+    f[59] = gp * gp;
 #pragma unroll
-    for (int k = 59; k < MLP_IN; ++k) f[k] = 0.f;
+    for (int k = 60; k < MLP_IN; ++k) f[k] = 0.f;
     return ood;
 }
 
@@ -338,7 +345,7 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
         for (int k = 0; k < ROWS; ++k) tgt_held[k] = a.action[(long long)k * N + di];
     if (ACT == 4 && valid)
         for (int k = 0; k < 4; ++k) sp[k] = a.s.ctl[k * N + di];
-    double jerr = 0.0, jref = 0.0, jterr = 0.0, jn = 0.0, jfb = 0.0;
+    double jerr = 0.0, jref = 0.0, jterr = 0.0, jn = 0.0, jfb = 0.0, jnf = 0.0;
     int phase = (ACT >= 1) ? (int)(a.step0 % (long long)c.decim) : 0;
     int oslot = 0;
     for (int step = 0; step < a.n_steps; ++step) {
@@ -364,7 +371,7 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
         const Rot R = rot_of(d);
         // ---- features -> standardised bfloat16 row
         int bj[KNN];
-        knn8(pos, lo, menv, mmax, slot, d.px, d.py, d.pz, bj);
+        knn8(pos, lo, menv, mmax, slot, d.px, d.py, bj);
         float f[MLP_IN];
         const bool ood = features(c, d, R, n, pos, vel, bj, sa.dz_ood, f) && valid;
         bf16 *row = feat + slot * FEAT_STRIDE;
@@ -406,10 +413,16 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
         }
         if (judge) {
             const float ex = sx - px_, ey = sy - py_, ez = sz - pz_;
-            jerr += (double)(ex * ex + ey * ey + ez * ez);
-            jref += (double)(px_ * px_ + py_ * py_ + pz_ * pz_);
-            jterr += (double)(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]);
-            jn += 1.0;
+            const float e2 = ex * ex + ey * ey + ez * ez, r2 = px_ * px_ + py_ * py_ + pz_ * pz_;
+            const float t2 = y[3] * y[3] + y[4] * y[4] + y[5] * y[5];
+            // a non-finite sample (a state that has left every sensible range)
+            // is counted apart so that it cannot poison the sums
+            const bool fin = __builtin_isfinite(e2) && __builtin_isfinite(r2) && __builtin_isfinite(t2);
+            jerr += fin ? (double)e2 : 0.0;
+            jref += fin ? (double)r2 : 0.0;
+            jterr += fin ? (double)t2 : 0.0;
+            jn += fin ? 1.0 : 0.0;
+            jnf += fin ? 0.0 : 1.0;
         }
         Fx += ax;
         Fy += ay;
@@ -448,7 +461,7 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
     }
     if (sa.judge != nullptr) {
         const double s0 = wave_sum(jerr), s1 = wave_sum(jref), s2 = wave_sum(jterr), s3 = wave_sum(jn),
-                     s4 = wave_sum(jfb);
+                     s4 = wave_sum(jfb), s5 = wave_sum(jnf);
         const double steps = wave_sum(valid ? (double)a.n_steps : 0.0);
         if (lane == 0) {
             atomicAdd(sa.judge + J_ERR2, s0);
@@ -457,6 +470,7 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
             atomicAdd(sa.judge + J_N, s3);
             atomicAdd(sa.judge + J_FALLBACK, s4);
             atomicAdd(sa.judge + J_STEPS, steps);
+            atomicAdd(sa.judge + J_NONFINITE, s5);
         }
     }
 }
@@ -490,7 +504,7 @@ __global__ void __launch_bounds__(256) datagen_kernel(GenArgs g) {
     motor(c, n, T, tx, ty, tz);
     const Rot R = rot_of(d);
     int bj[KNN];
-    knn8(pos, lo, menv, mmax, slot, d.px, d.py, d.pz, bj);
+    knn8(pos, lo, menv, mmax, slot, d.px, d.py, bj);
     float f[MLP_IN];
     (void)features(c, d, R, n, pos, vel, bj, 0.f, f);
     float *x = g.X + (long long)di * MLP_IN;
@@ -694,7 +708,8 @@ md_status judge_stats(md_ctx *ctx, md_judge *out) {
     out->torque_err2 = h[J_TERR2];
     out->n_fallback = h[J_FALLBACK];
     out->n_drone_steps = h[J_STEPS];
-    out->force_rel_err = h[J_REF2] > 0 ? std::sqrt(h[J_ERR2] / h[J_REF2]) : 0.0;
+    out->n_nonfinite = h[J_NONFINITE];
+    out->force_rel_err = std::sqrt(h[J_ERR2] / h[J_REF2]);  // NaN when nothing was judged
     return MD_OK;
 }
 

@@ -33,18 +33,19 @@ static std::string signature(const md_ctx *ctx) {
         h ^= (uint64_t)(ctx->off[e + 1] - ctx->off[e]);
         h *= 1099511628211ull;
     }
-    char buf[160];
-    std::snprintf(buf, sizeof buf, "n%d_e%d_m%d_h%016llx_mask%u_act%d", ctx->n_drones, ctx->n_envs, ctx->max_m,
-                  (unsigned long long)h, ctx->mask, ctx->act);
+    char buf[176];
+    std::snprintf(buf, sizeof buf, "n%d_e%d_m%d_h%016llx_mask%u_act%d_int%d", ctx->n_drones, ctx->n_envs,
+                  ctx->max_m, (unsigned long long)h, ctx->mask, ctx->act, ctx->integ);
     return buf;
 }
 
-static bool cfg_valid(const md_ctx *ctx, const LaunchCfg &c) {
+bool cfg_valid(const md_ctx *ctx, const LaunchCfg &c) {
     const int slots = 64 * c.waves / c.lpd;
     if (slots < ctx->max_m || slots < 1) return false;
     if (c.sym && c.lpd != 1) return false;
+    if (ctx->integ == MD_INTEG_RK4 && (ctx->mask & MD_AERO_DW) && c.lpd != 1) return false;
     if (c.sym) {
-        const size_t lds = 16 * 4 * (size_t)slots + 4 * (size_t)slots * (size_t)((ctx->max_m + 1) | 1);
+        const size_t lds = 16 * 4 * (size_t)slots + 4 * (size_t)slots * (size_t)pair_stride(ctx->max_m);
         if (lds > 64 * 1024) return false;
     }
     if (64 * c.waves > 1024) return false;
@@ -145,7 +146,11 @@ md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int ac
         return MD_OK;
     }
     // scratch copies of the state: the caller's state is never advanced
-    const size_t rows = 3 + 4 + 3 + 3 + 6 + 4 + 4;
+    const bool dr = ctx->dr_on, ring = dr && ctx->dr.delay != nullptr;
+    const size_t nr[10] = {3, 4, 3, 3, 6, 4, 4, dr ? 4u : 0u,
+                           ring ? (size_t)MD_DR_HIST * action_rows(ctx->act) : 0u, ring ? 1u : 0u};
+    size_t rows = 0;
+    for (size_t r : nr) rows += r;
     float *scratch = nullptr, *work = nullptr;
     hipError_t e = hipMalloc(&scratch, sizeof(float) * rows * N);
     if (e == hipSuccess) e = hipMalloc(&work, sizeof(float) * rows * N);
@@ -154,25 +159,38 @@ md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int ac
         ctx->err = hip_msg("autotune scratch", e);
         return MD_E_OOM;
     }
-    const float *src[7] = {s->p, s->q, s->v, s->w, s->pid_int, s->rpm, s->ctl};
-    const int nr[7] = {3, 4, 3, 3, 6, 4, 4};
+    // act_count is int32: copied bit for bit through a float-sized slot
+    const float *src[10] = {s->p, s->q, s->v, s->w, s->pid_int, s->rpm, s->ctl, s->rpm_cmd, s->act_hist,
+                            (const float *)s->act_count};
     size_t o = 0;
-    md_state ws;
-    float **dst[7] = {&ws.p, &ws.q, &ws.v, &ws.w, &ws.pid_int, &ws.rpm, &ws.ctl};
-    for (int k = 0; k < 7; ++k) {
+    md_state ws{};
+    float *blk[10] = {};
+    for (int k = 0; k < 10 && e == hipSuccess; ++k) {
+        if (nr[k] == 0) continue;
         if (src[k])
             e = hipMemcpyAsync(scratch + o, src[k], sizeof(float) * nr[k] * N, hipMemcpyDeviceToDevice, st);
         else
             e = hipMemsetAsync(scratch + o, 0, sizeof(float) * nr[k] * N, st);
-        *dst[k] = work + o;
+        blk[k] = work + o;
         o += nr[k] * N;
-        if (e != hipSuccess) break;
     }
+    ws.p = blk[0];
+    ws.q = blk[1];
+    ws.v = blk[2];
+    ws.w = blk[3];
+    ws.pid_int = blk[4];
+    ws.rpm = blk[5];
+    ws.ctl = blk[6];
+    ws.rpm_cmd = blk[7];
+    ws.act_hist = blk[8];
+    ws.act_count = (int32_t *)blk[9];
     hipEvent_t a = nullptr, b = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
     double best_us = 1e300;
     LaunchCfg best = ctx->cfg;
+    const char *venv = std::getenv("MD_AUTOTUNE_VERBOSE");
+    const bool verbose = venv && *venv && *venv != '0';
     md_status rc = MD_OK;
     for (const LaunchCfg &c : candidates(ctx)) {
         if (e != hipSuccess) break;
@@ -190,6 +208,9 @@ md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int ac
             if (rep > 0) t_best = std::min(t_best, ms);  // first repetition warms up
         }
         if (rc != MD_OK) break;
+        if (verbose && e == hipSuccess)
+            std::fprintf(stderr, "md_autotune %s: lpd %d unroll %d waves %d sym %d: %.1f us\n", sig.c_str(), c.lpd,
+                         c.unroll, c.waves, c.sym, t_best * 1000.0);
         if (e == hipSuccess && t_best * 1000.0 < best_us) {
             best_us = t_best * 1000.0;
             best = c;

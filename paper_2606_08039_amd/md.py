@@ -18,6 +18,7 @@ MD_OK = 0
 MD_E_INVALID_ARG, MD_E_HIP, MD_E_OOM, MD_E_UNSUPPORTED, MD_E_LAYOUT = -1, -2, -3, -4, -5
 MD_AERO_GND, MD_AERO_DRAG, MD_AERO_DW, MD_AERO_SURROGATE = 1, 2, 4, 8
 MD_ACT_RPM, MD_ACT_PID, MD_ACT_VEL, MD_ACT_ATTITUDE, MD_ACT_DSL = 0, 1, 2, 3, 4
+MD_INTEG_EULER, MD_INTEG_RK4 = 0, 1
 ACTION_ROWS = {MD_ACT_RPM: 4, MD_ACT_PID: 4, MD_ACT_VEL: 4, MD_ACT_ATTITUDE: 4, MD_ACT_DSL: 7}
 OBS_DIM = 20
 STATE_ROWS = (("p", 3), ("q", 4), ("v", 3), ("w", 3), ("pid_int", 6), ("rpm", 4), ("ctl", 4))
@@ -49,7 +50,17 @@ class md_derived(ctypes.Structure):
 
 
 class md_state(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_void_p) for n in ("p", "q", "v", "w", "pid_int", "rpm", "ctl")]
+    _fields_ = [(n, ctypes.c_void_p) for n in ("p", "q", "v", "w", "pid_int", "rpm", "ctl",
+                                               "rpm_cmd", "act_hist", "act_count")]
+
+
+class md_dr(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("scale", "tau_mot", "delay")]
+
+
+MD_DR_ROWS = ("m", "J", "L", "kf", "km", "drag", "C_gnd", "C1", "max_rpm", "g",
+              "bias0", "bias1", "bias2", "bias3")
+MD_DR_NSCALE, MD_DR_HIST = 14, 32
 
 
 _lib = None
@@ -190,6 +201,22 @@ class DeviceState:
                 d.t[k].copy_(torch.from_numpy(np.ascontiguousarray(s[k], dtype=np.float32)))
         return d
 
+    def add_dr_blocks(self, act_type, s=None):
+        """The blocks the domain-randomised step needs: the held controller
+        command (from s["rpm_cmd"], else the rotor speeds), the action ring
+        and its fill counts (from s, else empty)."""
+        import torch
+        rows = ACTION_ROWS[act_type]
+        dev = self.t["p"].device
+        self.t["rpm_cmd"] = self.t["rpm"].clone()
+        self.t["act_hist"] = torch.zeros((MD_DR_HIST, rows, self.n), dtype=torch.float32, device=dev)
+        self.t["act_count"] = torch.zeros(self.n, dtype=torch.int32, device=dev)
+        if s is not None:
+            for k, dt in (("rpm_cmd", np.float32), ("act_hist", np.float32), ("act_count", np.int32)):
+                if k in s:
+                    self.t[k].copy_(torch.from_numpy(np.ascontiguousarray(s[k], dtype=dt)))
+        return self
+
     def to_numpy(self):
         return {k: v.cpu().numpy() for k, v in self.t.items()}
 
@@ -200,7 +227,9 @@ class DeviceState:
         return d
 
     def as_md_state(self):
-        return md_state(*[self.t[k].data_ptr() for k in ("p", "q", "v", "w", "pid_int", "rpm", "ctl")])
+        return md_state(*[self.t[k].data_ptr() if k in self.t else None
+                          for k in ("p", "q", "v", "w", "pid_int", "rpm", "ctl", "rpm_cmd", "act_hist",
+                                    "act_count")])
 
 
 # ------------------------------------------------------------------ surrogate network
@@ -302,7 +331,8 @@ def mlp_flatten(parts):
 
 class md_judge(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("n_judged", "force_err2", "force_ref2", "torque_err2",
-                                                "n_fallback", "n_drone_steps", "force_rel_err")]
+                                                "n_fallback", "n_drone_steps", "force_rel_err",
+                                                "n_nonfinite")]
 
 
 def md_load_surrogate(ctx, flat, norm, dz_ood=1e-3, judge_stride=64):
@@ -330,6 +360,36 @@ def md_judge_stats(ctx):
 
 def md_judge_reset(ctx):
     check(lib().md_judge_reset(ctx), ctx)
+
+
+# ------------------------------------------------------------------ domain randomisation
+
+def md_set_domain_randomization(ctx, scale=None, tau_mot=None, delay=None):
+    """scale: CUDA float32 [MD_DR_NSCALE][N]; tau_mot: float32 [N] or None;
+    delay: int32 [N] or None.  scale None turns randomisation off.  The
+    tensors must stay alive while the context uses them."""
+    if scale is None:
+        check(lib().md_set_domain_randomization(ctx, None), ctx)
+        return
+    import torch
+    assert scale.dtype == torch.float32 and scale.is_contiguous()
+    assert tau_mot is None or (tau_mot.dtype == torch.float32 and tau_mot.is_contiguous())
+    assert delay is None or (delay.dtype == torch.int32 and delay.is_contiguous())
+    d = md_dr(scale.data_ptr(), tau_mot.data_ptr() if tau_mot is not None else None,
+              delay.data_ptr() if delay is not None else None)
+    check(lib().md_set_domain_randomization(ctx, ctypes.byref(d)), ctx)
+
+
+# ------------------------------------------------------------------ integrator
+
+def md_set_integrator(ctx, integrator):
+    check(lib().md_set_integrator(ctx, int(integrator)), ctx)
+
+
+def md_get_integrator(ctx):
+    v = ctypes.c_int(-1)
+    check(lib().md_get_integrator(ctx, ctypes.byref(v)), ctx)
+    return v.value
 
 
 # ------------------------------------------------------------------ launch configuration, graphs

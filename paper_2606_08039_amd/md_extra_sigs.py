@@ -26,6 +26,9 @@ def signatures():
         "md_datagen": (_I32, [_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, _VP]),
         "md_judge_stats": (_I32, [_VP, _VP]),
         "md_judge_reset": (_I32, [_VP]),
+        "md_set_integrator": (_I32, [_VP, ctypes.c_int]),
+        "md_set_domain_randomization": (_I32, [_VP, _VP]),
+        "md_get_integrator": (_I32, [_VP, ctypes.POINTER(ctypes.c_int)]),
         "md_get_launch_config": (_I32, [_VP, _VP]),
         "md_set_launch_config": (_I32, [_VP, _VP]),
         "md_autotune": (_I32, [_VP, _VP, _VP, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _VP,

@@ -8,7 +8,7 @@ pitch U[1.0,1.3] m, vertical pitch U[0.9,1.0] m, lower layer z ~ U[0.3,0.5],
 PID waypoints = lattice point + U[-0.05,0.05]^3, start = waypoint +
 U[-0.1,0.1]^3) are flown by the plain model (ground effect + drag +
 downwash, PID every 5 steps); every `every` steps the waypoints are drawn
-again and one sample per drone is taken: 59 features and the body-frame
+again and one sample per drone is taken: 60 features and the body-frame
 residual of Eq. 4-6.
 
 Weights file: a little-endian binary with magic b"MDSURR01", a uint32 JSON
@@ -105,7 +105,7 @@ def train(X, Y, norm, epochs=20, batch=4096, lr=2e-3, lr_final=2e-5, seed=0, log
     decay.  Returns (md_mlp handle, history)."""
     import torch
     N = X.shape[0]
-    m = md.md_mlp_create(batch)
+    m = md.md_mlp_create(max(batch, 4096))  # predict() runs batches of 4096
     md.md_mlp_set_params(m, init_params(seed))
     md.md_mlp_set_norm(m, norm)
     gen = torch.Generator(device=X.device)

@@ -204,3 +204,56 @@ def subset_envs(w, n_envs):
     if "lattice_points" in w:
         out["lattice_points"] = np.ascontiguousarray(w["lattice_points"][:, :n])
     return out
+
+
+def thin_envs(w, seed, m_lo=2):
+    """Ragged environments from a uniform workload: each environment keeps a
+    random subset of U{m_lo..M} of its drones (in their original order)."""
+    rng = np.random.default_rng(seed)
+    off = np.asarray(w["env_offsets"], dtype=np.int64)
+    keep = []
+    for e in range(len(off) - 1):
+        m = int(off[e + 1] - off[e])
+        k = int(rng.integers(min(m_lo, m), m + 1))
+        keep.append(np.sort(rng.choice(m, size=k, replace=False)) + off[e])
+    sizes = np.array([len(k) for k in keep])
+    idx = np.concatenate(keep) if keep else np.zeros(0, dtype=np.int64)
+    out = dict(w)
+    out["env_offsets"] = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    out["state"] = {k: np.ascontiguousarray(v[:, idx]) for k, v in w["state"].items()}
+    out["action"] = np.ascontiguousarray(w["action"][:, :, idx])
+    if "lattice_points" in w:
+        out["lattice_points"] = np.ascontiguousarray(w["lattice_points"][:, idx])
+    return out
+
+
+# Table "Recommended domain-randomization ranges": half-widths a of the
+# multiplicative factors U(1 - a, 1 + a), the motor time constant and the
+# action latency ranges.
+DR_HALF_WIDTH = {"m": 0.2, "J": 0.2, "L": 0.02, "kf": 0.15, "km": 0.15, "drag": 0.3, "C_gnd": 0.3,
+                 "C1": 0.3, "max_rpm": 0.05, "g": 0.02, "bias": 0.05}
+DR_TAU_MOT = (0.005, 0.050)   # s
+DR_LATENCY = (0.0, 0.050)     # s
+
+
+def domain_randomization(w, seed, lag=True, latency=True):
+    """Seeded draws for the workload's drones: one vehicle per drone (mass,
+    inertia, arm, kf, km, drag, C_gnd, C1, MAX_RPM, four motor biases, motor
+    time constant, action latency rounded to whole steps), gravity per
+    environment.  Returns float32 scale [14][N], float32 tau_mot [N] (None
+    without lag) and int32 delay [N] (None without latency)."""
+    rng = np.random.default_rng(seed)
+    off = np.asarray(w["env_offsets"], dtype=np.int64)
+    n = int(off[-1])
+    rows = ("m", "J", "L", "kf", "km", "drag", "C_gnd", "C1", "max_rpm")
+    scale = np.ones((14, n))
+    for r, k in enumerate(rows):
+        a = DR_HALF_WIDTH[k]
+        scale[r] = rng.uniform(1 - a, 1 + a, size=n)
+    a = DR_HALF_WIDTH["g"]
+    scale[9] = np.repeat(rng.uniform(1 - a, 1 + a, size=len(off) - 1), np.diff(off))
+    a = DR_HALF_WIDTH["bias"]
+    scale[10:14] = rng.uniform(1 - a, 1 + a, size=(4, n))
+    tau = rng.uniform(*DR_TAU_MOT, size=n).astype(np.float32) if lag else None
+    delay = np.rint(rng.uniform(*DR_LATENCY, size=n) / w["dt"]).astype(np.int32) if latency else None
+    return dict(scale=scale.astype(np.float32), tau_mot=tau, delay=delay)

@@ -40,9 +40,20 @@ class GpuRun:
         self.p = p or params()
         self.mask = w["aero_mask"] if mask is None else mask
         self.ctx = md.md_create(self.p, w["dt"], self.mask, ACT[w["act_type"]], w["ctrl_decim"])
+        if w.get("integrator", "euler") == "rk4":
+            md.md_set_integrator(self.ctx, md.MD_INTEG_RK4)
         md.md_bind_layout(self.ctx, w["env_offsets"])
+        if cfg is not None:
+            md.md_set_launch_config(self.ctx, **cfg)
         self.n = int(w["env_offsets"][-1])
         self.state = md.DeviceState.from_numpy(w["state"])
+        self.dr = None
+        if w.get("dr") is not None:
+            dr = w["dr"]
+            self.dr = {k: (torch.from_numpy(dr[k]).cuda() if dr.get(k) is not None else None)
+                       for k in ("scale", "tau_mot", "delay")}
+            self.state.add_dr_blocks(ACT[w["act_type"]], w["state"])
+            md.md_set_domain_randomization(self.ctx, self.dr["scale"], self.dr["tau_mot"], self.dr["delay"])
         self.action = torch.from_numpy(np.ascontiguousarray(w["action"], dtype=np.float32)).cuda()
         self.step_index = 0
 
@@ -69,7 +80,8 @@ class GpuRun:
 
 
 def to_oracle_state(s32):
-    return {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in s32.items()}
+    return {k: np.ascontiguousarray(v, dtype=np.int32 if k == "act_count" else np.float64)
+            for k, v in s32.items()}
 
 
 def obs_to_state(o, prev=None):
@@ -93,16 +105,24 @@ def oracle_one_step(w, s32, k, env_subset=None, mask=None, n_steps=1, obs_slots=
         idx = np.concatenate([np.arange(off[e], off[e + 1]) for e in env_subset])
         m = np.array([off[e + 1] - off[e] for e in env_subset])
         sub_off = np.concatenate([[0], np.cumsum(m)]).astype(np.int32)
-        s = {kk: np.ascontiguousarray(v[:, idx]) for kk, v in s.items()}
+        s = {kk: np.ascontiguousarray(v[..., idx]) for kk, v in s.items()}
         act = act[:, :, idx]
     else:
         idx = None
         sub_off = np.asarray(off, dtype=np.int32)
     a = act[k:k + n_steps] if w["action_per_step"] else act[0:1]
+    dr = None
+    if w.get("dr") is not None:
+        pick = (lambda v: v) if idx is None else (lambda v: v[..., idx])
+        dr = {kk: (np.ascontiguousarray(pick(v)) if v is not None else None) for kk, v in w["dr"].items()}
+        dr["scale"] = dr["scale"].astype(np.float64)
+        if dr.get("tau_mot") is not None:
+            dr["tau_mot"] = dr["tau_mot"].astype(np.float64)
     obs = orc.step(P, w["dt"], w["aero_mask"] if mask is None else mask,
                    ORC_ACT[w["act_type"]], w["ctrl_decim"],
                    sub_off, s, np.ascontiguousarray(a, dtype=np.float64), w["action_per_step"],
-                   n_steps, step0=k, n_obs_slots=obs_slots)
+                   n_steps, step0=k, n_obs_slots=obs_slots,
+                   integrator=w.get("integrator", "euler"), dr=dr)
     return s, obs, idx
 
 

@@ -1,0 +1,125 @@
+"""GPU parity of the domain-randomised step (md_set_domain_randomization)
+against the oracle's orc_step_dr: per-step criterion from GPU snapshots on
+the formation (sampled environments, both neighbour sweeps), the ragged grid
+with per-step rotor-speed actions, and every controller; chunked launches
+equal one launch bitwise (the latency ring carries across launches);
+the autotuner leaves the caller's state untouched; error paths."""
+import numpy as np
+import pytest
+
+import parity_util as pu
+from paper_2606_08039_amd import md, workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+SYM = dict(lanes_per_drone=1, unroll=4, waves_per_group=1, pair_symmetric=1)
+LPD2 = dict(lanes_per_drone=2, unroll=2, waves_per_group=2, pair_symmetric=0)
+EXTRA = ("pid_int", "rpm_cmd")
+
+
+def _dr(w, seed, **kw):
+    return dict(w, dr=wl.domain_randomization(w, seed, **kw))
+
+
+def _parity(w, ks, env_subset=None, cfg=None, blocks=pu.BLOCKS):
+    worst = {}
+    g = pu.GpuRun(w, cfg=cfg)
+    try:
+        for k in ks:
+            if k > g.step_index:
+                g.run(k - g.step_index)
+            s0 = g.snapshot()
+            gobs = g.run(1, obs_slots=1)
+            s1 = g.snapshot()
+            ref, robs, idx = pu.oracle_one_step(w, s0, k, env_subset=env_subset, obs_slots=1)
+            e = pu.assert_blocks(s1, ref, idx, blocks=blocks, what="dr step %d" % k)
+            a = gobs[0] if idx is None else gobs[0][:, idx]
+            sc = np.maximum(np.max(np.abs(robs[0]), axis=0), 1.0)
+            assert np.max(np.max(np.abs(a - robs[0]), axis=0) / sc) <= pu.TOL, k
+            if "act_count" in s1:
+                got = s1["act_count"] if idx is None else s1["act_count"][idx]
+                np.testing.assert_array_equal(got, ref["act_count"])
+            worst = {kk: max(worst.get(kk, 0.0), v) for kk, v in e.items()}
+    finally:
+        g.close()
+    return worst
+
+
+@pytest.mark.parametrize("cfg", [SYM, LPD2], ids=["sym", "lpd2"])
+def test_formation_full_size_sampled(cfg):
+    w = _dr(wl.formation(n_envs=8192, n_steps=1000, seed=4), 50)
+    rng = np.random.default_rng(2)
+    envs = np.sort(rng.choice(8192, 32, replace=False))
+    worst = _parity(w, [0, 1, 4, 5, 17, 333], env_subset=envs, cfg=cfg, blocks=pu.BLOCKS + EXTRA)
+    print("dr formation 8192x32 (32 sampled envs)", cfg, "worst:", worst)
+
+
+def test_ragged_grid_per_step_rotor_speeds():
+    w = _dr(wl.ragged_grid(pu.hover_rpm(), n_envs=512, n_steps=60, seed=2), 51)
+    worst = _parity(w, [0, 1, 2, 3, 11, 12, 13, 40])
+    print("dr ragged grid, worst:", worst)
+
+
+@pytest.mark.parametrize("kind", ["vel", "attitude", "dsl"])
+def test_controllers(kind):
+    p = md.md_default_params_cf2x()
+    w = _dr(wl.commanded(kind, p.m * p.g, n_envs=256, n_steps=60, seed=5), 52)
+    extra = EXTRA + (("ctl",) if kind == "dsl" else ())
+    _parity(w, [0, 1, 5, 13, 40], blocks=pu.BLOCKS + extra)
+
+
+def test_chunked_launches_equal_one_launch():
+    w = _dr(wl.ragged_grid(pu.hover_rpm(), n_envs=200, n_steps=40, seed=7), 53)
+    a = pu.GpuRun(w)
+    a.run(40)
+    sa = a.snapshot()
+    a.close()
+    b = pu.GpuRun(w)
+    for k in (7, 13, 20):
+        b.run(k)
+    sb = b.snapshot()
+    b.close()
+    for k in sa:
+        np.testing.assert_array_equal(sb[k], sa[k], err_msg=k)
+
+
+def test_autotune_leaves_state_untouched_and_keeps_parity():
+    import torch
+    w = _dr(wl.subset_envs(wl.formation(n_envs=8192, n_steps=1000, seed=4), 256), 54)
+    g = pu.GpuRun(w)
+    g.run(3)
+    before = g.snapshot()
+    md.md_autotune(g.ctx, g.state, g.action_slice(0, 1), w["action_per_step"], n_steps=8, cache_path="")
+    torch.cuda.synchronize()
+    after = g.snapshot()
+    for k in before:
+        np.testing.assert_array_equal(after[k], before[k], err_msg=k)
+    g.close()
+
+
+def test_error_paths():
+    import torch
+    p = md.md_default_params_cf2x()
+    sc = torch.ones((md.MD_DR_NSCALE, 4), dtype=torch.float32, device="cuda")
+    ctx = md.md_create(p, wl.DT, md.MD_AERO_SURROGATE, md.MD_ACT_PID, 5)
+    with pytest.raises(md.MdError):
+        md.md_set_domain_randomization(ctx, sc)
+    md.md_destroy(ctx)
+    ctx = md.md_create(p, wl.DT, 7, md.MD_ACT_PID, 5)
+    md.md_set_integrator(ctx, md.MD_INTEG_RK4)
+    with pytest.raises(md.MdError):
+        md.md_set_domain_randomization(ctx, sc)
+    md.md_set_integrator(ctx, md.MD_INTEG_EULER)
+    md.md_set_domain_randomization(ctx, sc, None, torch.zeros(4, dtype=torch.int32, device="cuda"))
+    with pytest.raises(md.MdError):
+        md.md_set_integrator(ctx, md.MD_INTEG_RK4)
+    md.md_bind_layout(ctx, np.array([0, 4], dtype=np.int32))
+    st = md.DeviceState(4)  # no rpm_cmd / act_hist / act_count blocks
+    act = torch.zeros((1, 4, 4), dtype=torch.float32, device="cuda")
+    with pytest.raises(md.MdError):
+        md.md_step(ctx, st, act, False, None, 0, 1, 0)
+    st.add_dr_blocks(md.MD_ACT_PID)
+    md.md_step(ctx, st, act, False, None, 0, 1, 0)
+    md.md_set_domain_randomization(ctx, None)
+    md.md_destroy(ctx)
+    torch.cuda.synchronize()
