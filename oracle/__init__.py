@@ -57,7 +57,19 @@ class Net(ctypes.Structure):
 class _CState(ctypes.Structure):
     _fields_ = [(n, ctypes.POINTER(ctypes.c_double)) for n in ("p", "q", "v", "w", "pid_int", "rpm", "ctl",
                                                                "rpm_cmd", "act_hist")] + \
-        [("act_count", ctypes.POINTER(ctypes.c_int32))]
+        [("act_count", ctypes.POINTER(ctypes.c_int32)), ("wind", ctypes.POINTER(ctypes.c_double))]
+
+
+class _CWind(ctypes.Structure):
+    _fields_ = [("models", ctypes.c_uint32), ("v_mean", ctypes.c_double * 3), ("rho", ctypes.c_double),
+                ("cd_area", ctypes.c_double), ("gust_prob", ctypes.c_double),
+                ("gust_duration", ctypes.c_double), ("gust_amp", ctypes.c_double),
+                ("dryden_sigma", ctypes.c_double), ("dryden_airspeed", ctypes.c_double),
+                ("sin_amp", ctypes.c_double), ("sin_omega", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+WIND_CONSTANT, WIND_GUST, WIND_DRYDEN, WIND_SINUSOIDAL = 1, 2, 4, 8
+WIND_COMBINED = 15
 
 
 class _CDr(ctypes.Structure):
@@ -111,6 +123,10 @@ def _load():
     lib.orc_step_rk4.argtypes = lib.orc_step.argtypes
     lib.orc_step_dr.argtypes = lib.orc_step.argtypes + [ctypes.POINTER(_CDr)]
     lib.orc_step_dr.restype = ctypes.c_int
+    lib.orc_step_disturbed.argtypes = lib.orc_step_dr.argtypes + [ctypes.POINTER(_CWind)]
+    lib.orc_step_disturbed.restype = ctypes.c_int
+    lib.orc_philox4x32.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
+    lib.orc_philox4x32.restype = None
     lib.orc_step_rk4.restype = ctypes.c_int
     lib.orc_knn.argtypes = [ctypes.c_int, _I32, ctypes.c_int, _D, ctypes.c_int, _I32]
     lib.orc_features.argtypes = [P, ctypes.c_int, _I32, ctypes.c_int, ctypes.POINTER(_CState),
@@ -293,14 +309,15 @@ def _cstate(s):
         if k == "ctl" and k not in s:
             continue
         assert s[k].dtype == np.float64 and s[k].flags.c_contiguous, k
-    for k in ("rpm_cmd", "act_hist"):
+    for k in ("rpm_cmd", "act_hist", "wind"):
         if k in s:
             assert s[k].dtype == np.float64 and s[k].flags.c_contiguous, k
     if "act_count" in s:
         assert s["act_count"].dtype == np.int32 and s["act_count"].flags.c_contiguous
     return _CState(*([s[k].ctypes.data_as(_D) if k in s else None
                       for k in ("p", "q", "v", "w", "pid_int", "rpm", "ctl", "rpm_cmd", "act_hist")] +
-                     [s["act_count"].ctypes.data_as(_I32) if "act_count" in s else None]))
+                     [s["act_count"].ctypes.data_as(_I32) if "act_count" in s else None,
+                      s["wind"].ctypes.data_as(_D) if "wind" in s else None]))
 
 
 def dr_state(state, act_type):
@@ -314,9 +331,31 @@ def dr_state(state, act_type):
     return state
 
 
+def wind_state(state):
+    """Add the wind block to a state dict: Dryden velocity 0, gusts idle."""
+    n = state["p"].shape[1]
+    state["wind"] = np.zeros((5, n))
+    state["wind"][3] = -1.0
+    return state
+
+
+def philox4x32(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xffffffff for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xffffffff for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    _load().orc_philox4x32(c, k, o)
+    return [o[i] for i in range(4)]
+
+
+def make_wind(models, v_mean=(0.0, 0.0, 0.0), rho=1.225, cd_area=0.01, gust_prob=0.0, gust_duration=0.5,
+              gust_amp=0.0, dryden_sigma=0.0, dryden_airspeed=1.0, sin_amp=0.0, sin_omega=0.0, seed=0):
+    return _CWind(int(models), (ctypes.c_double * 3)(*v_mean), rho, cd_area, gust_prob, gust_duration,
+                  gust_amp, dryden_sigma, dryden_airspeed, sin_amp, sin_omega, int(seed))
+
+
 def step(P, dt, aero_mask, act_type, ctrl_decim, env_offsets, state, action,
          action_per_step, n_steps, step0=0, n_obs_slots=0, n_threads=0, integrator="euler",
-         dr=None):
+         dr=None, wind=None):
     """Advance ``state`` (dict of [c][N] float64 arrays, updated in place) by
     n_steps with the semi-implicit Euler step or classic RK4; returns the
     observation array [slots][20][N] or None.  dr: None, or a dict with
@@ -334,15 +373,18 @@ def step(P, dt, aero_mask, act_type, ctrl_decim, env_offsets, state, action,
             int(ctrl_decim), n_envs, _ip(off), n, ctypes.byref(cs), _dp(act),
             int(bool(action_per_step)), _dp(obs) if obs is not None else None,
             int(n_obs_slots), int(n_steps), int(step0), int(n_threads))
-    if dr is not None:
+    if dr is not None or wind is not None:
         assert integrator == "euler"
-        sc = np.ascontiguousarray(dr["scale"], dtype=np.float64)
-        assert sc.shape == (len(DR_ROWS), n), sc.shape
-        tau = np.ascontiguousarray(dr["tau_mot"], dtype=np.float64) if dr.get("tau_mot") is not None else None
-        dl = np.ascontiguousarray(dr["delay"], dtype=np.int32) if dr.get("delay") is not None else None
-        cdr = _CDr(_dp(sc), _dp(tau) if tau is not None else None,
-                   dl.ctypes.data_as(_I32) if dl is not None else None)
-        rc = _load().orc_step_dr(*args, ctypes.byref(cdr))
+        cdr = None
+        if dr is not None:
+            sc = np.ascontiguousarray(dr["scale"], dtype=np.float64)
+            assert sc.shape == (len(DR_ROWS), n), sc.shape
+            tau = np.ascontiguousarray(dr["tau_mot"], dtype=np.float64) if dr.get("tau_mot") is not None else None
+            dl = np.ascontiguousarray(dr["delay"], dtype=np.int32) if dr.get("delay") is not None else None
+            cdr = _CDr(_dp(sc), _dp(tau) if tau is not None else None,
+                       dl.ctypes.data_as(_I32) if dl is not None else None)
+        rc = _load().orc_step_disturbed(*args, ctypes.byref(cdr) if cdr is not None else None,
+                                        ctypes.byref(wind) if wind is not None else None)
     else:
         fn = _load().orc_step if integrator == "euler" else _load().orc_step_rk4
         rc = fn(*args)

@@ -445,6 +445,127 @@ void orc_integrate(const orc_params *P, double dt, const double Fw[3], const dou
 /* Whole batched step.                                                       */
 /* ------------------------------------------------------------------------ */
 
+/* ------------------------------------------------------------------------ */
+/* Wind (Sec. "Wind and turbulence").                                        */
+/* ------------------------------------------------------------------------ */
+
+/* Philox4x32-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3", SC 2011): ten rounds of two 32x32 -> 64-bit products of
+ * counter words with the round multipliers, the high halves xored with the
+ * other counter words and the round key, the key bumped by the Weyl
+ * constants between rounds. */
+void orc_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+/* A 24-bit uniform in [0, 1) from the top bits of a 32-bit word (exact in
+ * binary32 and binary64). */
+static double unit24(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
+
+/* The random words of drone i at global step t: stream 0 feeds the Dryden
+ * normals, stream 1 the gust trigger and heading. */
+static void wind_words(const orc_wind *W, int32_t i, int64_t t, uint32_t stream, uint32_t out[4])
+{
+    const uint32_t ctr[4] = {(uint32_t)i, (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32),
+                             stream};
+    const uint32_t key[2] = {(uint32_t)(W->seed & 0xffffffffu), (uint32_t)(W->seed >> 32)};
+    orc_philox4x32(ctr, key, out);
+}
+
+/* World-frame wind force on drone i at global step t (pre-step position p and
+ * velocity v); ws = the drone's wind state (Dryden velocity x, y, z in m/s;
+ * gust step counter, -1 when idle; gust heading in rad), updated in place.
+ * Readings (the paper gives the model forms, not their constants or units):
+ *   CONSTANT   F = 1/2 rho CdA |u| u with u = v_mean - v, the air velocity
+ *              relative to the drone;
+ *   DRYDEN     per axis x <- alpha x + sigma sqrt(1 - alpha^2) xi, alpha =
+ *              exp(-dt V / L), L_u = L_v = h / (0.177 + 8.23e-4 h)^1.2 and
+ *              L_w = h with h the height in feet (the MIL-F-8785C low-altitude
+ *              scales) clamped to [10, 1000] ft, lengths back in metres; the
+ *              state is advanced first, then its drag 1/2 rho CdA |x| x acts;
+ *              xi from Box-Muller on Philox words;
+ *   GUST       an idle drone starts a gust when a uniform is below gust_prob,
+ *              heading uniform in [0, 2 pi); a gust lasts n_g = round(T / dt)
+ *              steps (at least 1) and pushes with gust_amp (cos h, sin h, 0)
+ *              sin(pi k / n_g) at its k-th step;
+ *   SINUSOIDAL F = A [sin w tau, cos w tau, 0.3 sin 2 w tau], tau = t dt;
+ *   COMBINED   the sum of the selected models. */
+static void wind_force(const orc_wind *W, double dt, int64_t t, int32_t i, const double p[3],
+                       const double v[3], double *ws, int N, double F[3])
+{
+    F[0] = F[1] = F[2] = 0.0;
+    const double k = 0.5 * W->rho * W->cd_area;
+    if (W->models & ORC_WIND_CONSTANT) {
+        const double u[3] = {W->v_mean[0] - v[0], W->v_mean[1] - v[1], W->v_mean[2] - v[2]};
+        const double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        for (int c = 0; c < 3; ++c) F[c] += k * un * u[c];
+    }
+    if (W->models & ORC_WIND_DRYDEN) {
+        uint32_t r[4];
+        wind_words(W, i, t, 0u, r);
+        const double rad0 = sqrt(-2.0 * log(1.0 - unit24(r[0])));
+        const double rad1 = sqrt(-2.0 * log(1.0 - unit24(r[2])));
+        const double xi[3] = {rad0 * cos(2.0 * M_PI * unit24(r[1])), rad0 * sin(2.0 * M_PI * unit24(r[1])),
+                              rad1 * cos(2.0 * M_PI * unit24(r[3]))};
+        double h = p[2] / 0.3048;
+        h = h < 10.0 ? 10.0 : (h > 1000.0 ? 1000.0 : h);
+        const double Lu = h / pow(0.177 + 8.23e-4 * h, 1.2) * 0.3048, Lw = h * 0.3048;
+        const double au = exp(-dt * W->dryden_airspeed / Lu), aw = exp(-dt * W->dryden_airspeed / Lw);
+        const double a[3] = {au, au, aw};
+        double x[3];
+        for (int c = 0; c < 3; ++c) {
+            x[c] = a[c] * ws[c * N] + W->dryden_sigma * sqrt(1.0 - a[c] * a[c]) * xi[c];
+            ws[c * N] = x[c];
+        }
+        const double xn = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        for (int c = 0; c < 3; ++c) F[c] += k * xn * x[c];
+    }
+    if (W->models & ORC_WIND_GUST) {
+        long ng = lround(W->gust_duration / dt);
+        if (ng < 1) ng = 1;
+        if (ws[3 * N] < 0.0) {
+            uint32_t g[4];
+            wind_words(W, i, t, 1u, g);
+            if (unit24(g[0]) < (double)(float)W->gust_prob) {
+                ws[3 * N] = 0.0;
+                ws[4 * N] = 2.0 * M_PI * unit24(g[1]);
+            }
+        }
+        if (ws[3 * N] >= 0.0) {
+            const double env = sin(M_PI * ws[3 * N] / (double)ng);
+            F[0] += W->gust_amp * cos(ws[4 * N]) * env;
+            F[1] += W->gust_amp * sin(ws[4 * N]) * env;
+            ws[3 * N] += 1.0;
+            if (ws[3 * N] >= (double)ng) ws[3 * N] = -1.0;
+        }
+    }
+    if (W->models & ORC_WIND_SINUSOIDAL) {
+        const double tau = (double)t * dt, wt = W->sin_omega * tau;
+        F[0] += W->sin_amp * sin(wt);
+        F[1] += W->sin_amp * cos(wt);
+        F[2] += W->sin_amp * 0.3 * sin(2.0 * wt);
+    }
+}
+
 /* One drone's physical parameter block under domain randomisation (Table
  * "Recommended domain-randomization ranges"): the nominal block with mass,
  * inertia (one factor for the three principal moments), arm length, kf, km,
@@ -494,7 +615,7 @@ static void dr_params(const orc_params *P, const orc_derived *D, const orc_dr *d
 static int step_impl(const orc_params *P, double dt, uint32_t aero_mask, int act_type, int ctrl_decim,
                      int n_envs, const int32_t *env_offsets, int n_drones, orc_state *s,
                      const double *action, int action_per_step, double *obs, int n_obs_slots,
-                     int n_steps, int64_t step0, int n_threads, const orc_dr *dr)
+                     int n_steps, int64_t step0, int n_threads, const orc_dr *dr, const orc_wind *wind)
 {
     if (n_drones < 0 || n_envs < 0 || n_steps < 0 || ctrl_decim < 1) return -1;
     if (env_offsets[0] != 0 || env_offsets[n_envs] != n_drones) return -1;
@@ -503,6 +624,7 @@ static int step_impl(const orc_params *P, double dt, uint32_t aero_mask, int act
     if (dr && (!dr->scale || (act_type != ORC_ACT_RPM && !s->rpm_cmd) ||
                (dr->delay && (!s->act_hist || !s->act_count))))
         return -1;
+    if (wind && (wind->models & (ORC_WIND_DRYDEN | ORC_WIND_GUST)) && !s->wind) return -1;
     orc_derived D;
     orc_derive(P, &D);
     const int N = n_drones;
@@ -586,6 +708,11 @@ static int step_impl(const orc_params *P, double dt, uint32_t aero_mask, int act
                         Fw[2] += orc_downwash_pair(&Pi, pi_, pj);
                     }
                 }
+                if (wind && wind->models) {
+                    double Fwind[3];
+                    wind_force(wind, dt, step0 + k, i, p, v, s->wind ? s->wind + i : NULL, N, Fwind);
+                    for (int c = 0; c < 3; ++c) Fw[c] += Fwind[c];
+                }
                 orc_integrate(&Pi, dt, Fw, tau, p, q, v, w);
                 for (int c = 0; c < 3; ++c) {
                     s->p[c * N + i] = p[c];
@@ -625,7 +752,7 @@ int orc_step(const orc_params *P, double dt, uint32_t aero_mask, int act_type, i
              int n_steps, int64_t step0, int n_threads)
 {
     return step_impl(P, dt, aero_mask, act_type, ctrl_decim, n_envs, env_offsets, n_drones, s, action,
-                     action_per_step, obs, n_obs_slots, n_steps, step0, n_threads, NULL);
+                     action_per_step, obs, n_obs_slots, n_steps, step0, n_threads, NULL, NULL);
 }
 
 int orc_step_dr(const orc_params *P, double dt, uint32_t aero_mask, int act_type, int ctrl_decim,
@@ -635,7 +762,16 @@ int orc_step_dr(const orc_params *P, double dt, uint32_t aero_mask, int act_type
 {
     if (!dr) return -1;
     return step_impl(P, dt, aero_mask, act_type, ctrl_decim, n_envs, env_offsets, n_drones, s, action,
-                     action_per_step, obs, n_obs_slots, n_steps, step0, n_threads, dr);
+                     action_per_step, obs, n_obs_slots, n_steps, step0, n_threads, dr, NULL);
+}
+
+int orc_step_disturbed(const orc_params *P, double dt, uint32_t aero_mask, int act_type, int ctrl_decim,
+                       int n_envs, const int32_t *env_offsets, int n_drones, orc_state *s,
+                       const double *action, int action_per_step, double *obs, int n_obs_slots,
+                       int n_steps, int64_t step0, int n_threads, const orc_dr *dr, const orc_wind *wind)
+{
+    return step_impl(P, dt, aero_mask, act_type, ctrl_decim, n_envs, env_offsets, n_drones, s, action,
+                     action_per_step, obs, n_obs_slots, n_steps, step0, n_threads, dr, wind);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -63,7 +63,25 @@ typedef struct orc_state {
     double *rpm_cmd;    /* [4][n] controller output held between updates (controller actions) */
     double *act_hist;   /* [ORC_DR_HIST][rows][n] action ring (with action latency) */
     int32_t *act_count; /* [n] actions entered since the ring was cleared (with latency) */
+    /* wind only: [5][n] Dryden velocity x, y, z (m/s), gust step (-1 idle), gust heading (rad) */
+    double *wind;
 } orc_state;
+
+/* Wind (Sec. "Wind and turbulence"); readings at wind_force in md_oracle.c. */
+enum { ORC_WIND_CONSTANT = 1, ORC_WIND_GUST = 2, ORC_WIND_DRYDEN = 4, ORC_WIND_SINUSOIDAL = 8 };
+typedef struct orc_wind {
+    uint32_t models;          /* OR of ORC_WIND_*; all four = COMBINED */
+    double v_mean[3];         /* mean wind, world frame, m/s */
+    double rho, cd_area;      /* air density (kg/m^3) and drag area C_d A (m^2) */
+    double gust_prob;         /* per-step trigger probability of an idle drone */
+    double gust_duration;     /* s */
+    double gust_amp;          /* N */
+    double dryden_sigma;      /* m/s */
+    double dryden_airspeed;   /* V in alpha = exp(-dt V / L), m/s */
+    double sin_amp, sin_omega;/* N, rad/s */
+    uint64_t seed;            /* Philox key */
+} orc_wind;
+void orc_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
 /* Domain randomisation (Table "Recommended domain-randomization ranges"):
  * per-drone multiplicative factors, motor lag and action latency. */
@@ -119,6 +137,13 @@ int orc_step_dr(const orc_params *P, double dt, uint32_t aero_mask, int act_type
                 int n_envs, const int32_t *env_offsets, int n_drones, orc_state *s,
                 const double *action, int action_per_step, double *obs, int n_obs_slots,
                 int n_steps, int64_t step0, int n_threads, const orc_dr *dr);
+
+/* orc_step with optional domain randomisation and optional wind (either may
+ * be NULL). */
+int orc_step_disturbed(const orc_params *P, double dt, uint32_t aero_mask, int act_type, int ctrl_decim,
+                       int n_envs, const int32_t *env_offsets, int n_drones, orc_state *s,
+                       const double *action, int action_per_step, double *obs, int n_obs_slots,
+                       int n_steps, int64_t step0, int n_threads, const orc_dr *dr, const orc_wind *wind);
 
 int orc_step_rk4(const orc_params *P, double dt, uint32_t aero_mask, int act_type, int ctrl_decim,
                  int n_envs, const int32_t *env_offsets, int n_drones, orc_state *s,
