@@ -104,6 +104,7 @@ typedef struct md_state {
     float *p, *q, *v, *w, *pid_int, *rpm, *ctl;
     float *rpm_cmd, *act_hist;
     int32_t *act_count;
+    float *wind; /* [5][n_drones] with wind gusts or turbulence, see md_set_wind */
 } md_state;
 
 typedef struct md_ctx md_ctx;
@@ -136,7 +137,8 @@ const char *md_last_error(const md_ctx *ctx);
 
 /* Bind the ragged environment layout: h_env_offsets[n_envs + 1] (host,
  * int32, non-decreasing, off[0] = 0, off[n_envs] = n_drones).  Each
- * environment may hold 0..1024 drones.  The library packs environments into
+ * environment may hold 0..1024 drones, a context up to 2^25 drones
+ * (MD_E_UNSUPPORTED beyond).  The library packs environments into
  * wavefront bins and uploads its lane tables (synchronously).  Re-binding
  * replaces the previous layout and invalidates captured graphs. */
 md_status md_bind_layout(md_ctx *ctx, const int32_t *h_env_offsets, int n_envs, int n_drones);
@@ -196,6 +198,45 @@ typedef struct md_dr {
 } md_dr;
 md_status md_set_domain_randomization(md_ctx *ctx, const md_dr *dr);
 
+/* Wind (Sec. "Wind and turbulence"): a world-frame force at the centre of
+ * mass of every drone, added to the semi-implicit Euler step (with or without
+ * domain randomisation), evaluated at the pre-step state of global step
+ * t = step0 + k.  Models (OR of bits; all four = COMBINED, their sum):
+ *   CONSTANT    F = 1/2 rho CdA |u| u, u = v_mean - v (air relative to drone);
+ *   GUST        an idle drone starts a gust when a uniform draw is below
+ *               gust_prob; heading uniform in [0, 2 pi); it lasts
+ *               n_g = max(1, round(gust_duration / dt)) steps with force
+ *               gust_amp (cos h, sin h, 0) sin(pi k / n_g) at its k-th step;
+ *   DRYDEN      per-drone turbulence velocity x, per axis
+ *               x <- alpha x + sigma sqrt(1 - alpha^2) xi, alpha = e^{-dt V/L},
+ *               L_u = L_v = h / (0.177 + 8.23e-4 h)^1.2, L_w = h, h the height
+ *               in feet clamped to [10, 1000] (MIL-F-8785C low altitude),
+ *               V = dryden_airspeed; then F = 1/2 rho CdA |x| x;
+ *   SINUSOIDAL  F = sin_amp [sin w t dt, cos w t dt, 0.3 sin 2 w t dt].
+ * Random draws: Philox4x32-10 keyed by seed, counter (drone index, t low,
+ * t high, stream): stream 0 gives the Dryden normals (Box-Muller), stream 1
+ * the gust trigger and heading; uniforms are the top 24 bits x 2^-24.  State:
+ * md_state.wind [5][N] = Dryden x, y, z (m/s), gust step (-1 idle), gust
+ * heading (rad), caller-owned, required with GUST or DRYDEN (start it at
+ * 0, 0, 0, -1, 0).  NULL or models 0 turns wind off.  Errors:
+ * MD_E_INVALID_ARG for unknown bits or negative parameters, MD_E_UNSUPPORTED
+ * with MD_AERO_SURROGATE or MD_INTEG_RK4. */
+#define MD_WIND_CONSTANT 1u
+#define MD_WIND_GUST 2u
+#define MD_WIND_DRYDEN 4u
+#define MD_WIND_SINUSOIDAL 8u
+#define MD_WIND_COMBINED 15u
+typedef struct md_wind {
+    uint32_t models;
+    float v_mean[3];
+    float rho, cd_area;
+    float gust_prob, gust_duration, gust_amp;
+    float dryden_sigma, dryden_airspeed;
+    float sin_amp, sin_omega;
+    uint64_t seed;
+} md_wind;
+md_status md_set_wind(md_ctx *ctx, const md_wind *w);
+
 /* Integrator of md_step (default MD_INTEG_EULER).  MD_INTEG_RK4 is the
  * classic fourth-order Runge-Kutta step, the integrator of the paper's MuJoCo
  * physics modes (Table "Physics modes"): rotor speeds, thrust and torques are
@@ -207,7 +248,7 @@ md_status md_set_domain_randomization(md_ctx *ctx, const md_dr *dr);
  * quaternion is renormalised after the step.  Observations, controllers and
  * all other arguments of md_step behave as with MD_INTEG_EULER.  Errors:
  * MD_E_INVALID_ARG for an unknown value, MD_E_UNSUPPORTED with
- * MD_AERO_SURROGATE or domain randomisation.  Switching to MD_INTEG_RK4 resets a launch
+ * MD_AERO_SURROGATE, domain randomisation or wind.  Switching to MD_INTEG_RK4 resets a launch
  * configuration with lanes_per_drone > 1 to the default. */
 #define MD_INTEG_EULER 0
 #define MD_INTEG_RK4 1

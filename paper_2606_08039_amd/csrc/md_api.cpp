@@ -241,8 +241,10 @@ md_status launch(md_ctx *ctx, const md_state *s, const float *d_action, int acti
     if (rc != MD_OK) return rc;
     StepArgs a;
     a.c = ctx->kc;
-    a.s = StatePtr{s->p, s->q, s->v, s->w, s->pid_int, s->rpm, s->ctl, s->rpm_cmd, s->act_hist, s->act_count};
+    a.s = StatePtr{s->p, s->q, s->v, s->w, s->pid_int, s->rpm, s->ctl, s->rpm_cmd, s->act_hist, s->act_count,
+                   s->wind};
     a.dr = ctx->dr;
+    a.wind = ctx->wind;
     a.action = d_action;
     a.act_step_stride = action_per_step ? (long long)action_rows(ctx->act) * ctx->n_drones : 0;
     a.obs = (n_obs_slots > 0) ? d_obs : nullptr;
@@ -253,7 +255,7 @@ md_status launch(md_ctx *ctx, const md_state *s, const float *d_action, int acti
     a.bins = BinTables{bs->d_slot, bs->d_mmax};
     a.tstride = pair_stride(ctx->max_m);
     hipError_t e = (ctx->integ == MD_INTEG_RK4) ? launch_step_rk4(a, ctx->mask, ctx->act, cfg, bs->n_bins, bs->slots, st)
-                   : ctx->dr_on                ? launch_step_dr(a, ctx->mask, ctx->act, cfg, bs->n_bins, bs->slots, st)
+                   : (ctx->dr_on || ctx->wind.models) ? launch_step_dr(a, ctx->mask, ctx->act, cfg, bs->n_bins, bs->slots, st)
                                                : launch_step(a, ctx->mask, ctx->act, cfg, bs->n_bins, bs->slots, st);
     if (e != hipSuccess) {
         ctx->err = hip_msg("step kernel launch", e);
@@ -414,6 +416,10 @@ md_status md_bind_layout(md_ctx *ctx, const int32_t *h_env_offsets, int n_envs, 
         ctx->err = "md_bind_layout: environments of more than 1024 drones are not supported";
         return MD_E_UNSUPPORTED;
     }
+    if (n_drones > (1 << 25)) {
+        ctx->err = "md_bind_layout: more than 2^25 drones per context are not supported";
+        return MD_E_UNSUPPORTED;
+    }
     (void)hipSetDevice(ctx->device);
     md::invalidate_layout_users(ctx);
     md::free_bins(ctx);
@@ -433,7 +439,7 @@ md_status md_set_integrator(md_ctx *ctx, int integrator) {
         ctx->err = "md_set_integrator: unknown integrator";
         return MD_E_INVALID_ARG;
     }
-    if (integrator == MD_INTEG_RK4 && ((ctx->mask & MD_AERO_SURROGATE) || ctx->dr_on)) {
+    if (integrator == MD_INTEG_RK4 && ((ctx->mask & MD_AERO_SURROGATE) || ctx->dr_on || ctx->wind.models)) {
         ctx->err = "md_set_integrator: the learned residual and domain randomisation run with the "
                    "semi-implicit Euler step only";
         return MD_E_UNSUPPORTED;
@@ -467,6 +473,39 @@ md_status md_set_domain_randomization(md_ctx *ctx, const md_dr *dr) {
     return MD_OK;
 }
 
+md_status md_set_wind(md_ctx *ctx, const md_wind *w) {
+    if (!ctx) return MD_E_INVALID_ARG;
+    if (!w || w->models == 0) {
+        ctx->wind = md::WindArgs{};
+        return MD_OK;
+    }
+    if ((w->models & ~MD_WIND_COMBINED) || !(w->rho >= 0.f) || !(w->cd_area >= 0.f) || !(w->gust_prob >= 0.f) ||
+        !(w->gust_prob <= 1.f) || !(w->gust_amp >= 0.f) || !(w->dryden_sigma >= 0.f) ||
+        !(w->dryden_airspeed >= 0.f) || ((w->models & MD_WIND_GUST) && !(w->gust_duration > 0.f))) {
+        ctx->err = "md_set_wind: unknown model bits or a negative / non-finite parameter";
+        return MD_E_INVALID_ARG;
+    }
+    if ((ctx->mask & MD_AERO_SURROGATE) || ctx->integ == MD_INTEG_RK4) {
+        ctx->err = "md_set_wind: supported with the plain semi-implicit Euler step only";
+        return MD_E_UNSUPPORTED;
+    }
+    md::WindArgs a{};
+    a.models = w->models;
+    for (int k = 0; k < 3; ++k) a.vm[k] = w->v_mean[k];
+    a.kd = (float)(0.5 * (double)w->rho * (double)w->cd_area);
+    a.gust_prob = w->gust_prob;
+    a.gust_amp = w->gust_amp;
+    a.gust_steps = std::max(1L, std::lround((double)w->gust_duration / (double)ctx->dt));
+    a.sigma = w->dryden_sigma;
+    a.airspeed = w->dryden_airspeed;
+    a.sin_amp = w->sin_amp;
+    a.sin_wdt = (double)w->sin_omega * (double)ctx->dt;
+    a.key0 = (uint32_t)(w->seed & 0xffffffffull);
+    a.key1 = (uint32_t)(w->seed >> 32);
+    ctx->wind = a;
+    return MD_OK;
+}
+
 md_status md_get_integrator(const md_ctx *ctx, int *out) {
     if (!ctx || !out) return MD_E_INVALID_ARG;
     *out = ctx->integ;
@@ -494,6 +533,10 @@ md_status md_step(md_ctx *ctx, const md_state *s, const float *d_action, int act
                        (ctx->dr.delay && (!s->act_hist || !s->act_count)))) {
         ctx->err = "md_step: domain randomisation needs rpm_cmd (controller actions) and, with delays, "
                    "act_hist and act_count";
+        return MD_E_INVALID_ARG;
+    }
+    if ((ctx->wind.models & (MD_WIND_GUST | MD_WIND_DRYDEN)) && !s->wind) {
+        ctx->err = "md_step: wind gusts and turbulence need the wind state block";
         return MD_E_INVALID_ARG;
     }
     if (ctx->mask & MD_AERO_SURROGATE) return md::surrogate_step(ctx, s, d_action, action_per_step, d_obs,

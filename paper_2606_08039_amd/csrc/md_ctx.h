@@ -36,6 +36,7 @@ struct md_ctx {
     int integ = MD_INTEG_EULER;
     bool dr_on = false;
     md::DrPtr dr{nullptr, nullptr, nullptr};
+    md::WindArgs wind{};  // models == 0: off
     int device = 0;
     int n_cu = 0;
     md::KConst kc{};

@@ -34,6 +34,20 @@ struct StatePtr {
     float *p, *q, *v, *w, *pid_int, *rpm, *ctl;
     float *rpm_cmd, *act_hist;  // domain randomisation: held command, action ring
     int32_t *act_count;         // domain randomisation: ring fill per drone
+    float *wind;                // wind: [5][N] Dryden velocity, gust step, gust heading
+};
+
+// Wind parameters (md_wind) prepared on the host.
+struct WindArgs {
+    uint32_t models;            // MD_WIND_* bits, 0 = off
+    float vm[3];                // mean wind, m/s
+    float kd;                   // rho CdA / 2
+    float gust_prob, gust_amp;  // per-step trigger probability, N
+    int gust_steps;             // round(duration / dt), >= 1
+    float sigma, airspeed;      // Dryden sigma (m/s) and V (m/s)
+    float sin_amp;              // N
+    double sin_wdt;             // sinusoid phase per step, omega dt (rad)
+    uint32_t key0, key1;        // Philox key (seed)
 };
 
 // Domain randomisation inputs (md_dr), device pointers.
@@ -69,7 +83,8 @@ struct StepArgs {
     int N;
     BinTables bins;
     int tstride;  // row stride (floats) of the pair-term matrix in LDS (sym sweep)
-    DrPtr dr;     // domain randomisation (used by the DR instantiation only)
+    DrPtr dr;       // domain randomisation (used by the disturbed instantiation only)
+    WindArgs wind;  // wind (disturbed instantiation only)
 };
 
 // Row stride (floats) of the pair-term matrix of the pair-symmetric sweep: a

@@ -84,6 +84,20 @@ __device__ __forceinline__ void euler_zyx(const Drone &d, float &roll, float &pi
     yaw = atan2_poly(2.f * (w * z + x * y), 1.f - 2.f * (y * y + z * z));
 }
 
+// One drone's KIN-20 row into ring slot `oslot` ([slot][20][N]) through a
+// buffer resource whose base is the slot (wave-uniform, so it lives in
+// scalar registers): each row is one buffer store with the lane's byte
+// offset and the row offset k N 4 as the scalar offset, no per-row address
+// arithmetic on the vector ALU (n_drones <= 2^25 keeps 80 N within 32 bits).
+__device__ __forceinline__ void store_obs(float *obs, int oslot, int N, int di, const float row[20]) {
+    float *base = obs + (long long)oslot * 20 * N;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)0xffffffffu, 0x00020000);
+    const int voff = di * 4;
+#pragma unroll
+    for (int k = 0; k < 20; ++k)
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(row[k]), rs, voff, (int)((uint32_t)k * (uint32_t)N * 4u), 0);
+}
+
 __device__ __forceinline__ float clampf(float x, float lo, float hi) {
     return fminf(fmaxf(x, lo), hi);
 }

@@ -166,11 +166,9 @@ __global__ void __launch_bounds__(1024) rk4_kernel(StepArgs a) {
         if (a.obs != nullptr && valid) {
             float roll, pitch, yaw;
             euler_zyx(d, roll, pitch, yaw);
-            float *o = a.obs + (long long)oslot * 20 * N + di;
             const float row[20] = {d.px, d.py, d.pz, d.qw, d.qx, d.qy, d.qz, roll, pitch, yaw,
                                    d.vx, d.vy, d.vz, d.wx, d.wy, d.wz, n[0], n[1], n[2], n[3]};
-#pragma unroll
-            for (int k = 0; k < 20; ++k) o[(long long)k * N] = row[k];
+            store_obs(a.obs, oslot, N, di, row);
         }
         oslot = (oslot + 1 == a.n_obs_slots) ? 0 : oslot + 1;
     }

@@ -17,14 +17,17 @@
 //   downwash       sum over higher drones j of -C1 (r_p/4dz)^2 exp(-(dxy/beta)^2/2) (Eq. 6)
 //   integrator     semi-implicit Euler, body-rate exponential map, renormalise (Eq. 7)
 //
-// Domain randomisation (DR = true; Sec. "Domain randomization", Table
+// Disturbed instantiation (DR = true): domain randomisation and wind.
+// Domain randomisation (Sec. "Domain randomization", Table
 // "Recommended domain-randomization ranges"): each drone carries its own
 // physical constants (mass, inertia, arm length, kf, km, drag, C_gnd, C1, g,
 // MAX_RPM as factors of the nominal ones) in registers for the launch, and
 // an actuator chain before the motor model: action latency through a ring of
 // MD_DR_HIST past actions, per-motor bias, clip to the drone's MAX_RPM, and a
 // first-order motor lag n <- n + (1 - e^{-dt/tau})(c - n).  Controllers keep
-// the nominal constants.
+// the nominal constants.  Wind (Sec. "Wind and turbulence"): constant-wind
+// drag, gusts, Dryden turbulence and a sinusoid, with per-drone state in
+// registers and Philox4x32-10 draws keyed by (drone, global step).
 #pragma once
 
 #include "md_sweep.h"
@@ -60,6 +63,91 @@ __device__ __forceinline__ void dr_constants(const KConst &c, const DrPtr &dr, i
     cl.max_rpm = c.max_rpm * dr.scale[MD_DR_MAXRPM * N + di];
 #pragma unroll
     for (int k = 0; k < 4; ++k) bias[k] = dr.scale[(MD_DR_BIAS + k) * N + di];
+}
+
+// Philox4x32-10 (Salmon et al., SC 2011): ten rounds of the two 32x32-bit
+// products with the round multipliers, high halves xored with the other
+// counter words and the round key, key bumped by the Weyl constants.
+__device__ __forceinline__ uint4 philox4x32(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__device__ __forceinline__ float unit24(uint32_t x) { return (float)(x >> 8) * (1.f / 16777216.f); }
+
+// World-frame wind force of one drone at global step t (pre-step state d);
+// ws = the drone's wind state (Dryden x, y, z; gust step, -1 idle; gust
+// heading), updated in place.  Models as documented at md_set_wind.
+__device__ __forceinline__ void wind_force(const WindArgs &W, float dt, long long t, int di, const Drone &d,
+                                           float ws[5], float &Fx, float &Fy, float &Fz) {
+    Fx = Fy = Fz = 0.f;
+    const uint32_t tl = (uint32_t)((unsigned long long)t & 0xffffffffull);
+    const uint32_t th = (uint32_t)((unsigned long long)t >> 32);
+    if (W.models & MD_WIND_CONSTANT) {
+        const float ux = W.vm[0] - d.vx, uy = W.vm[1] - d.vy, uz = W.vm[2] - d.vz;
+        const float kn = W.kd * fsqrt(ux * ux + uy * uy + uz * uz);
+        Fx += kn * ux;
+        Fy += kn * uy;
+        Fz += kn * uz;
+    }
+    if (W.models & MD_WIND_DRYDEN) {
+        const uint4 r = philox4x32(make_uint4((uint32_t)di, tl, th, 0u), W.key0, W.key1);
+        const float rad0 = fsqrt(-2.f * logf(1.f - unit24(r.x)));
+        const float rad1 = fsqrt(-2.f * logf(1.f - unit24(r.z)));
+        float s1, c1, s3, c3;
+        sincospif(2.f * unit24(r.y), &s1, &c1);
+        sincospif(2.f * unit24(r.w), &s3, &c3);
+        const float xi[3] = {rad0 * c1, rad0 * s1, rad1 * c3};
+        const float h = clampf(d.pz * (1.f / 0.3048f), 10.f, 1000.f);
+        const float Lu = h / powf(0.177f + 8.23e-4f * h, 1.2f) * 0.3048f, Lw = h * 0.3048f;
+        const float cu = dt * W.airspeed / Lu, cw = dt * W.airspeed / Lw;
+        // alpha = e^{-c}; 1 - alpha^2 = -expm1(-2c) without cancellation
+        const float au = expf(-cu), aw = expf(-cw);
+        const float bu = W.sigma * fsqrt(-expm1f(-2.f * cu)), bw = W.sigma * fsqrt(-expm1f(-2.f * cw));
+        ws[0] = au * ws[0] + bu * xi[0];
+        ws[1] = au * ws[1] + bu * xi[1];
+        ws[2] = aw * ws[2] + bw * xi[2];
+        const float kn = W.kd * fsqrt(ws[0] * ws[0] + ws[1] * ws[1] + ws[2] * ws[2]);
+        Fx += kn * ws[0];
+        Fy += kn * ws[1];
+        Fz += kn * ws[2];
+    }
+    if (W.models & MD_WIND_GUST) {
+        if (ws[3] < 0.f) {
+            const uint4 g = philox4x32(make_uint4((uint32_t)di, tl, th, 1u), W.key0, W.key1);
+            if (unit24(g.x) < W.gust_prob) {
+                ws[3] = 0.f;
+                ws[4] = 6.283185307179586f * unit24(g.y);
+            }
+        }
+        if (ws[3] >= 0.f) {
+            const float env = sinpif(ws[3] / (float)W.gust_steps);
+            float sh, ch;
+            sincosf(ws[4], &sh, &ch);
+            Fx += W.gust_amp * ch * env;
+            Fy += W.gust_amp * sh * env;
+            ws[3] += 1.f;
+            if (ws[3] >= (float)W.gust_steps) ws[3] = -1.f;
+        }
+    }
+    if (W.models & MD_WIND_SINUSOIDAL) {
+        // phase reduced in double: t dt grows without bound
+        const double ph = W.sin_wdt * (double)t;
+        const double red = ph - 6.283185307179586 * floor(ph * (1.0 / 6.283185307179586));
+        float s1, c1, s2, c2;
+        sincosf((float)red, &s1, &c1);
+        sincosf((float)(2.0 * red), &s2, &c2);
+        Fx += W.sin_amp * s1;
+        Fy += W.sin_amp * c1;
+        Fz += W.sin_amp * 0.3f * s2;
+    }
 }
 
 template <uint32_t MASK, int ACT, int LPD, int UNROLL, bool SYM, bool DR>
@@ -112,8 +200,12 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     int delay = 0, issued = 0;  // action latency (steps) and ring fill
     float cmdh[4] = {0.f, 0.f, 0.f, 0.f};  // controller output held between updates
     const bool ring = DR && a.dr.delay != nullptr;
+    float ws[5] = {0.f, 0.f, 0.f, -1.f, 0.f};  // wind state
+    const bool windy = DR && a.wind.models != 0u;
+    if (windy && valid && a.s.wind != nullptr)
+        for (int k = 0; k < 5; ++k) ws[k] = a.s.wind[k * N + di];
     if (DR && valid) {
-        dr_constants(c, a.dr, N, di, cl, bias);
+        if (a.dr.scale != nullptr) dr_constants(c, a.dr, N, di, cl, bias);
         const float tau = a.dr.tau_mot ? a.dr.tau_mot[di] : 0.f;
         has_lag = tau > 0.f;
         lag = has_lag ? 1.f - expf(-c.dt / tau) : 1.f;
@@ -221,17 +313,23 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
                                                        uniform, d);
             Fz -= cl.K1 * acc;
         }
+        // ---- wind
+        if (windy && valid) {
+            float wx, wy, wz;
+            wind_force(a.wind, c.dt, a.step0 + step, di, d, ws, wx, wy, wz);
+            Fx += wx;
+            Fy += wy;
+            Fz += wz;
+        }
         // ---- Newton-Euler + exponential map (Eq. 7)
         integrate(cl, d, Fx, Fy, Fz, tx, ty, tz);
         // ---- KIN observation
         if (a.obs != nullptr && writer) {
             float roll, pitch, yaw;
             euler_zyx(d, roll, pitch, yaw);
-            float *o = a.obs + (long long)oslot * 20 * N + di;
             const float orow[20] = {d.px, d.py, d.pz, d.qw, d.qx, d.qy, d.qz, roll, pitch, yaw,
                                     d.vx, d.vy, d.vz, d.wx, d.wy, d.wz, n[0], n[1], n[2], n[3]};
-#pragma unroll
-            for (int k = 0; k < 20; ++k) o[(long long)k * N] = orow[k];
+            store_obs(a.obs, oslot, N, di, orow);
         }
         oslot = (oslot + 1 == a.n_obs_slots) ? 0 : oslot + 1;
     }
@@ -259,6 +357,8 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         if (DR && ACT >= 1)
             for (int k = 0; k < 4; ++k) a.s.rpm_cmd[k * N + di] = cmdh[k];
         if (ring) a.s.act_count[di] = issued;
+        if (windy && a.s.wind != nullptr)
+            for (int k = 0; k < 5; ++k) a.s.wind[k * N + di] = ws[k];
     }
 }
 

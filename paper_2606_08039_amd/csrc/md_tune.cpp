@@ -147,8 +147,9 @@ md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int ac
     }
     // scratch copies of the state: the caller's state is never advanced
     const bool dr = ctx->dr_on, ring = dr && ctx->dr.delay != nullptr;
-    const size_t nr[10] = {3, 4, 3, 3, 6, 4, 4, dr ? 4u : 0u,
-                           ring ? (size_t)MD_DR_HIST * action_rows(ctx->act) : 0u, ring ? 1u : 0u};
+    const size_t nr[11] = {3, 4, 3, 3, 6, 4, 4, dr ? 4u : 0u,
+                           ring ? (size_t)MD_DR_HIST * action_rows(ctx->act) : 0u, ring ? 1u : 0u,
+                           (ctx->wind.models && s->wind) ? 5u : 0u};
     size_t rows = 0;
     for (size_t r : nr) rows += r;
     float *scratch = nullptr, *work = nullptr;
@@ -160,12 +161,12 @@ md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int ac
         return MD_E_OOM;
     }
     // act_count is int32: copied bit for bit through a float-sized slot
-    const float *src[10] = {s->p, s->q, s->v, s->w, s->pid_int, s->rpm, s->ctl, s->rpm_cmd, s->act_hist,
-                            (const float *)s->act_count};
+    const float *src[11] = {s->p, s->q, s->v, s->w, s->pid_int, s->rpm, s->ctl, s->rpm_cmd, s->act_hist,
+                            (const float *)s->act_count, s->wind};
     size_t o = 0;
     md_state ws{};
-    float *blk[10] = {};
-    for (int k = 0; k < 10 && e == hipSuccess; ++k) {
+    float *blk[11] = {};
+    for (int k = 0; k < 11 && e == hipSuccess; ++k) {
         if (nr[k] == 0) continue;
         if (src[k])
             e = hipMemcpyAsync(scratch + o, src[k], sizeof(float) * nr[k] * N, hipMemcpyDeviceToDevice, st);
@@ -184,6 +185,7 @@ md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int ac
     ws.rpm_cmd = blk[7];
     ws.act_hist = blk[8];
     ws.act_count = (int32_t *)blk[9];
+    ws.wind = blk[10];
     hipEvent_t a = nullptr, b = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);

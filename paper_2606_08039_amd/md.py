@@ -51,7 +51,19 @@ class md_derived(ctypes.Structure):
 
 class md_state(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("p", "q", "v", "w", "pid_int", "rpm", "ctl",
-                                               "rpm_cmd", "act_hist", "act_count")]
+                                               "rpm_cmd", "act_hist", "act_count", "wind")]
+
+
+class md_wind(ctypes.Structure):
+    _fields_ = [("models", ctypes.c_uint32), ("v_mean", ctypes.c_float * 3), ("rho", ctypes.c_float),
+                ("cd_area", ctypes.c_float), ("gust_prob", ctypes.c_float), ("gust_duration", ctypes.c_float),
+                ("gust_amp", ctypes.c_float), ("dryden_sigma", ctypes.c_float),
+                ("dryden_airspeed", ctypes.c_float), ("sin_amp", ctypes.c_float), ("sin_omega", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+MD_WIND_CONSTANT, MD_WIND_GUST, MD_WIND_DRYDEN, MD_WIND_SINUSOIDAL = 1, 2, 4, 8
+MD_WIND_COMBINED = 15
 
 
 class md_dr(ctypes.Structure):
@@ -217,6 +229,16 @@ class DeviceState:
                     self.t[k].copy_(torch.from_numpy(np.ascontiguousarray(s[k], dtype=dt)))
         return self
 
+    def add_wind_block(self, s=None):
+        """The wind state block (Dryden velocity 0, gusts idle, or s["wind"])."""
+        import torch
+        w = torch.zeros((5, self.n), dtype=torch.float32, device=self.t["p"].device)
+        w[3] = -1.0
+        if s is not None and "wind" in s:
+            w.copy_(torch.from_numpy(np.ascontiguousarray(s["wind"], dtype=np.float32)))
+        self.t["wind"] = w
+        return self
+
     def to_numpy(self):
         return {k: v.cpu().numpy() for k, v in self.t.items()}
 
@@ -229,7 +251,7 @@ class DeviceState:
     def as_md_state(self):
         return md_state(*[self.t[k].data_ptr() if k in self.t else None
                           for k in ("p", "q", "v", "w", "pid_int", "rpm", "ctl", "rpm_cmd", "act_hist",
-                                    "act_count")])
+                                    "act_count", "wind")])
 
 
 # ------------------------------------------------------------------ surrogate network
@@ -378,6 +400,20 @@ def md_set_domain_randomization(ctx, scale=None, tau_mot=None, delay=None):
     d = md_dr(scale.data_ptr(), tau_mot.data_ptr() if tau_mot is not None else None,
               delay.data_ptr() if delay is not None else None)
     check(lib().md_set_domain_randomization(ctx, ctypes.byref(d)), ctx)
+
+
+# ------------------------------------------------------------------ wind
+
+def md_set_wind(ctx, models=0, v_mean=(0.0, 0.0, 0.0), rho=1.225, cd_area=0.01, gust_prob=0.0,
+                gust_duration=0.5, gust_amp=0.0, dryden_sigma=0.0, dryden_airspeed=1.0, sin_amp=0.0,
+                sin_omega=0.0, seed=0):
+    """models 0 turns wind off."""
+    if not models:
+        check(lib().md_set_wind(ctx, None), ctx)
+        return
+    w = md_wind(int(models), (ctypes.c_float * 3)(*v_mean), rho, cd_area, gust_prob, gust_duration, gust_amp,
+                dryden_sigma, dryden_airspeed, sin_amp, sin_omega, int(seed))
+    check(lib().md_set_wind(ctx, ctypes.byref(w)), ctx)
 
 
 # ------------------------------------------------------------------ integrator

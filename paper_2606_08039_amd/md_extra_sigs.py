@@ -28,6 +28,7 @@ def signatures():
         "md_judge_reset": (_I32, [_VP]),
         "md_set_integrator": (_I32, [_VP, ctypes.c_int]),
         "md_set_domain_randomization": (_I32, [_VP, _VP]),
+        "md_set_wind": (_I32, [_VP, _VP]),
         "md_get_integrator": (_I32, [_VP, ctypes.POINTER(ctypes.c_int)]),
         "md_get_launch_config": (_I32, [_VP, _VP]),
         "md_set_launch_config": (_I32, [_VP, _VP]),

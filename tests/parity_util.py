@@ -54,6 +54,9 @@ class GpuRun:
                        for k in ("scale", "tau_mot", "delay")}
             self.state.add_dr_blocks(ACT[w["act_type"]], w["state"])
             md.md_set_domain_randomization(self.ctx, self.dr["scale"], self.dr["tau_mot"], self.dr["delay"])
+        if w.get("wind") is not None:
+            self.state.add_wind_block(w["state"])
+            md.md_set_wind(self.ctx, **w["wind"])
         self.action = torch.from_numpy(np.ascontiguousarray(w["action"], dtype=np.float32)).cuda()
         self.step_index = 0
 
@@ -118,11 +121,25 @@ def oracle_one_step(w, s32, k, env_subset=None, mask=None, n_steps=1, obs_slots=
         dr["scale"] = dr["scale"].astype(np.float64)
         if dr.get("tau_mot") is not None:
             dr["tau_mot"] = dr["tau_mot"].astype(np.float64)
+    wind = None
+    if w.get("wind") is not None:
+        wk = dict(w["wind"])
+        # the GPU takes float32 parameters; hand the oracle the same values
+        f32 = lambda x: float(np.float32(x))
+        for key in ("rho", "cd_area", "gust_prob", "gust_duration", "gust_amp", "dryden_sigma",
+                    "dryden_airspeed", "sin_amp", "sin_omega"):
+            if key in wk:
+                wk[key] = f32(wk[key])
+        if "v_mean" in wk:
+            wk["v_mean"] = tuple(f32(x) for x in wk["v_mean"])
+        wind = orc.make_wind(**wk)
+    if wind is not None and idx is not None:
+        raise ValueError("wind parity runs on whole workloads (the draws are keyed by drone index)")
     obs = orc.step(P, w["dt"], w["aero_mask"] if mask is None else mask,
                    ORC_ACT[w["act_type"]], w["ctrl_decim"],
                    sub_off, s, np.ascontiguousarray(a, dtype=np.float64), w["action_per_step"],
                    n_steps, step0=k, n_obs_slots=obs_slots,
-                   integrator=w.get("integrator", "euler"), dr=dr)
+                   integrator=w.get("integrator", "euler"), dr=dr, wind=wind)
     return s, obs, idx
 
 

@@ -1,0 +1,97 @@
+"""GPU parity of the wind models (md_set_wind) against the oracle's wind
+(orc_step_disturbed): both sides draw from their own Philox4x32-10 keyed by
+(drone, global step), so gust triggers agree exactly and the Dryden normals
+to rounding.  Per-step criterion from GPU snapshots, including the wind
+state block; wind together with domain randomisation; error paths."""
+import numpy as np
+import pytest
+
+import parity_util as pu
+from paper_2606_08039_amd import md, workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+COMBINED = dict(models=md.MD_WIND_COMBINED, v_mean=(0.9, -0.4, 0.0), rho=1.225, cd_area=0.012,
+                gust_prob=0.02, gust_duration=0.25, gust_amp=0.03, dryden_sigma=0.6, dryden_airspeed=4.0,
+                sin_amp=0.01, sin_omega=2.5, seed=2024)
+
+
+def _parity(w, ks, blocks):
+    worst = {}
+    g = pu.GpuRun(w)
+    try:
+        for k in ks:
+            if k > g.step_index:
+                g.run(k - g.step_index)
+            s0 = g.snapshot()
+            gobs = g.run(1, obs_slots=1)
+            s1 = g.snapshot()
+            ref, robs, _ = pu.oracle_one_step(w, s0, k, obs_slots=1)
+            e = pu.assert_blocks(s1, ref, blocks=blocks, what="wind step %d" % k)
+            sc = np.maximum(np.max(np.abs(robs[0]), axis=0), 1.0)
+            assert np.max(np.max(np.abs(gobs[0] - robs[0]), axis=0) / sc) <= pu.TOL, k
+            worst = {kk: max(worst.get(kk, 0.0), v) for kk, v in e.items()}
+    finally:
+        g.close()
+    return worst
+
+
+def test_combined_wind_on_formation_subset():
+    w = dict(wl.subset_envs(wl.formation(n_envs=8192, n_steps=1000, seed=4), 256), wind=COMBINED)
+    worst = _parity(w, [0, 1, 2, 5, 61, 62, 200, 333], pu.BLOCKS + ("pid_int", "wind"))
+    print("combined wind, formation 256 envs, worst:", worst)
+
+
+def test_wind_with_domain_randomization():
+    base = wl.subset_envs(wl.formation(n_envs=8192, n_steps=1000, seed=4), 128)
+    w = dict(base, wind=dict(COMBINED, seed=7), dr=wl.domain_randomization(base, 60))
+    _parity(w, [0, 1, 13, 120], pu.BLOCKS + ("pid_int", "rpm_cmd", "wind"))
+
+
+def test_stateless_wind_with_rotor_speed_actions():
+    w = dict(wl.ragged_grid(pu.hover_rpm(), n_envs=128, n_steps=40, seed=2),
+             wind=dict(models=md.MD_WIND_CONSTANT | md.MD_WIND_SINUSOIDAL, v_mean=(0.5, 0.2, -0.1),
+                       cd_area=0.02, sin_amp=0.02, sin_omega=4.0))
+    _parity(w, [0, 1, 17, 39], pu.BLOCKS)
+
+
+def test_gusts_start_and_end_on_schedule():
+    """With trigger probability 1 every drone starts a gust at once; it lasts
+    round(duration / dt) steps, then a new one starts."""
+    w = dict(wl.subset_envs(wl.formation(n_envs=8192, n_steps=1000, seed=4), 8),
+             wind=dict(models=md.MD_WIND_GUST, gust_prob=1.0, gust_duration=0.1, gust_amp=0.02, seed=3))
+    g = pu.GpuRun(w)
+    g.run(23)
+    s = g.snapshot()
+    assert np.all(s["wind"][3] == 23 - 24)  # 24 steps: the 24th step ended the first gust
+    g.run(1)
+    s = g.snapshot()
+    assert np.all(s["wind"][3] == 1)
+    g.close()
+
+
+def test_error_paths():
+    import torch
+    p = md.md_default_params_cf2x()
+    ctx = md.md_create(p, wl.DT, md.MD_AERO_SURROGATE, md.MD_ACT_PID, 5)
+    with pytest.raises(md.MdError):
+        md.md_set_wind(ctx, **COMBINED)
+    md.md_destroy(ctx)
+    ctx = md.md_create(p, wl.DT, 7, md.MD_ACT_PID, 5)
+    with pytest.raises(md.MdError):
+        md.md_set_wind(ctx, models=64)
+    with pytest.raises(md.MdError):
+        md.md_set_wind(ctx, models=md.MD_WIND_GUST, gust_duration=0.0)
+    md.md_set_wind(ctx, **COMBINED)
+    with pytest.raises(md.MdError):
+        md.md_set_integrator(ctx, md.MD_INTEG_RK4)
+    md.md_bind_layout(ctx, np.array([0, 4], dtype=np.int32))
+    st = md.DeviceState(4)
+    act = torch.zeros((1, 4, 4), dtype=torch.float32, device="cuda")
+    with pytest.raises(md.MdError):
+        md.md_step(ctx, st, act, False, None, 0, 1, 0)  # no wind block
+    st.add_wind_block()
+    md.md_step(ctx, st, act, False, None, 0, 1, 0)
+    md.md_set_wind(ctx, 0)
+    md.md_destroy(ctx)
+    torch.cuda.synchronize()
