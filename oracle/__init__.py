@@ -51,7 +51,8 @@ class Derived(ctypes.Structure):
 
 
 class Net(ctypes.Structure):
-    _fields_ = [("W", _D_T * 4), ("b", _D_T * 4), ("norm", _D_T), ("dz_ood", ctypes.c_double)]
+    _fields_ = [("W", _D_T * 4), ("b", _D_T * 4), ("norm", _D_T), ("dz_ood", ctypes.c_double),
+                ("ood_speed", ctypes.c_double), ("ood_rel_speed", ctypes.c_double), ("ood_tilt", ctypes.c_double)]
 
 
 class _CState(ctypes.Structure):
@@ -483,10 +484,11 @@ def bf16_round(x):
     return np.vectorize(f, otypes=[np.float64])(np.asarray(x, dtype=np.float64))
 
 
-def make_net(flat_params, norm, dz_ood):
+def make_net(flat_params, norm, dz_ood, ood_speed=0.0, ood_rel_speed=0.0, ood_tilt=0.0):
     """The surrogate as the oracle evaluates it: weight matrices rounded to
     bfloat16 (as the in-step network stores them), biases and normalisation
-    as given (float32 values).  Returns (Net, keepalive)."""
+    as given (float32 values), fallback thresholds as float32 values.
+    Returns (Net, keepalive)."""
     flat = np.asarray(flat_params, dtype=np.float32).astype(np.float64)
     shapes = ((128, 64), (128,), (128, 128), (128,), (128, 128), (128,), (6, 128), (6,))
     parts, o = [], 0
@@ -503,6 +505,9 @@ def make_net(flat_params, norm, dz_ood):
         net.b[l] = _dp(bs[l])
     net.norm = _dp(nrm)
     net.dz_ood = float(np.float32(dz_ood))
+    net.ood_speed = float(np.float32(ood_speed))
+    net.ood_rel_speed = float(np.float32(ood_rel_speed))
+    net.ood_tilt = float(ood_tilt)
     return net, (Ws, bs, nrm)
 
 

@@ -1264,8 +1264,13 @@ void orc_adam(int n, double *param, const double *grad, double *m1, double *m2, 
 
 /* Per drone and step: rotor speeds and motor model as in orc_step; the 8
  * nearest neighbours (binary32 decisions, see orc_knn) and the raw inputs;
- * fallback when a neighbour is above by less than dz_ood (the difference
- * formed in binary32, as the GPU forms it) -> the plain Eq. (4)-(6) force;
+ * fallback -> the plain Eq. (4)-(6) force when a neighbour is above by less
+ * than dz_ood, or (each check optional) when the drone leaves the region the
+ * network was trained on: a world velocity component beyond ood_speed, a
+ * neighbour's relative velocity component beyond ood_rel_speed, or a tilt
+ * beyond ood_tilt (qx^2 + qy^2 > sin^2(ood_tilt / 2)).  Every fallback
+ * decision is taken in binary32 on quantities the GPU forms exactly the same
+ * way (differences of stored values; qx*qx + qy*qy with rounded operations);
  * otherwise inputs standardised x' = (x - mean) * inv_std, rounded to
  * bfloat16, the network (W already rounded to bfloat16 by the caller; hidden
  * outputs rounded to bfloat16, sums in double), y = y' * y_std + y_mean,
@@ -1339,10 +1344,25 @@ int orc_step_surrogate(const orc_params *P, double dt, int act_type, int ctrl_de
 
                 const int32_t *nb = nbr + (size_t)i * K;
                 int ood = 0;
+                const float vrel = (float)net->ood_rel_speed;
                 for (int t = 0; t < K; ++t) {
                     if (nb[t] < 0) continue;
                     const float dz = (float)p_pre[2 * N + nb[t]] - (float)p_pre[2 * N + i];
                     if (dz > 0.0f && dz < (float)net->dz_ood) ood = 1;
+                    for (int c = 0; c < 3 && vrel > 0.0f; ++c) {
+                        const float dv = (float)v_pre[c * N + nb[t]] - (float)v_pre[c * N + i];
+                        if (fabsf(dv) > vrel) ood = 1;
+                    }
+                }
+                if (net->ood_speed > 0.0)
+                    for (int c = 0; c < 3; ++c)
+                        if (fabsf((float)v[c]) > (float)net->ood_speed) ood = 1;
+                if (net->ood_tilt > 0.0) {
+                    const double sh = sin(0.5 * net->ood_tilt);
+                    volatile float a = (float)q[1] * (float)q[1];
+                    volatile float b = (float)q[2] * (float)q[2];
+                    volatile float t2 = a + b;
+                    if (t2 > (float)(sh * sh)) ood = 1;
                 }
                 double yb[6];
                 if (ood) {

@@ -174,6 +174,10 @@ typedef struct orc_net {
     const double *b[4]; /* [128], [128], [128], [6] */
     const double *norm; /* x_mean[64], x_inv_std[64], y_mean[6], y_std[6] */
     double dz_ood;
+    /* out-of-distribution fallback (0 = that check off): own world speed
+     * component above ood_speed, a neighbour's relative speed component
+     * above ood_rel_speed, tilt above ood_tilt (rad) */
+    double ood_speed, ood_rel_speed, ood_tilt;
 } orc_net;
 
 int orc_step_surrogate(const orc_params *P, double dt, int act_type, int ctrl_decim, int n_envs,

@@ -271,3 +271,31 @@ def test_surrogate_fallback_takes_the_plain_terms():
     orc.step(P, 1 / 240, 7, orc.ACT_RPM, 1, off, s_ref, act, False, 1)
     for k in ("p", "v", "w", "q"):
         np.testing.assert_allclose(s[k][:, 0], s_ref[k][:, 0], rtol=1e-12, atol=1e-15)
+
+
+def test_out_of_distribution_fallback_checks():
+    """Each optional check sends exactly the drones beyond its threshold to the
+    plain terms: a fast drone (speed), a drone whose neighbour moves fast
+    relative to it (relative speed, both members of the pair), a tilted drone
+    (tilt), with the thresholds just above and below the values."""
+    P = orc.cf2x()
+    D = orc.derive(P)
+    s0, off = _lattice_pair_state(0.9)
+    s0["v"][:, 0] = [1.6, 0.0, 0.0]         # drone 0: 1.6 m/s, 1.6 m/s relative to drone 1
+    th = np.radians(3.0)                    # drone 2: tilted 3 degrees about x
+    s0["q"][:, 2] = [np.cos(th / 2), np.sin(th / 2), 0.0, 0.0]
+    act = np.full((1, 4, 3), D.hover_rpm)
+    cases = [(dict(ood_speed=1.5), [1, 0, 0]), (dict(ood_speed=1.7), [0, 0, 0]),
+             (dict(ood_rel_speed=1.5), [1, 1, 0]), (dict(ood_rel_speed=1.7), [0, 0, 0]),
+             (dict(ood_tilt=np.radians(2.9)), [0, 0, 1]), (dict(ood_tilt=np.radians(3.1)), [0, 0, 0])]
+    for kw, expect in cases:
+        s = {k: v.copy() for k, v in s0.items()}
+        net, keep = orc.make_net(_flat_zero(), _norm_identity(), 1e-3, **kw)
+        _, aero, fb = orc.step_surrogate(P, 1 / 240, orc.ACT_RPM, 1, off, s, act, False, 1, net)
+        assert list(fb) == expect, (kw, list(fb))
+        Y = orc.aero_residual(P, 7, off, s0, rpm=np.full((4, 3), D.hover_rpm))
+        for i in range(3):
+            if expect[i]:
+                np.testing.assert_allclose(aero[i], Y[i], rtol=1e-12, atol=1e-18)
+            else:
+                np.testing.assert_array_equal(aero[i], 0.0)
