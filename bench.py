@@ -173,7 +173,8 @@ def timed_rollouts(args, w, p, with_obs, mask=None, integrator=None, surrogate_w
         md.md_bind_layout(ctx, w["env_offsets"])
         if surrogate_weights is not None:
             flat, norm = surrogate_weights
-            md.md_load_surrogate(ctx, flat, norm, 1e-3, 64)
+            md.md_load_surrogate(ctx, flat, norm, SUR_DZ_OOD, 64)
+            md.md_set_surrogate_ood(ctx, *SUR_OOD)
         state = md.DeviceState.from_numpy(w["state"])
         dr_t = None
         if dr is not None:
@@ -222,6 +223,14 @@ def timed_rollouts(args, w, p, with_obs, mask=None, integrator=None, surrogate_w
     return wall, kernel_ms, cfg, judge, check_state
 
 
+# Surrogate fallback: the downwash singularity (dz below 1 mm) and the edge of
+# the training data (lattice flights: speeds below 1 m/s, neighbour relative
+# speeds below 1.2 m/s, tilts below half a degree): world speed 1.5 m/s,
+# relative speed 2 m/s, tilt 2 degrees.
+SUR_DZ_OOD = 1e-3
+SUR_OOD = (1.5, 2.0, float(np.radians(2.0)))
+
+
 def surrogate_leg(args, w, p, with_obs):
     """The same rollouts with the learned residual in place of Eq. 4-6
     (fallback near the downwash singularity, 1/64 of drone-steps judged
@@ -245,6 +254,8 @@ def surrogate_leg(args, w, p, with_obs):
             "judge_nonfinite": j["n_nonfinite"], "final_state": chk,
             "fallback_fraction": j["n_fallback"] / max(j["n_drone_steps"], 1.0),
             "held_out_force_rel_err": meta.get("eps_held_out"),
+            "fallback_bounds": {"dz": SUR_DZ_OOD, "speed": SUR_OOD[0], "rel_speed": SUR_OOD[1],
+                                "tilt_rad": SUR_OOD[2]},
             "weights": os.path.relpath(path, ROOT)}
 
 

@@ -376,6 +376,17 @@ md_status md_load_surrogate(md_ctx *ctx, const float *h_params, const float *h_n
 /* Same, reading the parameters and normalisation of a trained md_mlp. */
 md_status md_load_surrogate_mlp(md_ctx *ctx, const md_mlp *m, float dz_ood, int judge_stride);
 
+/* Out-of-distribution fallback of the loaded surrogate (each bound 0 = that
+ * check off; loading a network turns all three off): a drone with a world
+ * velocity component beyond max_speed (m/s), a neighbour among its 8 whose
+ * velocity differs from its own by more than max_rel_speed along an axis,
+ * or a tilt beyond max_tilt (rad; qx^2 + qy^2 > sin^2(max_tilt / 2), formed
+ * with rounded operations) takes the plain Eq. 4-6 terms for that step, as
+ * at the downwash singularity.  The network is valid only where it was
+ * trained.  MD_E_INVALID_ARG without a loaded surrogate or for a negative
+ * bound. */
+md_status md_set_surrogate_ood(md_ctx *ctx, float max_speed, float max_rel_speed, float max_tilt);
+
 /* Training samples at the current state (bound layout, current device):
  * d_X [N][64] fp32 raw surrogate inputs (v_body[3], world up axis in the
  * body frame[3], rpm/HOVER_RPM[4], for the 8 nearest same-environment

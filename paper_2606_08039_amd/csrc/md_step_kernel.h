@@ -199,13 +199,18 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     bool has_lag = false;
     int delay = 0, issued = 0;  // action latency (steps) and ring fill
     float cmdh[4] = {0.f, 0.f, 0.f, 0.f};  // controller output held between updates
-    const bool ring = DR && a.dr.delay != nullptr;
+    // The disturbed instantiation also serves wind alone: randomisation (the
+    // factor table, lag, latency, the held-command block) is on only when the
+    // context has a factor table; otherwise the plain actuator chain runs and
+    // rpm_cmd / act_hist / act_count are never touched.
+    const bool rnd = DR && a.dr.scale != nullptr;
+    const bool ring = rnd && a.dr.delay != nullptr;
     float ws[5] = {0.f, 0.f, 0.f, -1.f, 0.f};  // wind state
     const bool windy = DR && a.wind.models != 0u;
     if (windy && valid && a.s.wind != nullptr)
         for (int k = 0; k < 5; ++k) ws[k] = a.s.wind[k * N + di];
-    if (DR && valid) {
-        if (a.dr.scale != nullptr) dr_constants(c, a.dr, N, di, cl, bias);
+    if (rnd && valid) {
+        dr_constants(c, a.dr, N, di, cl, bias);
         const float tau = a.dr.tau_mot ? a.dr.tau_mot[di] : 0.f;
         has_lag = tau > 0.f;
         lag = has_lag ? 1.f - expf(-c.dt / tau) : 1.f;
@@ -247,7 +252,7 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         }
         // ---- rotor speeds
         const float *act = a.action + a.act_step_stride * step;
-        if (!DR) {
+        if (!rnd) {
             if (ACT == 0) {
                 if (valid) {
                     for (int k = 0; k < 4; ++k) n[k] = clampf(act[(long long)k * N + di], 0.f, c.max_rpm);
@@ -354,7 +359,7 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         }
         if (ACT == 4)
             for (int k = 0; k < 4; ++k) a.s.ctl[k * N + di] = sp[k];
-        if (DR && ACT >= 1)
+        if (rnd && ACT >= 1)
             for (int k = 0; k < 4; ++k) a.s.rpm_cmd[k * N + di] = cmdh[k];
         if (ring) a.s.act_count[di] = issued;
         if (windy && a.s.wind != nullptr)

@@ -51,6 +51,7 @@ struct SurrogateState {
     float *norm = nullptr;  // x_mean[64], x_inv_std[64], y_mean[6], y_std[6]
     double *judge = nullptr;
     float dz_ood = 1e-3f;
+    float ood_speed = 0.f, ood_rel = 0.f, ood_tilt_s = 0.f;  // 0: check off
     int judge_stride = 64;
     bool loaded = false;
 };
@@ -62,6 +63,8 @@ struct SurArgs {
     const float *norm;
     double *judge;
     float dz_ood;
+    float ood_speed, ood_rel;  // world speed / relative speed component bounds (0: off)
+    float ood_tilt_s;          // sin^2(max tilt / 2) (0: off)
     int judge_mask;  // judge_stride - 1 (power of two), or -1 for no judging
 };
 
@@ -137,10 +140,11 @@ __device__ __forceinline__ void knn8(const float4 *pos, int lo, int m, int mmax,
 // Raw surrogate inputs (see md.h): v_body, world up in the body frame, n/HOVER,
 // 8 x (dp, dv) of the nearest neighbours (world frame, zero if missing), z,
 // ground proximity (h_clip / max(z, h_clip))^2, 0-pad.
-// Returns whether a neighbour sits above within (0, dz_ood).
+// Returns whether a neighbour sits above within (0, dz_ood) or (ood_rel > 0)
+// moves relative to the drone faster than ood_rel along an axis.
 __device__ __forceinline__ bool features(const KConst &c, const Drone &d, const Rot &R, const float n[4],
                                          const float4 *pos, const float4 *vel, const int bj[KNN],
-                                         float dz_ood, float f[MLP_IN]) {
+                                         float dz_ood, float ood_rel, float f[MLP_IN]) {
     f[0] = R.r00 * d.vx + R.r10 * d.vy + R.r20 * d.vz;
     f[1] = R.r01 * d.vx + R.r11 * d.vy + R.r21 * d.vz;
     f[2] = R.r02 * d.vx + R.r12 * d.vy + R.r22 * d.vz;
@@ -167,6 +171,9 @@ __device__ __forceinline__ bool features(const KConst &c, const Drone &d, const 
         f[10 + 6 * t + 4] = h ? vj.y - d.vy : 0.f;
         f[10 + 6 * t + 5] = h ? vj.z - d.vz : 0.f;
         ood |= h && dz > 0.f && dz < dz_ood;
+        ood |= h && ood_rel > 0.f &&
+               (fabsf(f[10 + 6 * t + 3]) > ood_rel || fabsf(f[10 + 6 * t + 4]) > ood_rel ||
+                fabsf(f[10 + 6 * t + 5]) > ood_rel);
     }
     f[58] = d.pz;
     const float gp = c.h_clip / fmaxf(d.pz, c.h_clip);
@@ -200,6 +207,14 @@ __device__ __forceinline__ void plain_aero(const KConst &c, uint32_t mask, const
         }
         Fz -= c.K1 * acc;
     }
+}
+
+// qx^2 + qy^2 = sin^2(tilt / 2) with every operation rounded (no fused
+// multiply-add), the value the tilt fallback compares.
+__device__ __forceinline__ float tilt_sq(const Drone &d) {
+#pragma clang fp contract(off)
+    const float a = d.qx * d.qx, b = d.qy * d.qy;
+    return a + b;
 }
 
 __device__ __forceinline__ float silu(float z) { return z * __builtin_amdgcn_rcpf(1.f + __expf(-z)); }
@@ -373,7 +388,12 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
         int bj[KNN];
         knn8(pos, lo, menv, mmax, slot, d.px, d.py, bj);
         float f[MLP_IN];
-        const bool ood = features(c, d, R, n, pos, vel, bj, sa.dz_ood, f) && valid;
+        bool ood = features(c, d, R, n, pos, vel, bj, sa.dz_ood, sa.ood_rel, f);
+        // outside the trained region: fast or tilted drones take the plain terms
+        ood |= sa.ood_speed > 0.f &&
+               (fabsf(d.vx) > sa.ood_speed || fabsf(d.vy) > sa.ood_speed || fabsf(d.vz) > sa.ood_speed);
+        ood |= sa.ood_tilt_s > 0.f && tilt_sq(d) > sa.ood_tilt_s;
+        ood = ood && valid;
         bf16 *row = feat + slot * FEAT_STRIDE;
 #pragma unroll
         for (int k = 0; k < MLP_IN; k += 8) {
@@ -504,7 +524,7 @@ __global__ void __launch_bounds__(256) datagen_kernel(GenArgs g) {
     int bj[KNN];
     knn8(pos, lo, menv, mmax, slot, d.px, d.py, bj);
     float f[MLP_IN];
-    (void)features(c, d, R, n, pos, vel, bj, 0.f, f);
+    (void)features(c, d, R, n, pos, vel, bj, 0.f, 0.f, f);
     float *x = g.X + (long long)di * MLP_IN;
 #pragma unroll
     for (int k = 0; k < MLP_IN; k += 4) *(float4 *)(x + k) = make_float4(f[k], f[k + 1], f[k + 2], f[k + 3]);
@@ -617,6 +637,7 @@ md_status load_surrogate(md_ctx *ctx, const float *params, const float *norm, fl
         return MD_E_HIP;
     }
     S->dz_ood = dz_ood;
+    S->ood_speed = S->ood_rel = S->ood_tilt_s = 0.f;
     S->judge_stride = judge_stride;
     S->loaded = true;
     return MD_OK;
@@ -653,6 +674,9 @@ md_status surrogate_step(md_ctx *ctx, const md_state *s, const float *d_action, 
     sa.norm = ctx->sur->norm;
     sa.judge = ctx->sur->judge;
     sa.dz_ood = ctx->sur->dz_ood;
+    sa.ood_speed = ctx->sur->ood_speed;
+    sa.ood_rel = ctx->sur->ood_rel;
+    sa.ood_tilt_s = ctx->sur->ood_tilt_s;
     sa.judge_mask = ctx->sur->judge_stride > 0 ? ctx->sur->judge_stride - 1 : -1;
     hipError_t e = launch_sur_step(sa, ctx->act, bs->n_bins, bs->slots, st);
     if (e != hipSuccess) {
@@ -740,6 +764,23 @@ md_status md_load_surrogate(md_ctx *ctx, const float *h_params, const float *h_n
     }
     (void)hipSetDevice(ctx->device);
     return md::load_surrogate(ctx, h_params, h_norm, dz_ood, judge_stride);
+}
+
+md_status md_set_surrogate_ood(md_ctx *ctx, float max_speed, float max_rel_speed, float max_tilt) {
+    if (!ctx) return MD_E_INVALID_ARG;
+    if (!ctx->sur || !ctx->sur->loaded) {
+        ctx->err = "md_set_surrogate_ood: no surrogate loaded";
+        return MD_E_INVALID_ARG;
+    }
+    if (!(max_speed >= 0.f) || !(max_rel_speed >= 0.f) || !(max_tilt >= 0.f)) {
+        ctx->err = "md_set_surrogate_ood: bounds must be >= 0 (0 turns a check off)";
+        return MD_E_INVALID_ARG;
+    }
+    const double sh = std::sin(0.5 * (double)max_tilt);
+    ctx->sur->ood_speed = max_speed;
+    ctx->sur->ood_rel = max_rel_speed;
+    ctx->sur->ood_tilt_s = max_tilt > 0.f ? (float)(sh * sh) : 0.f;
+    return MD_OK;
 }
 
 md_status md_load_surrogate_mlp(md_ctx *ctx, const md_mlp *m, float dz_ood, int judge_stride) {

@@ -380,6 +380,10 @@ def md_judge_stats(ctx):
     return {k: getattr(j, k) for k, _ in md_judge._fields_}
 
 
+def md_set_surrogate_ood(ctx, max_speed=0.0, max_rel_speed=0.0, max_tilt=0.0):
+    check(lib().md_set_surrogate_ood(ctx, float(max_speed), float(max_rel_speed), float(max_tilt)), ctx)
+
+
 def md_judge_reset(ctx):
     check(lib().md_judge_reset(ctx), ctx)
 

@@ -105,9 +105,9 @@ class SurRun(pu.GpuRun):
         self.step_index = 0
 
 
-def _oracle_sur_step(w, s32, k, flat, norm, dz_ood=1e-3, env_subset=None):
+def _oracle_sur_step(w, s32, k, flat, norm, dz_ood=1e-3, env_subset=None, ood=None):
     P = pu.oracle_params()
-    net, keep = orc.make_net(flat, norm, dz_ood)
+    net, keep = orc.make_net(flat, norm, dz_ood, **(ood or {}))
     off = np.asarray(w["env_offsets"], dtype=np.int64)
     s = pu.to_oracle_state(s32)
     act = w["action"]
@@ -200,3 +200,32 @@ def test_judge_matches_oracle_force_error():
     ref2 = np.sum(Yp[ok, :3] ** 2)
     assert j["n_judged"] == ok.sum()
     assert j["force_rel_err"] == pytest.approx(np.sqrt(err2 / ref2), rel=1e-3)
+
+
+def test_out_of_distribution_fallback_matches_oracle():
+    """Fast, relatively fast and tilted drones take the plain terms on both
+    sides (decisions in binary32), and the step matches the oracle."""
+    rng = np.random.default_rng(53)
+    flat, norm = _random_net(rng)
+    w = wl.subset_envs(wl.lattice(n_envs=16384, shape=(2, 2, 2), seed=3), 128)
+    n = int(w["env_offsets"][-1])
+    st = {k: v.copy() for k, v in w["state"].items()}
+    pick = rng.choice(n, 60, replace=False)
+    st["v"][:, pick[:20]] += rng.uniform(-3, 3, size=(3, 20))            # fast
+    th = rng.uniform(0.01, 0.2, size=20)                                 # tilted up to 11 degrees
+    st["q"][:, pick[20:40]] = np.stack([np.cos(th / 2), np.sin(th / 2), np.zeros(20), np.zeros(20)])
+    st["v"][2, pick[40:]] += rng.uniform(-2.5, 2.5, size=20)            # vertical speed only
+    w = dict(w, state=st)
+    ood = dict(ood_speed=1.5, ood_rel_speed=2.0, ood_tilt=np.radians(2.0))
+    g = SurRun(w, flat, norm, judge_stride=1)
+    md.md_set_surrogate_ood(g.ctx, 1.5, 2.0, np.radians(2.0))
+    s0 = g.snapshot()
+    md.md_judge_reset(g.ctx)
+    g.run(1)
+    s1 = g.snapshot()
+    j = md.md_judge_stats(g.ctx)
+    g.close()
+    ref, aero, fb, _ = _oracle_sur_step(w, s0, 0, flat, norm, ood=ood)
+    assert fb.sum() > 40
+    assert j["n_fallback"] == fb.sum()
+    pu.assert_blocks(s1, ref, what="ood step")
