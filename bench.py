@@ -155,7 +155,7 @@ def cpu_baseline(w, with_obs, seconds_target=12.0):
 
 
 def timed_rollouts(args, w, p, with_obs, mask=None, integrator=None, surrogate_weights=None,
-                   tune=True, config=None, dr=None):
+                   tune=True, config=None, dr=None, wind=None):
     """Warm up, then time args.steps rollouts (one md_step call of w["n_steps"]
     physics steps each) on torch's current stream, which is also the stream
     the step kernels are launched on.  Returns wall seconds, the per-launch
@@ -181,6 +181,9 @@ def timed_rollouts(args, w, p, with_obs, mask=None, integrator=None, surrogate_w
             dr_t = {k: (torch.from_numpy(v).cuda() if v is not None else None) for k, v in dr.items()}
             state.add_dr_blocks(act)
             md.md_set_domain_randomization(ctx, dr_t["scale"], dr_t["tau_mot"], dr_t["delay"])
+        if wind is not None:
+            state.add_wind_block()
+            md.md_set_wind(ctx, **wind)
         action = torch.from_numpy(np.ascontiguousarray(w["action"], dtype=np.float32)).cuda()
         obs = torch.empty((K, 20, n), dtype=torch.float32, device="cuda") if with_obs else None
         n_slots = K if with_obs else 0
@@ -271,6 +274,22 @@ def dr_leg(args, w, p, with_obs):
             "launch_config": cfg, "final_state": chk}
 
 
+# Sec. "Wind and turbulence", COMBINED: a 0.9 m/s mean wind along +y (the
+# paper's hover example), gusts, Dryden turbulence and a sinusoid.
+WIND_COMBINED = dict(models=15, v_mean=(0.0, 0.9, 0.0), rho=1.225, cd_area=0.01, gust_prob=0.002,
+                     gust_duration=0.5, gust_amp=0.02, dryden_sigma=0.5, dryden_airspeed=0.9, sin_amp=0.005,
+                     sin_omega=1.0, seed=7)
+
+
+def wind_leg(args, w, p, with_obs):
+    """The same rollouts under COMBINED wind (per-drone Philox draws)."""
+    n = int(w["env_offsets"][-1])
+    wall, kernel_ms, cfg, _, chk = timed_rollouts(args, w, p, with_obs, wind=WIND_COMBINED)
+    return {"value": float(n) * w["n_steps"] * args.steps / wall, "unit": "drone-steps/s",
+            "ms_per_step": wall / args.steps * 1e3, "kernel_ms_avg": float(np.mean(kernel_ms)),
+            "launch_config": cfg, "final_state": chk, "wind": WIND_COMBINED}
+
+
 def rk4_leg(args, w, p, with_obs):
     """The same rollouts with the classic Runge-Kutta integrator (four force
     evaluations, four neighbour sweeps per physics step)."""
@@ -293,6 +312,7 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-aero leg")
     ap.add_argument("--no-rk4", action="store_true", help="skip the Runge-Kutta leg")
     ap.add_argument("--no-dr", action="store_true", help="skip the domain-randomisation leg")
+    ap.add_argument("--no-wind", action="store_true", help="skip the wind leg")
     ap.add_argument("--no-tune", action="store_true", help="default launch configuration, no autotuning")
     ap.add_argument("--config", default=None,
                     help="launch configuration lanes_per_drone,unroll,waves_per_group,pair_symmetric "
@@ -375,6 +395,9 @@ def main():
     if not args.no_dr:
         out["domain_randomization"] = dr_leg(args, w, p, with_obs)
         out["domain_randomization"]["speed_vs_plain"] = out["domain_randomization"]["value"] / value
+    if not args.no_wind:
+        out["wind"] = wind_leg(args, w, p, with_obs)
+        out["wind"]["speed_vs_plain"] = out["wind"]["value"] / value
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
