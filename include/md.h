@@ -260,15 +260,20 @@ md_status md_get_integrator(const md_ctx *ctx, int *out);
  * ---------------------------------------------------------------------- */
 
 /* How md_step maps drones to the GPU.  Every valid configuration computes
- * the same physics: lanes_per_drone 1 with or without pair_symmetric and any
+ * the same physics: lanes_per_drone 1 with pair_symmetric 0 or 1 and any
  * waves_per_group give bitwise identical results; lanes_per_drone 2 or 4
- * split each neighbour sum into interleaved partial sums (a different but
- * fixed summation order). */
+ * split each neighbour sum into interleaved partial sums, and
+ * pair_symmetric 2 sums each drone's terms shift by shift (different but
+ * fixed summation orders, independent of how environments are packed). */
 typedef struct md_launch_config {
     int lanes_per_drone; /* 1, 2 or 4 lanes share one drone's neighbour sweep */
     int unroll;          /* neighbour-loop unroll: 1, 2 or 4 */
     int waves_per_group; /* 1, 2, 4, 8 or 16 wave64s per workgroup (bin of 64*w/lpd slots) */
-    int pair_symmetric;  /* 1: each unordered pair evaluated once (needs lanes_per_drone 1) */
+    int pair_symmetric;  /* 0: all ordered pairs; 1: each unordered pair once, terms routed
+                            through an LDS matrix; 2: each unordered pair once, terms routed
+                            between lanes by wave permutes (environments of at most 64
+                            drones, packed so that none crosses a wavefront).  1 and 2
+                            need lanes_per_drone 1. */
 } md_launch_config;
 
 md_status md_get_launch_config(const md_ctx *ctx, md_launch_config *out);

@@ -161,8 +161,44 @@ static void pack_bins(const std::vector<int32_t> &off, int slots, std::vector<in
     }
 }
 
-md_status build_bins(md_ctx *ctx, int slots, BinSet **out) {
-    auto it = ctx->binsets.find(slots);
+// Bins for the wave-shuffle sweep: environments packed into 64-slot wave
+// bins (best fit decreasing, as above), then consecutive wave bins grouped
+// into workgroups of slots / 64 waves, so that no environment crosses a
+// wavefront.
+static void pack_bins_wave_aligned(const std::vector<int32_t> &off, int slots, std::vector<int2> &tab,
+                                   std::vector<int> &mmax, int &n_bins) {
+    std::vector<int2> t64;
+    std::vector<int> m64;
+    int n64 = 0;
+    pack_bins(off, 64, t64, m64, n64);
+    const int W = slots / 64;
+    n_bins = (n64 + W - 1) / W;
+    tab.assign((size_t)n_bins * slots, make_int2(-1, 0));
+    mmax.assign(n_bins, 0);
+    for (int b = 0; b < n_bins; ++b) {
+        int mm = 0;
+        bool uniform = true;
+        int first = -1;
+        for (int w = 0; w < W && b * W + w < n64; ++w) {
+            const int src = b * W + w;
+            for (int s = 0; s < 64; ++s) {
+                int2 e = t64[(size_t)src * 64 + s];
+                if (e.x >= 0) e.y = (((e.y >> 16) + 64 * w) << 16) | (e.y & 0xffff);
+                tab[(size_t)b * slots + 64 * w + s] = e;
+            }
+            const int mw = m64[src] & 0xffff;
+            uniform = uniform && (m64[src] >> 16) != 0 && (first < 0 || mw == first);
+            if (first < 0) first = mw;
+            mm = std::max(mm, mw);
+        }
+        // a trailing group may hold fewer waves; their idle slots hold no drone
+        mmax[b] = mm | ((uniform && b * W + W <= n64) ? 0x10000 : 0);
+    }
+}
+
+md_status build_bins(md_ctx *ctx, int slots, bool wave_aligned, BinSet **out) {
+    const int key = slots * 2 + (wave_aligned ? 1 : 0);
+    auto it = ctx->binsets.find(key);
     if (it != ctx->binsets.end()) {
         *out = &it->second;
         return MD_OK;
@@ -175,7 +211,10 @@ md_status build_bins(md_ctx *ctx, int slots, BinSet **out) {
     std::vector<int2> tab;
     std::vector<int> mm;
     BinSet bs;
-    pack_bins(ctx->off, slots, tab, mm, bs.n_bins);
+    if (wave_aligned)
+        pack_bins_wave_aligned(ctx->off, slots, tab, mm, bs.n_bins);
+    else
+        pack_bins(ctx->off, slots, tab, mm, bs.n_bins);
     bs.slots = slots;
     if (bs.n_bins > 0) {
         hipError_t e = hipMalloc(&bs.d_slot, sizeof(int2) * tab.size());
@@ -195,7 +234,7 @@ md_status build_bins(md_ctx *ctx, int slots, BinSet **out) {
         }
         bs.h_mmax = mm;
     }
-    auto ins = ctx->binsets.emplace(slots, std::move(bs));
+    auto ins = ctx->binsets.emplace(key, std::move(bs));
     *out = &ins.first->second;
     return MD_OK;
 }
@@ -213,6 +252,10 @@ int slots_for(const md_ctx *ctx, const LaunchCfg &cfg) {
     return 64 * cfg.waves / lpd;
 }
 
+bool wave_aligned_for(const md_ctx *ctx, const LaunchCfg &cfg) {
+    return (ctx->mask & MD_AERO_DW) && cfg.sym == 2;
+}
+
 LaunchCfg default_cfg(const md_ctx *ctx) {
     LaunchCfg c{1, 4, 1, 0};
     while (64 * c.waves < ctx->max_m && c.waves < 16) c.waves *= 2;
@@ -228,16 +271,16 @@ md_status prepare_launch(md_ctx *ctx) {
     if (ctx->mask & MD_AERO_SURROGATE) {
         int waves = 1;
         while (64 * waves < ctx->max_m) waves *= 2;
-        return build_bins(ctx, 64 * waves, &bs);
+        return build_bins(ctx, 64 * waves, false, &bs);
     }
-    return build_bins(ctx, slots_for(ctx, ctx->cfg), &bs);
+    return build_bins(ctx, slots_for(ctx, ctx->cfg), wave_aligned_for(ctx, ctx->cfg), &bs);
 }
 
 md_status launch(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
                  float *d_obs, int n_obs_slots, int n_steps, int64_t step0, hipStream_t st,
                  const LaunchCfg &cfg) {
     BinSet *bs = nullptr;
-    md_status rc = build_bins(ctx, slots_for(ctx, cfg), &bs);
+    md_status rc = build_bins(ctx, slots_for(ctx, cfg), wave_aligned_for(ctx, cfg), &bs);
     if (rc != MD_OK) return rc;
     StepArgs a;
     a.c = ctx->kc;
@@ -430,7 +473,7 @@ md_status md_bind_layout(md_ctx *ctx, const int32_t *h_env_offsets, int n_envs, 
     ctx->has_layout = true;
     ctx->cfg = md::default_cfg(ctx);
     md::BinSet *bs = nullptr;
-    return md::build_bins(ctx, md::slots_for(ctx, ctx->cfg), &bs);
+    return md::build_bins(ctx, md::slots_for(ctx, ctx->cfg), md::wave_aligned_for(ctx, ctx->cfg), &bs);
 }
 
 md_status md_set_integrator(md_ctx *ctx, int integrator) {

@@ -44,7 +44,7 @@ struct md_ctx {
     bool has_layout = false;
     int n_envs = 0, n_drones = 0, max_m = 0;
     std::vector<int32_t> off;
-    std::map<int, md::BinSet> binsets;  // keyed by slots per bin
+    std::map<int, md::BinSet> binsets;  // keyed by 2 x slots per bin + wave-aligned packing
     md::LaunchCfg cfg{1, 4, 1, 0};
     bool tuned = false;
     // optional subsystems
@@ -54,9 +54,10 @@ struct md_ctx {
 
 namespace md {
 
-md_status build_bins(md_ctx *ctx, int slots, BinSet **out);
+md_status build_bins(md_ctx *ctx, int slots, bool wave_aligned, BinSet **out);
 void free_bins(md_ctx *ctx);
 int slots_for(const md_ctx *ctx, const LaunchCfg &cfg);
+bool wave_aligned_for(const md_ctx *ctx, const LaunchCfg &cfg);
 LaunchCfg default_cfg(const md_ctx *ctx);
 md_status launch(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
                  float *d_obs, int n_obs_slots, int n_steps, int64_t step0, hipStream_t st,

@@ -20,7 +20,7 @@ namespace {
 
 using namespace phys;
 
-template <uint32_t MASK, int ACT, int UNROLL, bool SYM>
+template <uint32_t MASK, int ACT, int UNROLL, int SYM>
 __global__ void __launch_bounds__(1024) rk4_kernel(StepArgs a) {
     extern __shared__ float4 lds_pos[];  // [2][2 * slots] positions; then T [slots][tstride] (SYM)
     const KConst &c = a.c;
@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(1024) rk4_kernel(StepArgs a) {
     }
 
     float *tmat = (float *)(lds_pos + 4 * slots);
-    if (SYM && (MASK & 4u) && valid) {
+    if (SYM == 1 && (MASK & 4u) && valid) {
         // the diagonal and the padding up to the next multiple of 4 stay 0
         tmat[slot * a.tstride + (slot - lo)] = 0.f;
         for (int j = menv; j < ((menv + 3) & ~3); ++j) tmat[slot * a.tstride + j] = 0.f;
@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(1024) rk4_kernel(StepArgs a) {
     }
 }
 
-template <uint32_t MASK, int ACT, bool SYM>
+template <uint32_t MASK, int ACT, int SYM>
 hipError_t launch_u(const StepArgs &a, int unroll, int n_bins, int threads, size_t lds, hipStream_t st) {
     switch (unroll) {
         case 1: hipLaunchKernelGGL((rk4_kernel<MASK, ACT, 1, SYM>), dim3(n_bins), dim3(threads), lds, st, a); break;
@@ -211,12 +211,16 @@ template <uint32_t MASK, int ACT>
 hipError_t launch_l(const StepArgs &a, const LaunchCfg &cfg, int n_bins, int threads, size_t lds,
                     hipStream_t st) {
     if (!(MASK & 4u)) {
-        hipLaunchKernelGGL((rk4_kernel<MASK, ACT, 1, false>), dim3(n_bins), dim3(threads), lds, st, a);
+        hipLaunchKernelGGL((rk4_kernel<MASK, ACT, 1, 0>), dim3(n_bins), dim3(threads), lds, st, a);
         return hipGetLastError();
     }
     if (cfg.lpd != 1) return hipErrorInvalidValue;
-    return cfg.sym ? launch_u<MASK, ACT, true>(a, cfg.unroll, n_bins, threads, lds, st)
-                   : launch_u<MASK, ACT, false>(a, cfg.unroll, n_bins, threads, lds, st);
+    switch (cfg.sym) {
+        case 0: return launch_u<MASK, ACT, 0>(a, cfg.unroll, n_bins, threads, lds, st);
+        case 1: return launch_u<MASK, ACT, 1>(a, cfg.unroll, n_bins, threads, lds, st);
+        case 2: return launch_u<MASK, ACT, 2>(a, cfg.unroll, n_bins, threads, lds, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int ACT>
@@ -242,7 +246,7 @@ hipError_t launch_step_rk4(const StepArgs &a, uint32_t mask, int act, const Laun
     if ((mask & 4u) && cfg.lpd != 1) return hipErrorInvalidValue;
     const int threads = slots;
     size_t lds = (mask & 4u) ? sizeof(float4) * 2 * 2 * (size_t)slots : 0;
-    if ((mask & 4u) && cfg.sym) lds += sizeof(float) * (size_t)slots * (size_t)a.tstride;
+    if ((mask & 4u) && cfg.sym == 1) lds += sizeof(float) * (size_t)slots * (size_t)a.tstride;
     switch (act) {
         case 0: return launch_m<0>(a, mask, cfg, n_bins, threads, lds, stream);
         case 1: return launch_m<1>(a, mask, cfg, n_bins, threads, lds, stream);

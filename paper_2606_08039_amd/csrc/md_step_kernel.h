@@ -150,7 +150,7 @@ __device__ __forceinline__ void wind_force(const WindArgs &W, float dt, long lon
     }
 }
 
-template <uint32_t MASK, int ACT, int LPD, int UNROLL, bool SYM, bool DR>
+template <uint32_t MASK, int ACT, int LPD, int UNROLL, int SYM, bool DR>
 __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     extern __shared__ float4 lds_pos[];  // [2][2 * slots] positions; then T [slots][tstride] (SYM)
     const KConst &c = a.c;
@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     }
 
     float *tmat = (float *)(lds_pos + 4 * slots);
-    if (SYM && (MASK & 4u) && valid) {
+    if (SYM == 1 && (MASK & 4u) && valid) {
         // the diagonal and the padding up to the next multiple of 4 stay 0
         tmat[slot * a.tstride + (slot - lo)] = 0.f;
         for (int j = menv; j < ((menv + 3) & ~3); ++j) tmat[slot * a.tstride + j] = 0.f;
@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     }
 }
 
-template <uint32_t MASK, int ACT, int LPD, bool SYM, bool DR>
+template <uint32_t MASK, int ACT, int LPD, int SYM, bool DR>
 hipError_t launch_u(const StepArgs &a, int unroll, int n_bins, int threads, size_t lds, hipStream_t st) {
     switch (unroll) {
         case 1: hipLaunchKernelGGL((step_kernel<MASK, ACT, LPD, 1, SYM, DR>), dim3(n_bins), dim3(threads), lds, st, a); break;
@@ -383,17 +383,18 @@ hipError_t launch_l(const StepArgs &a, const LaunchCfg &cfg, int n_bins, int thr
                     hipStream_t st) {
     if (!(MASK & 4u)) {
         // no neighbour sweep: one lane per drone, no loop to tune
-        hipLaunchKernelGGL((step_kernel<MASK, ACT, 1, 1, false, DR>), dim3(n_bins), dim3(threads), lds, st, a);
+        hipLaunchKernelGGL((step_kernel<MASK, ACT, 1, 1, 0, DR>), dim3(n_bins), dim3(threads), lds, st, a);
         return hipGetLastError();
     }
     if (cfg.sym) {
         if (cfg.lpd != 1) return hipErrorInvalidValue;
-        return launch_u<MASK, ACT, 1, true, DR>(a, cfg.unroll, n_bins, threads, lds, st);
+        return cfg.sym == 2 ? launch_u<MASK, ACT, 1, 2, DR>(a, cfg.unroll, n_bins, threads, lds, st)
+                            : launch_u<MASK, ACT, 1, 1, DR>(a, cfg.unroll, n_bins, threads, lds, st);
     }
     switch (cfg.lpd) {
-        case 1: return launch_u<MASK, ACT, 1, false, DR>(a, cfg.unroll, n_bins, threads, lds, st);
-        case 2: return launch_u<MASK, ACT, 2, false, DR>(a, cfg.unroll, n_bins, threads, lds, st);
-        case 4: return launch_u<MASK, ACT, 4, false, DR>(a, cfg.unroll, n_bins, threads, lds, st);
+        case 1: return launch_u<MASK, ACT, 1, 0, DR>(a, cfg.unroll, n_bins, threads, lds, st);
+        case 2: return launch_u<MASK, ACT, 2, 0, DR>(a, cfg.unroll, n_bins, threads, lds, st);
+        case 4: return launch_u<MASK, ACT, 4, 0, DR>(a, cfg.unroll, n_bins, threads, lds, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -420,7 +421,7 @@ hipError_t launch_step_t(const StepArgs &a, uint32_t mask, int act, const Launch
     const int lpd = (mask & 4u) ? cfg.lpd : 1;
     const int threads = slots * lpd;
     size_t lds = (mask & 4u) ? sizeof(float4) * 2 * 2 * (size_t)slots : 0;
-    if ((mask & 4u) && cfg.sym) lds += sizeof(float) * (size_t)slots * (size_t)a.tstride;
+    if ((mask & 4u) && cfg.sym == 1) lds += sizeof(float) * (size_t)slots * (size_t)a.tstride;
     switch (act) {
         case 0: return launch_m<0, DR>(a, mask, cfg, n_bins, threads, lds, stream);
         case 1: return launch_m<1, DR>(a, mask, cfg, n_bins, threads, lds, stream);

@@ -67,15 +67,79 @@ __device__ __forceinline__ void dw_pairs(const KConst &c, const float4 *buf, flo
     }
 }
 
+// Pair-symmetric sweep through wave shuffles, for bins whose environments
+// each lie inside one wavefront (one lane per drone).  As in dw_pairs, lane i
+// evaluates the pairs (i, (i + k) mod M) for k = 1..(M-1)/2; the term stays
+// with lane i when its partner is above, and otherwise travels to the
+// partner's lane through a cross-lane permute (ds_bpermute): at shift k lane
+// j receives from lane (j - k) mod M.  The loop runs to the bin's largest
+// environment so that every permute executes with the whole wave.  For even
+// M the pair at distance M/2 is evaluated by both members, each keeping it
+// when its partner is above.  The summation order (per shift: own term, then
+// the received one) is fixed by the drone's place in its environment.
+template <bool DZMIN, bool UNIFORM, int UNROLL>
+__device__ __forceinline__ float dw_pairs_shfl(const KConst &c, const float4 *buf, int slot, int lo, int m,
+                                               int mmax, const Drone &d) {
+    // an idle slot (m = 0) runs the loop as a one-drone environment of itself
+    const int mm = m > 0 ? m : 1;
+    const int li = m > 0 ? slot - lo : 0;
+    const int base = (slot & 63) - li;  // the environment's first lane in this wave
+    // every lane runs to the bin's largest environment, so that each permute
+    // executes with the whole wave; in a uniform bin every environment has
+    // that size and no shift needs masking
+    const int h = (m - 1) >> 1, hmax = (mmax - 1) >> 1;
+    // byte offsets, advanced cyclically: the partner's position (li + k) mod M
+    // in `buf`, and the lane (li - k) mod M whose term this lane receives
+    const char *bb = (const char *)buf;
+    const int a_beg = lo * 16, a_end = (lo + mm) * 16;
+    const int p_beg = base * 4, p_last = (base + mm - 1) * 4;
+    int aj = (lo + li) * 16, ps = (base + li) * 4;
+    float acc = 0.f;
+#pragma unroll UNROLL
+    for (int k = 1; k <= hmax; ++k) {
+        aj = (aj + 16 == a_end) ? a_beg : aj + 16;
+        ps = (ps == p_beg) ? p_last : ps - 4;
+        const float4 q = *(const float4 *)(bb + aj);
+        const float dz = q.z - d.pz;
+        float t = dw_term<DZMIN>(c, q.x - d.px, q.y - d.py, fabsf(dz));
+        if (!UNIFORM) t = (k <= h) ? t : 0.f;
+        const float mine = dz > 0.f ? t : 0.f;
+        const float theirs = t - mine;  // exactly t when the partner is below, else 0
+        const float recv = __int_as_float(__builtin_amdgcn_ds_bpermute(ps, __float_as_int(theirs)));
+        acc += mine;
+        acc += recv;
+    }
+    if ((m & 1) == 0 && m > 0) {
+        const int half = m >> 1;
+        const int lj = li < half ? li + half : li - half;
+        const float4 q = buf[lo + lj];
+        const float dz = q.z - d.pz;
+        const float t = dw_term<DZMIN>(c, q.x - d.px, q.y - d.py, fabsf(dz));
+        acc += dz > 0.f ? t : 0.f;
+    }
+    return acc;
+}
+
 // Downwash sum (without K1) of this slot's drone against the positions in
-// `buf`: the all-pairs sweep over LPD lanes (their partial sums combined in a
-// fixed order) or the pair-symmetric sweep through the LDS term matrix (it
-// contains the barrier between the term writes and the row sums).
-template <int LPD, int UNROLL, bool SYM>
+// `buf`.  SYM 0: the all-pairs sweep over LPD lanes (their partial sums
+// combined in a fixed order); SYM 1: the pair-symmetric sweep through the LDS
+// term matrix (it contains the barrier between the term writes and the row
+// sums; bitwise equal to SYM 0 with one lane); SYM 2: the pair-symmetric
+// sweep through wave shuffles (environments inside one wave).
+template <int LPD, int UNROLL, int SYM>
 __device__ __forceinline__ float dw_sum(const KConst &c, const float4 *buf, float *tmat, int ts, int slot,
                                         int sub, int lo, int mmax, int menv, bool uniform, const Drone &d) {
     float acc = 0.f;
-    if (SYM) {
+    if (SYM == 2) {
+        // `uniform` and dz_min are the same for the whole workgroup: the
+        // permutes inside run with every lane of the wave
+        if (uniform)
+            acc = c.dz_min > 0.f ? dw_pairs_shfl<true, true, UNROLL>(c, buf, slot, lo, menv, mmax, d)
+                                 : dw_pairs_shfl<false, true, UNROLL>(c, buf, slot, lo, menv, mmax, d);
+        else
+            acc = c.dz_min > 0.f ? dw_pairs_shfl<true, false, UNROLL>(c, buf, slot, lo, menv, mmax, d)
+                                 : dw_pairs_shfl<false, false, UNROLL>(c, buf, slot, lo, menv, mmax, d);
+    } else if (SYM == 1) {
         if (c.dz_min > 0.f)
             dw_pairs<true, UNROLL>(c, buf, tmat, ts, slot, lo, menv, d);
         else

@@ -42,9 +42,11 @@ static std::string signature(const md_ctx *ctx) {
 bool cfg_valid(const md_ctx *ctx, const LaunchCfg &c) {
     const int slots = 64 * c.waves / c.lpd;
     if (slots < ctx->max_m || slots < 1) return false;
+    if (c.sym < 0 || c.sym > 2) return false;
     if (c.sym && c.lpd != 1) return false;
+    if (c.sym == 2 && ctx->max_m > 64) return false;  // environments inside one wave
     if (ctx->integ == MD_INTEG_RK4 && (ctx->mask & MD_AERO_DW) && c.lpd != 1) return false;
-    if (c.sym) {
+    if (c.sym == 1) {
         const size_t lds = 16 * 4 * (size_t)slots + 4 * (size_t)slots * (size_t)pair_stride(ctx->max_m);
         if (lds > 64 * 1024) return false;
     }
@@ -60,7 +62,7 @@ static std::vector<LaunchCfg> candidates(const md_ctx *ctx) {
         if (out.empty()) out.push_back(default_cfg(ctx));
         return out;
     }
-    for (int sym : {0, 1})
+    for (int sym : {0, 1, 2})
         for (int lpd : {1, 2, 4})
             for (int w : {1, 2, 4, 8, 16})
                 for (int u : {1, 2, 4}) {
@@ -276,7 +278,7 @@ md_status md_set_launch_config(md_ctx *ctx, md_launch_config *cfg) {
         ctx->err = "md_set_launch_config: bind a layout first";
         return MD_E_LAYOUT;
     }
-    md::LaunchCfg c{cfg->lanes_per_drone, cfg->unroll, cfg->waves_per_group, cfg->pair_symmetric ? 1 : 0};
+    md::LaunchCfg c{cfg->lanes_per_drone, cfg->unroll, cfg->waves_per_group, cfg->pair_symmetric};
     const bool lpd_ok = c.lpd == 1 || c.lpd == 2 || c.lpd == 4;
     const bool u_ok = c.unroll == 1 || c.unroll == 2 || c.unroll == 4;
     const bool w_ok = c.waves == 1 || c.waves == 2 || c.waves == 4 || c.waves == 8 || c.waves == 16;
