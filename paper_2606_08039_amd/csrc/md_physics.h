@@ -279,15 +279,16 @@ __device__ __forceinline__ void integrate(const KConst &c, Drone &d, float Fx, f
 // dz == 0 are exact), returns exp(-dxy^2 / (2 beta^2)) / dz^2 if dz > 0 and
 // dxy < 10 m, else 0.  The Gaussian is evaluated as 2^(-dxy^2 / beta'^2)
 // with beta' = sqrt(2 ln 2) beta (C2, C3 pre-scaled on the host); 1/dz and
-// 1/beta'^2 both come from the one reciprocal 1/(dz beta'^2).  beta'^2 is
-// floored at 1e-30, which reproduces the beta -> 0 limit (1 at dxy = 0, 0
-// at any float-representable dxy > 0) and keeps dz beta'^2 a normal number.
+// 1/beta'^2 both come from the one reciprocal 1/(dz beta'^2).  beta'^2 + 1e-30
+// (one fused multiply-add; the addend is below half an ulp of any
+// beta'^2 > 2e-23) reproduces the beta -> 0 limit (1 at dxy = 0, 0 at any
+// float-representable dxy > 0) and keeps dz beta'^2 a normal number.
 template <bool DZMIN>
 __device__ __forceinline__ float dw_term(const KConst &c, float dx, float dy, float dz) {
     const float d2 = dx * dx + dy * dy;
     const float dze = DZMIN ? fmaxf(dz, c.dz_min) : dz;
     const float bs = c.C2s * dze + c.C3s;
-    const float b2 = fmaxf(bs * bs, 1e-30f);
+    const float b2 = fmaf(bs, bs, 1e-30f);
     const float inv = rcp(dze * b2);  // one reciprocal for 1/dz and 1/beta'^2
     const float r = b2 * inv;
     const float gauss = __builtin_amdgcn_exp2f(-d2 * (dze * inv));

@@ -9,13 +9,26 @@
 namespace md {
 namespace phys {
 
+// The constants of the pair term with C3s pinned in a vector register: the
+// term's fused multiply-add C2s dz + C3s may read only one scalar operand, and
+// without this the compiler re-copies C3s into a vector register on every
+// iteration of the neighbour loops.
+__device__ __forceinline__ KConst pair_consts(const KConst &c) {
+    KConst cc = c;
+    float c3 = c.C3s;
+    asm volatile("" : "+v"(c3));
+    cc.C3s = c3;
+    return cc;
+}
+
 // This lane's share of the downwash sum over its environment's slots
 // [lo, lo + mmax), in ascending order (every LPD-th slot from `sub`).  In a
 // uniform bin every environment has mmax drones and the bound check is
 // dropped.
 template <bool DZMIN, int LPD, int UNROLL>
-__device__ __forceinline__ float dw_sweep(const KConst &c, const float4 *buf, int lo, int sub, int mmax,
+__device__ __forceinline__ float dw_sweep(const KConst &c0, const float4 *buf, int lo, int sub, int mmax,
                                           int menv, bool uniform, const Drone &d) {
+    const KConst c = pair_consts(c0);
     float acc = 0.f;
     if (uniform) {
 #pragma unroll UNROLL
@@ -78,8 +91,9 @@ __device__ __forceinline__ void dw_pairs(const KConst &c, const float4 *buf, flo
 // when its partner is above.  The summation order (per shift: own term, then
 // the received one) is fixed by the drone's place in its environment.
 template <bool DZMIN, bool UNIFORM, int UNROLL>
-__device__ __forceinline__ float dw_pairs_shfl(const KConst &c, const float4 *buf, int slot, int lo, int m,
+__device__ __forceinline__ float dw_pairs_shfl(const KConst &c0, const float4 *buf, int slot, int lo, int m,
                                                int mmax, const Drone &d) {
+    const KConst c = pair_consts(c0);
     // an idle slot (m = 0) runs the loop as a one-drone environment of itself
     const int mm = m > 0 ? m : 1;
     const int li = m > 0 ? slot - lo : 0;
@@ -88,18 +102,18 @@ __device__ __forceinline__ float dw_pairs_shfl(const KConst &c, const float4 *bu
     // executes with the whole wave; in a uniform bin every environment has
     // that size and no shift needs masking
     const int h = (m - 1) >> 1, hmax = (mmax - 1) >> 1;
-    // byte offsets, advanced cyclically: the partner's position (li + k) mod M
-    // in `buf`, and the lane (li - k) mod M whose term this lane receives
-    const char *bb = (const char *)buf;
-    const int a_beg = lo * 16, a_end = (lo + mm) * 16;
+    // advanced cyclically: the partner's position (li + k) mod M in `buf`, and
+    // the byte address of lane (li - k) mod M, whose term this lane receives
+    const float4 *q_beg = buf + lo, *q_end = buf + lo + mm;
+    const float4 *qj = buf + lo + li;
     const int p_beg = base * 4, p_last = (base + mm - 1) * 4;
-    int aj = (lo + li) * 16, ps = (base + li) * 4;
+    int ps = (base + li) * 4;
     float acc = 0.f;
 #pragma unroll UNROLL
     for (int k = 1; k <= hmax; ++k) {
-        aj = (aj + 16 == a_end) ? a_beg : aj + 16;
+        qj = (qj + 1 == q_end) ? q_beg : qj + 1;
         ps = (ps == p_beg) ? p_last : ps - 4;
-        const float4 q = *(const float4 *)(bb + aj);
+        const float4 q = *qj;
         const float dz = q.z - d.pz;
         float t = dw_term<DZMIN>(c, q.x - d.px, q.y - d.py, fabsf(dz));
         if (!UNIFORM) t = (k <= h) ? t : 0.f;
