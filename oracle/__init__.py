@@ -58,7 +58,8 @@ class Net(ctypes.Structure):
 class _CState(ctypes.Structure):
     _fields_ = [(n, ctypes.POINTER(ctypes.c_double)) for n in ("p", "q", "v", "w", "pid_int", "rpm", "ctl",
                                                                "rpm_cmd", "act_hist")] + \
-        [("act_count", ctypes.POINTER(ctypes.c_int32)), ("wind", ctypes.POINTER(ctypes.c_double))]
+        [("act_count", ctypes.POINTER(ctypes.c_int32)), ("wind", ctypes.POINTER(ctypes.c_double)),
+         ("obs_hist", ctypes.POINTER(ctypes.c_double)), ("obs_count", ctypes.POINTER(ctypes.c_int32))]
 
 
 class _CWind(ctypes.Structure):
@@ -75,13 +76,16 @@ WIND_COMBINED = 15
 
 class _CDr(ctypes.Structure):
     _fields_ = [("scale", ctypes.POINTER(ctypes.c_double)), ("tau_mot", ctypes.POINTER(ctypes.c_double)),
-                ("delay", ctypes.POINTER(ctypes.c_int32))]
+                ("delay", ctypes.POINTER(ctypes.c_int32)), ("noise_p", ctypes.c_double),
+                ("noise_v", ctypes.c_double), ("noise_rpy", ctypes.c_double), ("noise_w", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("obs_delay", ctypes.POINTER(ctypes.c_int32))]
 
 
 # Domain randomisation factor rows (orc_dr.scale) and the latency ring depth.
 DR_ROWS = ("m", "J", "L", "kf", "km", "drag", "C_gnd", "C1", "max_rpm", "g",
            "bias0", "bias1", "bias2", "bias3")
 DR_HIST = 32
+DR_OBS_HIST = 8
 
 
 _lib = None
@@ -310,15 +314,18 @@ def _cstate(s):
         if k == "ctl" and k not in s:
             continue
         assert s[k].dtype == np.float64 and s[k].flags.c_contiguous, k
-    for k in ("rpm_cmd", "act_hist", "wind"):
+    for k in ("rpm_cmd", "act_hist", "wind", "obs_hist"):
         if k in s:
             assert s[k].dtype == np.float64 and s[k].flags.c_contiguous, k
-    if "act_count" in s:
-        assert s["act_count"].dtype == np.int32 and s["act_count"].flags.c_contiguous
+    for k in ("act_count", "obs_count"):
+        if k in s:
+            assert s[k].dtype == np.int32 and s[k].flags.c_contiguous, k
     return _CState(*([s[k].ctypes.data_as(_D) if k in s else None
                       for k in ("p", "q", "v", "w", "pid_int", "rpm", "ctl", "rpm_cmd", "act_hist")] +
                      [s["act_count"].ctypes.data_as(_I32) if "act_count" in s else None,
-                      s["wind"].ctypes.data_as(_D) if "wind" in s else None]))
+                      s["wind"].ctypes.data_as(_D) if "wind" in s else None,
+                      s["obs_hist"].ctypes.data_as(_D) if "obs_hist" in s else None,
+                      s["obs_count"].ctypes.data_as(_I32) if "obs_count" in s else None]))
 
 
 def dr_state(state, act_type):
@@ -329,6 +336,8 @@ def dr_state(state, act_type):
     state["rpm_cmd"] = state["rpm"].copy()
     state["act_hist"] = np.zeros((DR_HIST, ACTION_ROWS[act_type], n))
     state["act_count"] = np.zeros(n, dtype=np.int32)
+    state["obs_hist"] = np.zeros((DR_OBS_HIST, 20, n))
+    state["obs_count"] = np.zeros(n, dtype=np.int32)
     return state
 
 
@@ -360,8 +369,9 @@ def step(P, dt, aero_mask, act_type, ctrl_decim, env_offsets, state, action,
     """Advance ``state`` (dict of [c][N] float64 arrays, updated in place) by
     n_steps with the semi-implicit Euler step or classic RK4; returns the
     observation array [slots][20][N] or None.  dr: None, or a dict with
-    "scale" [len(DR_ROWS)][N] and optional "tau_mot" [N] (s) and "delay" [N]
-    (int steps) for the domain-randomised Euler step (orc_step_dr)."""
+    "scale" [len(DR_ROWS)][N] and optional "tau_mot" [N] (s), "delay" [N]
+    (int steps), "noise" (sigma_p, sigma_v, sigma_rpy, sigma_w), "seed" and
+    "obs_delay" [N] (int steps) for the domain-randomised Euler step."""
     off = np.ascontiguousarray(np.asarray(env_offsets, dtype=np.int32))
     n_envs = len(off) - 1
     n = int(off[-1])
@@ -382,8 +392,11 @@ def step(P, dt, aero_mask, act_type, ctrl_decim, env_offsets, state, action,
             assert sc.shape == (len(DR_ROWS), n), sc.shape
             tau = np.ascontiguousarray(dr["tau_mot"], dtype=np.float64) if dr.get("tau_mot") is not None else None
             dl = np.ascontiguousarray(dr["delay"], dtype=np.int32) if dr.get("delay") is not None else None
+            od = np.ascontiguousarray(dr["obs_delay"], dtype=np.int32) if dr.get("obs_delay") is not None else None
+            nz = tuple(float(x) for x in (dr.get("noise") or (0.0, 0.0, 0.0, 0.0)))
             cdr = _CDr(_dp(sc), _dp(tau) if tau is not None else None,
-                       dl.ctypes.data_as(_I32) if dl is not None else None)
+                       dl.ctypes.data_as(_I32) if dl is not None else None, nz[0], nz[1], nz[2], nz[3],
+                       int(dr.get("seed", 0)), od.ctypes.data_as(_I32) if od is not None else None)
         rc = _load().orc_step_disturbed(*args, ctypes.byref(cdr) if cdr is not None else None,
                                         ctypes.byref(wind) if wind is not None else None)
     else:

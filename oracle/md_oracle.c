@@ -566,6 +566,51 @@ static void wind_force(const orc_wind *W, double dt, int64_t t, int32_t i, const
     }
 }
 
+/* The KIN row the sensors deliver under domain randomisation (Table
+ * "Recommended domain-randomization ranges", sensors): per-step Gaussian
+ * noise added to position, roll/pitch/yaw, velocity and body rates (the
+ * quaternion and rotor-speed rows stay exact), twelve normals from Philox
+ * streams 2-4 of (drone, global step) by Box-Muller; then the sensor latency:
+ * the noisy row enters a ring of ORC_DR_OBS_HIST slots indexed by the global
+ * step and the row delivered is the one entered min(obs_delay, entered - 1)
+ * steps earlier.  Readings: noise and latency act on the returned
+ * observation only (the controllers fly on the simulator's state); the ring
+ * is advanced every step whether or not observations are requested. */
+static void sensor_row(const orc_dr *dr, int64_t t, int32_t i, int N, orc_state *s, double row[20])
+{
+    if (dr->noise_p > 0.0 || dr->noise_v > 0.0 || dr->noise_rpy > 0.0 || dr->noise_w > 0.0) {
+        const orc_wind key = {.seed = dr->seed};
+        double xi[12];
+        for (uint32_t st = 0; st < 3; ++st) {
+            uint32_t r[4];
+            wind_words(&key, i, t, 2u + st, r);
+            const double rad0 = sqrt(-2.0 * log(1.0 - unit24(r[0])));
+            const double rad1 = sqrt(-2.0 * log(1.0 - unit24(r[2])));
+            xi[4 * st + 0] = rad0 * cos(2.0 * M_PI * unit24(r[1]));
+            xi[4 * st + 1] = rad0 * sin(2.0 * M_PI * unit24(r[1]));
+            xi[4 * st + 2] = rad1 * cos(2.0 * M_PI * unit24(r[3]));
+            xi[4 * st + 3] = rad1 * sin(2.0 * M_PI * unit24(r[3]));
+        }
+        for (int c = 0; c < 3; ++c) {
+            row[c] += dr->noise_p * xi[c];
+            row[7 + c] += dr->noise_rpy * xi[6 + c];
+            row[10 + c] += dr->noise_v * xi[3 + c];
+            row[13 + c] += dr->noise_w * xi[9 + c];
+        }
+    }
+    if (dr->obs_delay) {
+        const int64_t slot = t % ORC_DR_OBS_HIST;
+        for (int c = 0; c < 20; ++c) s->obs_hist[((size_t)slot * 20 + c) * N + i] = row[c];
+        int32_t cnt = s->obs_count[i] + 1;
+        if (cnt > ORC_DR_OBS_HIST) cnt = ORC_DR_OBS_HIST;
+        s->obs_count[i] = cnt;
+        int32_t d = dr->obs_delay[i];
+        if (d > cnt - 1) d = cnt - 1;
+        const int64_t from = (slot - d + ORC_DR_OBS_HIST) % ORC_DR_OBS_HIST;
+        for (int c = 0; c < 20; ++c) row[c] = s->obs_hist[((size_t)from * 20 + c) * N + i];
+    }
+}
+
 /* One drone's physical parameter block under domain randomisation (Table
  * "Recommended domain-randomization ranges"): the nominal block with mass,
  * inertia (one factor for the three principal moments), arm length, kf, km,
@@ -625,6 +670,7 @@ static int step_impl(const orc_params *P, double dt, uint32_t aero_mask, int act
                (dr->delay && (!s->act_hist || !s->act_count))))
         return -1;
     if (wind && (wind->models & (ORC_WIND_DRYDEN | ORC_WIND_GUST)) && !s->wind) return -1;
+    if (dr && dr->obs_delay && (!s->obs_hist || !s->obs_count)) return -1;
     orc_derived D;
     orc_derive(P, &D);
     const int N = n_drones;
@@ -721,14 +767,19 @@ static int step_impl(const orc_params *P, double dt, uint32_t aero_mask, int act
                 }
                 for (int c = 0; c < 4; ++c) s->q[c * N + i] = q[c];
 
-                if (obs && n_obs_slots > 0) {
-                    double *o = obs + (size_t)(k % n_obs_slots) * 20 * N;
+                const int sensors = dr && (dr->obs_delay || dr->noise_p > 0.0 || dr->noise_v > 0.0 ||
+                                            dr->noise_rpy > 0.0 || dr->noise_w > 0.0);
+                if ((obs && n_obs_slots > 0) || sensors) {
                     double rpy[3];
                     orc_euler_zyx(q, rpy);
-                    const double row[20] = {p[0], p[1], p[2], q[0], q[1], q[2], q[3],
-                                            rpy[0], rpy[1], rpy[2], v[0], v[1], v[2],
-                                            w[0], w[1], w[2], n[0], n[1], n[2], n[3]};
-                    for (int c = 0; c < 20; ++c) o[(size_t)c * N + i] = row[c];
+                    double row[20] = {p[0], p[1], p[2], q[0], q[1], q[2], q[3],
+                                      rpy[0], rpy[1], rpy[2], v[0], v[1], v[2],
+                                      w[0], w[1], w[2], n[0], n[1], n[2], n[3]};
+                    if (sensors) sensor_row(dr, step0 + k, i, N, s, row);
+                    if (obs && n_obs_slots > 0) {
+                        double *o = obs + (size_t)(k % n_obs_slots) * 20 * N;
+                        for (int c = 0; c < 20; ++c) o[(size_t)c * N + i] = row[c];
+                    }
                 }
             }
         }

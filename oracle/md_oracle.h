@@ -65,6 +65,10 @@ typedef struct orc_state {
     int32_t *act_count; /* [n] actions entered since the ring was cleared (with latency) */
     /* wind only: [5][n] Dryden velocity x, y, z (m/s), gust step (-1 idle), gust heading (rad) */
     double *wind;
+    /* sensor latency only: [ORC_DR_OBS_HIST][20][n] ring of noisy KIN rows, and
+     * [n] rows entered since the ring was cleared */
+    double *obs_hist;
+    int32_t *obs_count;
 } orc_state;
 
 /* Wind (Sec. "Wind and turbulence"); readings at wind_force in md_oracle.c. */
@@ -91,10 +95,18 @@ enum {
     ORC_DR_NSCALE = ORC_DR_BIAS + 4
 };
 #define ORC_DR_HIST 32
+#define ORC_DR_OBS_HIST 8
 typedef struct orc_dr {
     const double *scale;   /* [ORC_DR_NSCALE][n] */
     const double *tau_mot; /* [n] motor time constant, s (0 = no lag); nullable */
     const int32_t *delay;  /* [n] action latency in steps, 0..ORC_DR_HIST-1; nullable */
+    /* sensor side: per-step Gaussian noise on the KIN rows (standard deviations
+     * of position m, velocity m/s, roll/pitch/yaw rad, body rate rad/s; 0 =
+     * off), Philox key, and sensor latency in steps 0..ORC_DR_OBS_HIST-1
+     * (nullable) */
+    double noise_p, noise_v, noise_rpy, noise_w;
+    uint64_t seed;
+    const int32_t *obs_delay;
 } orc_dr;
 
 enum { ORC_AERO_GND = 1, ORC_AERO_DRAG = 2, ORC_AERO_DW = 4, ORC_AERO_SURROGATE = 8 };

@@ -195,3 +195,76 @@ def test_controllers_keep_nominal_constants():
         outs.append((s["rpm_cmd"].copy(), s["pid_int"].copy()))
     np.testing.assert_array_equal(outs[0][0], outs[1][0])
     np.testing.assert_array_equal(outs[0][1], outs[1][1])
+
+
+def test_sensor_noise_statistics_and_exact_rows():
+    """Per-step Gaussian sensor noise with the table's standard deviations on
+    position, velocity, roll/pitch/yaw and body rates; quaternion and rotor
+    speed rows untouched; same seed, same draws."""
+    from scipy import stats
+    P = orc.cf2x()
+    h = orc.derive(P).hover_rpm
+    n = 20000
+    sig = (0.01, 0.05, np.radians(1.0), 0.05)
+    act = np.full((1, 4, n), h)
+    clean_s = orc.dr_state(_state(n), orc.ACT_RPM)
+    clean = orc.step(P, H, 0, orc.ACT_RPM, 1, np.arange(n + 1), clean_s, act, False, 1, n_obs_slots=1,
+                     dr=_ones(n))[0]
+    outs = []
+    for seed in (5, 5, 6):
+        dr = dict(_ones(n), noise=sig, seed=seed)
+        s = orc.dr_state(_state(n), orc.ACT_RPM)
+        outs.append(orc.step(P, H, 0, orc.ACT_RPM, 1, np.arange(n + 1), s, act, False, 1, n_obs_slots=1,
+                             dr=dr)[0])
+        for k in ("p", "v", "q", "w"):
+            np.testing.assert_array_equal(s[k], clean_s[k])  # the state is not disturbed
+    np.testing.assert_array_equal(outs[0], outs[1])
+    assert np.abs(outs[0] - outs[2]).max() > 0
+    d = outs[0] - clean
+    np.testing.assert_array_equal(d[3:7], 0)
+    np.testing.assert_array_equal(d[16:20], 0)
+    for rows, sd in ((range(0, 3), sig[0]), (range(10, 13), sig[1]), (range(7, 10), sig[2]), (range(13, 16), sig[3])):
+        for r in rows:
+            z = d[r] / sd
+            assert abs(z.mean()) < 0.03 and abs(z.std() - 1) < 0.03, r
+            assert stats.kstest(z, "norm").pvalue > 1e-3
+    assert abs(np.corrcoef(d[0], d[10])[0, 1]) < 0.03
+
+
+def test_sensor_latency_delays_the_rows_across_launches():
+    P = orc.cf2x()
+    h = orc.derive(P).hover_rpm
+    n, K = 3, 14
+    rng = np.random.default_rng(44)
+    act = h * (1 + rng.uniform(-0.05, 0.05, size=(K, 4, n)))
+    ref_s = orc.dr_state(_state(n), orc.ACT_RPM)
+    ref = orc.step(P, H, 0, orc.ACT_RPM, 1, [0, 1, 2, 3], ref_s, act, True, K, n_obs_slots=K, dr=_ones(n))
+    dr = dict(_ones(n), obs_delay=np.array([0, 2, 5], dtype=np.int32))
+    s = orc.dr_state(_state(n), orc.ACT_RPM)
+    o1 = orc.step(P, H, 0, orc.ACT_RPM, 1, [0, 1, 2, 3], s, act[:4], True, 4, n_obs_slots=4, dr=dr)
+    o2 = orc.step(P, H, 0, orc.ACT_RPM, 1, [0, 1, 2, 3], s, act[4:], True, K - 4, step0=4,
+                  n_obs_slots=K - 4, dr=dr)
+    got = np.concatenate([o1, o2])
+    for i, dly in enumerate((0, 2, 5)):
+        src = np.maximum(np.arange(K) - dly, 0)
+        np.testing.assert_array_equal(got[:, :, i], ref[src][:, :, i])
+    for k in ("p", "v", "q", "w", "rpm"):
+        np.testing.assert_array_equal(s[k], ref_s[k])
+
+
+def test_sensor_ring_advances_on_steps_without_observations():
+    """The sensor latency ring is written on every step, whether or not the
+    launch returns observations, so the row returned after K steps does not
+    depend on which earlier steps were observed."""
+    P = orc.cf2x()
+    h = orc.derive(P).hover_rpm
+    n, K = 3, 11
+    rng = np.random.default_rng(45)
+    act = h * (1 + rng.uniform(-0.05, 0.05, size=(K, 4, n)))
+    dr = dict(_ones(n), obs_delay=np.array([1, 3, 7], dtype=np.int32), noise=(0.01, 0.05, 0.02, 0.05), seed=9)
+    a = orc.dr_state(_state(n), orc.ACT_RPM)
+    every = orc.step(P, H, 0, orc.ACT_RPM, 1, [0, 1, 2, 3], a, act, True, K, n_obs_slots=K, dr=dr)
+    b = orc.dr_state(_state(n), orc.ACT_RPM)
+    orc.step(P, H, 0, orc.ACT_RPM, 1, [0, 1, 2, 3], b, act[:6], True, 6, dr=dr)
+    last = orc.step(P, H, 0, orc.ACT_RPM, 1, [0, 1, 2, 3], b, act[6:], True, K - 6, step0=6, n_obs_slots=1, dr=dr)
+    np.testing.assert_array_equal(last[-1], every[-1])
