@@ -178,9 +178,10 @@ def timed_rollouts(args, w, p, with_obs, mask=None, integrator=None, surrogate_w
         state = md.DeviceState.from_numpy(w["state"])
         dr_t = None
         if dr is not None:
-            dr_t = {k: (torch.from_numpy(v).cuda() if v is not None else None) for k, v in dr.items()}
+            dr_t = {k: (torch.from_numpy(v).cuda() if isinstance(v, np.ndarray) else v) for k, v in dr.items()}
             state.add_dr_blocks(act)
-            md.md_set_domain_randomization(ctx, dr_t["scale"], dr_t["tau_mot"], dr_t["delay"])
+            md.md_set_domain_randomization(ctx, dr_t["scale"], dr_t["tau_mot"], dr_t["delay"],
+                                           noise=dr_t["noise"], seed=dr_t["seed"], obs_delay=dr_t["obs_delay"])
         if wind is not None:
             state.add_wind_block()
             md.md_set_wind(ctx, **wind)
@@ -265,13 +266,20 @@ def surrogate_leg(args, w, p, with_obs):
 def dr_leg(args, w, p, with_obs):
     """The same rollouts with per-drone domain randomisation (Table
     "Recommended domain-randomization ranges": factors, motor lag, action
-    latency through the history ring)."""
+    latency through the history ring, sensor noise and sensor latency)."""
     from paper_2606_08039_amd import workloads as wl
     n = int(w["env_offsets"][-1])
-    wall, kernel_ms, cfg, _, chk = timed_rollouts(args, w, p, with_obs, dr=wl.domain_randomization(w, 50))
+    # latencies drawn per environment (one sensing and radio pipeline per
+    # arena); the per-vehicle draw is timed beside it
+    wall, kernel_ms, cfg, _, chk = timed_rollouts(args, w, p, with_obs,
+                                                  dr=wl.domain_randomization(w, 50, latency_per="env"))
+    wall_d, kernel_ms_d, cfg_d, _, _ = timed_rollouts(args, w, p, with_obs,
+                                                      dr=wl.domain_randomization(w, 50, latency_per="drone"))
     return {"value": float(n) * w["n_steps"] * args.steps / wall, "unit": "drone-steps/s",
             "ms_per_step": wall / args.steps * 1e3, "kernel_ms_avg": float(np.mean(kernel_ms)),
-            "launch_config": cfg, "final_state": chk}
+            "launch_config": cfg, "final_state": chk, "latency_per": "environment",
+            "per_drone_latency": {"value": float(n) * w["n_steps"] * args.steps / wall_d,
+                                  "kernel_ms_avg": float(np.mean(kernel_ms_d)), "launch_config": cfg_d}}
 
 
 # Sec. "Wind and turbulence", the paper's hover example: a steady 0.9 m/s

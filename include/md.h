@@ -99,12 +99,18 @@ typedef struct md_derived {
  * [MD_DR_HIST][rows][n_drones] the action-latency ring and act_count
  * (int32 [n_drones]) the number of actions entered into it, saturating at
  * MD_DR_HIST (both only with per-drone delays; zero act_count to start an
- * episode).  They may be NULL otherwise. */
+ * episode).  They may be NULL otherwise.  With per-drone sensor latency
+ * (md_dr.obs_delay) obs_hist [MD_DR_OBS_HIST][20][n_drones] float32 is the
+ * ring of observation rows and obs_count (int32 [n_drones]) the number of
+ * rows entered into it, saturating at MD_DR_OBS_HIST (zero it to start an
+ * episode); NULL otherwise. */
 typedef struct md_state {
     float *p, *q, *v, *w, *pid_int, *rpm, *ctl;
     float *rpm_cmd, *act_hist;
     int32_t *act_count;
     float *wind; /* [5][n_drones] with wind gusts or turbulence, see md_set_wind */
+    float *obs_hist;
+    int32_t *obs_count;
 } md_state;
 
 typedef struct md_ctx md_ctx;
@@ -165,18 +171,40 @@ md_status md_step(md_ctx *ctx, const md_state *s, const float *d_action, int act
  *     C_gnd, C1 (the downwash a drone receives), MAX_RPM, g, and four
  *     per-motor bias factors on the commanded rotor speeds;
  *   tau_mot [n_drones] motor time constant in s (0: no lag), nullable;
- *   delay [n_drones] action latency in steps, 0..MD_DR_HIST-1, nullable.
- * Per step and drone: the step's action rows enter the act_hist ring at slot
- * (step0 + k) mod MD_DR_HIST and the rows used are those entered
- * min(delay, act_count - 1) steps earlier; the command (the RPM action, or
+ *   delay [n_drones] action latency in steps, 0..MD_DR_HIST-1 (values
+ *     outside are clamped to that range), nullable.
+ * Per step k and drone: the action rows used are those of step
+ * k - min(delay, act_count - 1), act_count counting the actions of the
+ * episode up to step k and saturating at MD_DR_HIST; the command (the RPM action, or
  * the controller's output at controller steps, held in rpm_cmd) is
  * multiplied by the bias, clipped to [0, factor x MAX_RPM] and passed
  * through the lag n <- n + (1 - e^{-dt/tau})(c - n) (n = c for tau = 0);
  * Eq. 1-7 then use the drone's constants.  Controllers keep the nominal
  * constants; h_clip stays nominal.  All factors 1, tau 0 and delay 0
- * reproduce the plain step.  The arrays are device memory owned by the
- * caller and read by every later md_step until the next call; NULL turns
- * randomisation off.  Errors: MD_E_INVALID_ARG for a null scale,
+ * reproduce the plain step.
+ * Sensor side (same table: observation noise and sensor latency), applied
+ * to the KIN row of every step, which the controllers never see:
+ *   noise_p, noise_v, noise_rpy, noise_w standard deviations (m, m/s, rad,
+ *     rad/s) of zero-mean Gaussian noise added to position, velocity,
+ *     roll/pitch/yaw and body rates (quaternion and rotor rows exact); the
+ *     twelve normals of drone i at global step t are Box-Muller pairs of the
+ *     24-bit uniforms of Philox4x32-10 blocks with counter (i, t low word,
+ *     t high word, 2 + b), b = 0, 1, 2, key = seed (low word, high word), in
+ *     the order p xyz, v xyz, rpy, w xyz;
+ *   obs_delay [n_drones] sensor latency in steps, 0..MD_DR_OBS_HIST-1
+ *     (clamped), nullable: the row returned at step k is the (noisy) row of
+ *     step k - min(obs_delay, obs_count - 1), obs_count counting the rows of
+ *     the episode up to step k and saturating at MD_DR_OBS_HIST; rows are
+ *     counted whether or not the launch returns observations.
+ * Both rings carry the latency across launches: at its end a launch leaves
+ * its last MD_DR_HIST action rows in act_hist and its last MD_DR_OBS_HIST
+ * rows in obs_hist, at slot (global step) mod the ring size, which is
+ * exactly what the next launch can reach (earlier slots keep older entries).
+ * Within a launch the delayed values come from the launch's own inputs and
+ * rows, not from the rings.
+ * The arrays are device memory owned by the caller and read by every later
+ * md_step until the next call; NULL turns randomisation off.  Errors:
+ * MD_E_INVALID_ARG for a null scale or a negative or non-finite noise level,
  * MD_E_UNSUPPORTED with MD_AERO_SURROGATE or MD_INTEG_RK4. */
 #define MD_DR_M 0
 #define MD_DR_J 1
@@ -191,10 +219,14 @@ md_status md_step(md_ctx *ctx, const md_state *s, const float *d_action, int act
 #define MD_DR_BIAS 10 /* rows 10..13: motors 0..3 */
 #define MD_DR_NSCALE 14
 #define MD_DR_HIST 32
+#define MD_DR_OBS_HIST 8
 typedef struct md_dr {
     const float *scale;
     const float *tau_mot;
     const int32_t *delay;
+    float noise_p, noise_v, noise_rpy, noise_w;
+    uint64_t seed;
+    const int32_t *obs_delay;
 } md_dr;
 md_status md_set_domain_randomization(md_ctx *ctx, const md_dr *dr);
 

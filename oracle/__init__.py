@@ -67,7 +67,8 @@ class _CWind(ctypes.Structure):
                 ("cd_area", ctypes.c_double), ("gust_prob", ctypes.c_double),
                 ("gust_duration", ctypes.c_double), ("gust_amp", ctypes.c_double),
                 ("dryden_sigma", ctypes.c_double), ("dryden_airspeed", ctypes.c_double),
-                ("sin_amp", ctypes.c_double), ("sin_omega", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("sin_amp", ctypes.c_double), ("sin_omega", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("drone_id", ctypes.POINTER(ctypes.c_int32))]
 
 
 WIND_CONSTANT, WIND_GUST, WIND_DRYDEN, WIND_SINUSOIDAL = 1, 2, 4, 8
@@ -78,7 +79,8 @@ class _CDr(ctypes.Structure):
     _fields_ = [("scale", ctypes.POINTER(ctypes.c_double)), ("tau_mot", ctypes.POINTER(ctypes.c_double)),
                 ("delay", ctypes.POINTER(ctypes.c_int32)), ("noise_p", ctypes.c_double),
                 ("noise_v", ctypes.c_double), ("noise_rpy", ctypes.c_double), ("noise_w", ctypes.c_double),
-                ("seed", ctypes.c_uint64), ("obs_delay", ctypes.POINTER(ctypes.c_int32))]
+                ("seed", ctypes.c_uint64), ("obs_delay", ctypes.POINTER(ctypes.c_int32)),
+                ("drone_id", ctypes.POINTER(ctypes.c_int32))]
 
 
 # Domain randomisation factor rows (orc_dr.scale) and the latency ring depth.
@@ -358,9 +360,16 @@ def philox4x32(ctr, key):
 
 
 def make_wind(models, v_mean=(0.0, 0.0, 0.0), rho=1.225, cd_area=0.01, gust_prob=0.0, gust_duration=0.5,
-              gust_amp=0.0, dryden_sigma=0.0, dryden_airspeed=1.0, sin_amp=0.0, sin_omega=0.0, seed=0):
-    return _CWind(int(models), (ctypes.c_double * 3)(*v_mean), rho, cd_area, gust_prob, gust_duration,
-                  gust_amp, dryden_sigma, dryden_airspeed, sin_amp, sin_omega, int(seed))
+              gust_amp=0.0, dryden_sigma=0.0, dryden_airspeed=1.0, sin_amp=0.0, sin_omega=0.0, seed=0,
+              drone_id=None):
+    """drone_id: optional int32 [N], the first Philox counter word of each
+    drone (default its index), so that a sub-batch keeps its drones' draws."""
+    ids = np.ascontiguousarray(drone_id, dtype=np.int32) if drone_id is not None else None
+    w = _CWind(int(models), (ctypes.c_double * 3)(*v_mean), rho, cd_area, gust_prob, gust_duration,
+               gust_amp, dryden_sigma, dryden_airspeed, sin_amp, sin_omega, int(seed),
+               ids.ctypes.data_as(_I32) if ids is not None else None)
+    w._keep = ids
+    return w
 
 
 def step(P, dt, aero_mask, act_type, ctrl_decim, env_offsets, state, action,
@@ -370,8 +379,9 @@ def step(P, dt, aero_mask, act_type, ctrl_decim, env_offsets, state, action,
     n_steps with the semi-implicit Euler step or classic RK4; returns the
     observation array [slots][20][N] or None.  dr: None, or a dict with
     "scale" [len(DR_ROWS)][N] and optional "tau_mot" [N] (s), "delay" [N]
-    (int steps), "noise" (sigma_p, sigma_v, sigma_rpy, sigma_w), "seed" and
-    "obs_delay" [N] (int steps) for the domain-randomised Euler step."""
+    (int steps), "noise" (sigma_p, sigma_v, sigma_rpy, sigma_w), "seed",
+    "obs_delay" [N] (int steps) and "drone_id" [N] (Philox counter word) for
+    the domain-randomised Euler step."""
     off = np.ascontiguousarray(np.asarray(env_offsets, dtype=np.int32))
     n_envs = len(off) - 1
     n = int(off[-1])
@@ -393,10 +403,12 @@ def step(P, dt, aero_mask, act_type, ctrl_decim, env_offsets, state, action,
             tau = np.ascontiguousarray(dr["tau_mot"], dtype=np.float64) if dr.get("tau_mot") is not None else None
             dl = np.ascontiguousarray(dr["delay"], dtype=np.int32) if dr.get("delay") is not None else None
             od = np.ascontiguousarray(dr["obs_delay"], dtype=np.int32) if dr.get("obs_delay") is not None else None
+            ids = np.ascontiguousarray(dr["drone_id"], dtype=np.int32) if dr.get("drone_id") is not None else None
             nz = tuple(float(x) for x in (dr.get("noise") or (0.0, 0.0, 0.0, 0.0)))
             cdr = _CDr(_dp(sc), _dp(tau) if tau is not None else None,
                        dl.ctypes.data_as(_I32) if dl is not None else None, nz[0], nz[1], nz[2], nz[3],
-                       int(dr.get("seed", 0)), od.ctypes.data_as(_I32) if od is not None else None)
+                       int(dr.get("seed", 0)), od.ctypes.data_as(_I32) if od is not None else None,
+                       ids.ctypes.data_as(_I32) if ids is not None else None)
         rc = _load().orc_step_disturbed(*args, ctypes.byref(cdr) if cdr is not None else None,
                                         ctypes.byref(wind) if wind is not None else None)
     else:

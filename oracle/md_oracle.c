@@ -583,7 +583,7 @@ static void sensor_row(const orc_dr *dr, int64_t t, int32_t i, int N, orc_state 
         double xi[12];
         for (uint32_t st = 0; st < 3; ++st) {
             uint32_t r[4];
-            wind_words(&key, i, t, 2u + st, r);
+            wind_words(&key, dr->drone_id ? dr->drone_id[i] : i, t, 2u + st, r);
             const double rad0 = sqrt(-2.0 * log(1.0 - unit24(r[0])));
             const double rad1 = sqrt(-2.0 * log(1.0 - unit24(r[2])));
             xi[4 * st + 0] = rad0 * cos(2.0 * M_PI * unit24(r[1]));
@@ -756,7 +756,8 @@ static int step_impl(const orc_params *P, double dt, uint32_t aero_mask, int act
                 }
                 if (wind && wind->models) {
                     double Fwind[3];
-                    wind_force(wind, dt, step0 + k, i, p, v, s->wind ? s->wind + i : NULL, N, Fwind);
+                    wind_force(wind, dt, step0 + k, wind->drone_id ? wind->drone_id[i] : i, p, v,
+                               s->wind ? s->wind + i : NULL, N, Fwind);
                     for (int c = 0; c < 3; ++c) Fw[c] += Fwind[c];
                 }
                 orc_integrate(&Pi, dt, Fw, tau, p, q, v, w);

@@ -84,6 +84,9 @@ typedef struct orc_wind {
     double dryden_airspeed;   /* V in alpha = exp(-dt V / L), m/s */
     double sin_amp, sin_omega;/* N, rad/s */
     uint64_t seed;            /* Philox key */
+    const int32_t *drone_id;  /* [n] first Philox counter word of each drone
+                               * (nullable: the drone's index), so that a
+                               * sub-batch keeps the streams of its drones */
 } orc_wind;
 void orc_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
@@ -107,6 +110,7 @@ typedef struct orc_dr {
     double noise_p, noise_v, noise_rpy, noise_w;
     uint64_t seed;
     const int32_t *obs_delay;
+    const int32_t *drone_id; /* [n] first Philox counter word (nullable: index) */
 } orc_dr;
 
 enum { ORC_AERO_GND = 1, ORC_AERO_DRAG = 2, ORC_AERO_DW = 4, ORC_AERO_SURROGATE = 8 };

@@ -285,7 +285,7 @@ md_status launch(md_ctx *ctx, const md_state *s, const float *d_action, int acti
     StepArgs a;
     a.c = ctx->kc;
     a.s = StatePtr{s->p, s->q, s->v, s->w, s->pid_int, s->rpm, s->ctl, s->rpm_cmd, s->act_hist, s->act_count,
-                   s->wind};
+                   s->wind, s->obs_hist, s->obs_count};
     a.dr = ctx->dr;
     a.wind = ctx->wind;
     a.action = d_action;
@@ -500,18 +500,33 @@ md_status md_set_domain_randomization(md_ctx *ctx, const md_dr *dr) {
     if (!ctx) return MD_E_INVALID_ARG;
     if (!dr) {
         ctx->dr_on = false;
-        ctx->dr = md::DrPtr{nullptr, nullptr, nullptr};
+        ctx->dr = md::DrPtr{};
         return MD_OK;
     }
     if (!dr->scale) {
         ctx->err = "md_set_domain_randomization: null scale array";
         return MD_E_INVALID_ARG;
     }
+    const float sig[4] = {dr->noise_p, dr->noise_v, dr->noise_rpy, dr->noise_w};
+    for (float x : sig)
+        if (!(x >= 0.f) || !std::isfinite(x)) {
+            ctx->err = "md_set_domain_randomization: negative or non-finite sensor noise level";
+            return MD_E_INVALID_ARG;
+        }
     if ((ctx->mask & MD_AERO_SURROGATE) || ctx->integ == MD_INTEG_RK4) {
         ctx->err = "md_set_domain_randomization: supported with the plain semi-implicit Euler step only";
         return MD_E_UNSUPPORTED;
     }
-    ctx->dr = md::DrPtr{dr->scale, dr->tau_mot, dr->delay};
+    md::DrPtr d{};
+    d.scale = dr->scale;
+    d.tau_mot = dr->tau_mot;
+    d.delay = dr->delay;
+    for (int k = 0; k < 4; ++k) d.sig[k] = sig[k];
+    d.noisy = sig[0] > 0.f || sig[1] > 0.f || sig[2] > 0.f || sig[3] > 0.f;
+    d.key0 = (uint32_t)(dr->seed & 0xffffffffull);
+    d.key1 = (uint32_t)(dr->seed >> 32);
+    d.obs_delay = dr->obs_delay;
+    ctx->dr = d;
     ctx->dr_on = true;
     return MD_OK;
 }
@@ -573,9 +588,10 @@ md_status md_step(md_ctx *ctx, const md_state *s, const float *d_action, int act
         return MD_E_INVALID_ARG;
     }
     if (ctx->dr_on && ((ctx->act != MD_ACT_RPM && !s->rpm_cmd) ||
-                       (ctx->dr.delay && (!s->act_hist || !s->act_count)))) {
-        ctx->err = "md_step: domain randomisation needs rpm_cmd (controller actions) and, with delays, "
-                   "act_hist and act_count";
+                       (ctx->dr.delay && (!s->act_hist || !s->act_count)) ||
+                       (ctx->dr.obs_delay && (!s->obs_hist || !s->obs_count)))) {
+        ctx->err = "md_step: domain randomisation needs rpm_cmd (controller actions), with action delays "
+                   "act_hist and act_count, with sensor delays obs_hist and obs_count";
         return MD_E_INVALID_ARG;
     }
     if ((ctx->wind.models & (MD_WIND_GUST | MD_WIND_DRYDEN)) && !s->wind) {

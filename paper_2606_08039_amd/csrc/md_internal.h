@@ -35,6 +35,8 @@ struct StatePtr {
     float *rpm_cmd, *act_hist;  // domain randomisation: held command, action ring
     int32_t *act_count;         // domain randomisation: ring fill per drone
     float *wind;                // wind: [5][N] Dryden velocity, gust step, gust heading
+    float *obs_hist;            // sensor latency: [MD_DR_OBS_HIST][20][N] ring of rows
+    int32_t *obs_count;         // sensor latency: ring fill per drone
 };
 
 // Wind parameters (md_wind) prepared on the host.
@@ -52,9 +54,13 @@ struct WindArgs {
 
 // Domain randomisation inputs (md_dr), device pointers.
 struct DrPtr {
-    const float *scale;     // [MD_DR_NSCALE][N]
-    const float *tau_mot;   // [N] or null
-    const int32_t *delay;   // [N] or null
+    const float *scale;      // [MD_DR_NSCALE][N]
+    const float *tau_mot;    // [N] or null
+    const int32_t *delay;    // [N] or null
+    float sig[4];            // sensor noise sigma: position, velocity, roll/pitch/yaw, body rates
+    bool noisy;              // any sigma > 0
+    uint32_t key0, key1;     // Philox key of the sensor noise (seed)
+    const int32_t *obs_delay;  // [N] or null
 };
 
 // Action rows per action type (MD_ACT_DSL carries a feed-forward acceleration).

@@ -150,6 +150,44 @@ __device__ __forceinline__ void wind_force(const WindArgs &W, float dt, long lon
     }
 }
 
+// Sensor noise on one drone's KIN row at global step t, as documented at
+// md_set_domain_randomization: Gaussian noise on position, velocity,
+// roll/pitch/yaw and body rates from three Philox blocks (streams 2, 3, 4;
+// Box-Muller on 24-bit uniforms).
+__device__ __forceinline__ void sensor_noise(const DrPtr &dr, int di, long long t, float row[20]) {
+    const uint32_t tl = (uint32_t)((unsigned long long)t & 0xffffffffull);
+    const uint32_t th = (uint32_t)((unsigned long long)t >> 32);
+    float xi[12];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const uint4 r = philox4x32(make_uint4((uint32_t)di, tl, th, 2u + (uint32_t)b), dr.key0, dr.key1);
+        const float rad0 = fsqrt(-2.f * logf(1.f - unit24(r.x)));
+        const float rad1 = fsqrt(-2.f * logf(1.f - unit24(r.z)));
+        float s1, c1, s3, c3;
+        sincospif(2.f * unit24(r.y), &s1, &c1);
+        sincospif(2.f * unit24(r.w), &s3, &c3);
+        xi[4 * b + 0] = rad0 * c1;
+        xi[4 * b + 1] = rad0 * s1;
+        xi[4 * b + 2] = rad1 * c3;
+        xi[4 * b + 3] = rad1 * s3;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        row[k] = fmaf(dr.sig[0], xi[k], row[k]);
+        row[10 + k] = fmaf(dr.sig[1], xi[3 + k], row[10 + k]);
+        row[7 + k] = fmaf(dr.sig[2], xi[6 + k], row[7 + k]);
+        row[13 + k] = fmaf(dr.sig[3], xi[9 + k], row[13 + k]);
+    }
+}
+
+// One drone's 20-row observation into slot `slot` of [slots][20][N] when the
+// slot differs between lanes (64-bit per-lane addresses).
+__device__ __forceinline__ void store_obs_lane(float *obs, int slot, int N, int di, const float row[20]) {
+    float *b = obs + (long long)slot * 20 * N + di;
+#pragma unroll
+    for (int k = 0; k < 20; ++k) b[(long long)k * N] = row[k];
+}
+
 template <uint32_t MASK, int ACT, int LPD, int UNROLL, int SYM, bool DR>
 __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     extern __shared__ float4 lds_pos[];  // [2][2 * slots] positions; then T [slots][tstride] (SYM)
@@ -197,7 +235,7 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     float bias[4] = {1.f, 1.f, 1.f, 1.f};
     float lag = 1.f;            // 1 - e^{-dt/tau}
     bool has_lag = false;
-    int delay = 0, issued = 0;  // action latency (steps) and ring fill
+    int delay = 0, acnt0 = 0;  // action latency (steps, clamped to the ring) and ring fill at launch
     float cmdh[4] = {0.f, 0.f, 0.f, 0.f};  // controller output held between updates
     // The disturbed instantiation also serves wind alone: randomisation (the
     // factor table, lag, latency, the held-command block) is on only when the
@@ -215,12 +253,28 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         has_lag = tau > 0.f;
         lag = has_lag ? 1.f - expf(-c.dt / tau) : 1.f;
         if (ring) {
-            delay = a.dr.delay[di];
-            issued = a.s.act_count[di];
+            delay = min(max(a.dr.delay[di], 0), MD_DR_HIST - 1);
+            acnt0 = min(max(a.s.act_count[di], 0), MD_DR_HIST);
         }
         if (ACT >= 1)
             for (int k = 0; k < 4; ++k) cmdh[k] = a.s.rpm_cmd[k * N + di];
     }
+    // Sensor noise and latency act on the returned rows only.  The latency
+    // rings (actions and rows) are kept in HBM across launches only: the
+    // value used at global step t is the one entered at step
+    // r = t - min(delay, fill at launch + steps so far) (the oldest one while
+    // the ring fills), read from this launch's own inputs or rows when
+    // r >= step0 and from the ring otherwise; each launch enters only its
+    // last MD_DR_HIST actions and MD_DR_OBS_HIST rows, which is all a later
+    // launch can reach.
+    const bool oring = rnd && a.dr.obs_delay != nullptr;
+    const bool noisy = rnd && a.dr.noisy;
+    int odelay = 0, ocnt0 = 0;
+    if (oring && valid) {
+        odelay = min(max(a.dr.obs_delay[di], 0), MD_DR_OBS_HIST - 1);
+        ocnt0 = min(max(a.s.obs_count[di], 0), MD_DR_OBS_HIST);
+    }
+    int osl = oring ? (int)(a.step0 % (long long)MD_DR_OBS_HIST) : 0;
 
     float *tmat = (float *)(lds_pos + 4 * slots);
     if (SYM == 1 && (MASK & 4u) && valid) {
@@ -266,18 +320,18 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
                 phase = (phase + 1 == c.decim) ? 0 : phase + 1;
             }
         } else {
-            // action rows of this step, through the latency ring
-            const bool need = (ACT == 0) || (phase == 0) || ring;
+            // action rows of this step, delayed by the drone's latency
+            const bool need = (ACT == 0) || (phase == 0);
             float row[ROWS];
             if (valid && need) {
-                for (int k = 0; k < ROWS; ++k)
-                    row[k] = (ACT >= 1 && held) ? tgt_held[k] : act[(long long)k * N + di];
-                if (ring) {
-                    float *h = a.s.act_hist;
-                    for (int k = 0; k < ROWS; ++k) h[((long long)hslot * ROWS + k) * N + di] = row[k];
-                    issued = min(issued + 1, MD_DR_HIST);
-                    const int dd = min(delay, issued - 1);
-                    const int from = hslot - dd + (hslot < dd ? MD_DR_HIST : 0);
+                const int back = ring ? min(delay, acnt0 + step) : 0;
+                if (back <= step) {
+                    const float *ar = act - a.act_step_stride * back;
+                    for (int k = 0; k < ROWS; ++k)
+                        row[k] = (ACT >= 1 && held) ? tgt_held[k] : ar[(long long)k * N + di];
+                } else {
+                    const float *h = a.s.act_hist;
+                    const int from = hslot - back + (hslot < back ? MD_DR_HIST : 0);
                     for (int k = 0; k < ROWS; ++k) row[k] = h[((long long)from * ROWS + k) * N + di];
                 }
             }
@@ -329,14 +383,46 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         // ---- Newton-Euler + exponential map (Eq. 7)
         integrate(cl, d, Fx, Fy, Fz, tx, ty, tz);
         // ---- KIN observation
-        if (a.obs != nullptr && writer) {
+        const bool otail = oring && step >= a.n_steps - MD_DR_OBS_HIST;
+        if ((a.obs != nullptr || otail) && writer) {
             float roll, pitch, yaw;
             euler_zyx(d, roll, pitch, yaw);
-            const float orow[20] = {d.px, d.py, d.pz, d.qw, d.qx, d.qy, d.qz, roll, pitch, yaw,
-                                    d.vx, d.vy, d.vz, d.wx, d.wy, d.wz, n[0], n[1], n[2], n[3]};
-            store_obs(a.obs, oslot, N, di, orow);
+            float orow[20] = {d.px, d.py, d.pz, d.qw, d.qx, d.qy, d.qz, roll, pitch, yaw,
+                              d.vx, d.vy, d.vz, d.wx, d.wy, d.wz, n[0], n[1], n[2], n[3]};
+            if (noisy) sensor_noise(a.dr, di, a.step0 + step, orow);
+            if (!oring) {
+                store_obs(a.obs, oslot, N, di, orow);
+            } else {
+                float *h = a.s.obs_hist;
+                if (otail) {
+#pragma unroll
+                    for (int k = 0; k < 20; ++k) h[((long long)osl * 20 + k) * N + di] = orow[k];
+                }
+                if (a.obs != nullptr) {
+                    const int S = a.n_obs_slots, n_st = a.n_steps;
+                    // this step returns a row entered before the launch
+                    const int back = min(odelay, ocnt0 + step);
+                    if (back > step && step >= n_st - S) {
+                        const int from = osl - back + (osl < back ? MD_DR_OBS_HIST : 0);
+                        float old[20];
+#pragma unroll
+                        for (int k = 0; k < 20; ++k) old[k] = h[((long long)from * 20 + k) * N + di];
+                        store_obs(a.obs, oslot, N, di, old);
+                    }
+                    // the steps that return this row: step + delay, and every
+                    // step up to it when the ring starts empty here
+                    const int k_hi = min(step + odelay, n_st - 1);
+                    const int k_lo = max((ocnt0 == 0 && step == 0) ? 0 : step + odelay, n_st - S);
+                    for (int kk = k_lo; kk <= k_hi; ++kk) {
+                        int sl = oslot + (kk - step);
+                        while (sl >= S) sl -= S;
+                        store_obs_lane(a.obs, sl, N, di, orow);
+                    }
+                }
+            }
         }
         oslot = (oslot + 1 == a.n_obs_slots) ? 0 : oslot + 1;
+        if (oring) osl = (osl + 1 == MD_DR_OBS_HIST) ? 0 : osl + 1;
     }
 
     if (writer) {
@@ -361,7 +447,20 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
             for (int k = 0; k < 4; ++k) a.s.ctl[k * N + di] = sp[k];
         if (rnd && ACT >= 1)
             for (int k = 0; k < 4; ++k) a.s.rpm_cmd[k * N + di] = cmdh[k];
-        if (ring) a.s.act_count[di] = issued;
+        if (ring) {
+            // enter this launch's last MD_DR_HIST action rows
+            const int j0 = max(a.n_steps - MD_DR_HIST, 0);
+            int sl = (int)((a.step0 + j0) % (long long)MD_DR_HIST);
+            for (int j = j0; j < a.n_steps; ++j) {
+                const float *ar = a.action + a.act_step_stride * j;
+                for (int k = 0; k < ROWS; ++k)
+                    a.s.act_hist[((long long)sl * ROWS + k) * N + di] =
+                        (ACT >= 1 && held) ? tgt_held[k] : ar[(long long)k * N + di];
+                sl = (sl + 1 == MD_DR_HIST) ? 0 : sl + 1;
+            }
+            a.s.act_count[di] = (int)min((long long)acnt0 + a.n_steps, (long long)MD_DR_HIST);
+        }
+        if (oring) a.s.obs_count[di] = (int)min((long long)ocnt0 + a.n_steps, (long long)MD_DR_OBS_HIST);
         if (windy && a.s.wind != nullptr)
             for (int k = 0; k < 5; ++k) a.s.wind[k * N + di] = ws[k];
     }

@@ -149,9 +149,11 @@ md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int ac
     }
     // scratch copies of the state: the caller's state is never advanced
     const bool dr = ctx->dr_on, ring = dr && ctx->dr.delay != nullptr;
-    const size_t nr[11] = {3, 4, 3, 3, 6, 4, 4, dr ? 4u : 0u,
+    const bool oring = dr && ctx->dr.obs_delay != nullptr;
+    const size_t nr[13] = {3, 4, 3, 3, 6, 4, 4, dr ? 4u : 0u,
                            ring ? (size_t)MD_DR_HIST * action_rows(ctx->act) : 0u, ring ? 1u : 0u,
-                           (ctx->wind.models && s->wind) ? 5u : 0u};
+                           (ctx->wind.models && s->wind) ? 5u : 0u,
+                           oring ? (size_t)MD_DR_OBS_HIST * 20u : 0u, oring ? 1u : 0u};
     size_t rows = 0;
     for (size_t r : nr) rows += r;
     float *scratch = nullptr, *work = nullptr;
@@ -162,13 +164,13 @@ md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int ac
         ctx->err = hip_msg("autotune scratch", e);
         return MD_E_OOM;
     }
-    // act_count is int32: copied bit for bit through a float-sized slot
-    const float *src[11] = {s->p, s->q, s->v, s->w, s->pid_int, s->rpm, s->ctl, s->rpm_cmd, s->act_hist,
-                            (const float *)s->act_count, s->wind};
+    // act_count and obs_count are int32: copied bit for bit through float-sized slots
+    const float *src[13] = {s->p, s->q, s->v, s->w, s->pid_int, s->rpm, s->ctl, s->rpm_cmd, s->act_hist,
+                            (const float *)s->act_count, s->wind, s->obs_hist, (const float *)s->obs_count};
     size_t o = 0;
     md_state ws{};
-    float *blk[11] = {};
-    for (int k = 0; k < 11 && e == hipSuccess; ++k) {
+    float *blk[13] = {};
+    for (int k = 0; k < 13 && e == hipSuccess; ++k) {
         if (nr[k] == 0) continue;
         if (src[k])
             e = hipMemcpyAsync(scratch + o, src[k], sizeof(float) * nr[k] * N, hipMemcpyDeviceToDevice, st);
@@ -188,6 +190,8 @@ md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int ac
     ws.act_hist = blk[8];
     ws.act_count = (int32_t *)blk[9];
     ws.wind = blk[10];
+    ws.obs_hist = blk[11];
+    ws.obs_count = (int32_t *)blk[12];
     hipEvent_t a = nullptr, b = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);

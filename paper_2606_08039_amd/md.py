@@ -51,7 +51,8 @@ class md_derived(ctypes.Structure):
 
 class md_state(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("p", "q", "v", "w", "pid_int", "rpm", "ctl",
-                                               "rpm_cmd", "act_hist", "act_count", "wind")]
+                                               "rpm_cmd", "act_hist", "act_count", "wind",
+                                               "obs_hist", "obs_count")]
 
 
 class md_wind(ctypes.Structure):
@@ -67,12 +68,14 @@ MD_WIND_COMBINED = 15
 
 
 class md_dr(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_void_p) for n in ("scale", "tau_mot", "delay")]
+    _fields_ = [(n, ctypes.c_void_p) for n in ("scale", "tau_mot", "delay")] + [
+        (n, ctypes.c_float) for n in ("noise_p", "noise_v", "noise_rpy", "noise_w")] + [
+        ("seed", ctypes.c_uint64), ("obs_delay", ctypes.c_void_p)]
 
 
 MD_DR_ROWS = ("m", "J", "L", "kf", "km", "drag", "C_gnd", "C1", "max_rpm", "g",
               "bias0", "bias1", "bias2", "bias3")
-MD_DR_NSCALE, MD_DR_HIST = 14, 32
+MD_DR_NSCALE, MD_DR_HIST, MD_DR_OBS_HIST = 14, 32, 8
 
 
 _lib = None
@@ -87,6 +90,11 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libmd.so is not built (%s); run `python -m paper_2606_08039_amd.build`"
                            % LIB_PATH)
+    # torch first: its HIP runtime and libmd's share one soname, so loading
+    # libmd first would hand torch a runtime it was not built against (torch
+    # then finds no GPU); loaded after torch, libmd binds to torch's runtime
+    # and both use one set of devices, streams and allocations.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     sig = {
         "md_version": (ctypes.c_char_p, []),
@@ -215,16 +223,19 @@ class DeviceState:
 
     def add_dr_blocks(self, act_type, s=None):
         """The blocks the domain-randomised step needs: the held controller
-        command (from s["rpm_cmd"], else the rotor speeds), the action ring
-        and its fill counts (from s, else empty)."""
+        command (from s["rpm_cmd"], else the rotor speeds), the action and
+        sensor latency rings and their fill counts (from s, else empty)."""
         import torch
         rows = ACTION_ROWS[act_type]
         dev = self.t["p"].device
         self.t["rpm_cmd"] = self.t["rpm"].clone()
         self.t["act_hist"] = torch.zeros((MD_DR_HIST, rows, self.n), dtype=torch.float32, device=dev)
         self.t["act_count"] = torch.zeros(self.n, dtype=torch.int32, device=dev)
+        self.t["obs_hist"] = torch.zeros((MD_DR_OBS_HIST, 20, self.n), dtype=torch.float32, device=dev)
+        self.t["obs_count"] = torch.zeros(self.n, dtype=torch.int32, device=dev)
         if s is not None:
-            for k, dt in (("rpm_cmd", np.float32), ("act_hist", np.float32), ("act_count", np.int32)):
+            for k, dt in (("rpm_cmd", np.float32), ("act_hist", np.float32), ("act_count", np.int32),
+                          ("obs_hist", np.float32), ("obs_count", np.int32)):
                 if k in s:
                     self.t[k].copy_(torch.from_numpy(np.ascontiguousarray(s[k], dtype=dt)))
         return self
@@ -251,7 +262,7 @@ class DeviceState:
     def as_md_state(self):
         return md_state(*[self.t[k].data_ptr() if k in self.t else None
                           for k in ("p", "q", "v", "w", "pid_int", "rpm", "ctl", "rpm_cmd", "act_hist",
-                                    "act_count", "wind")])
+                                    "act_count", "wind", "obs_hist", "obs_count")])
 
 
 # ------------------------------------------------------------------ surrogate network
@@ -390,10 +401,14 @@ def md_judge_reset(ctx):
 
 # ------------------------------------------------------------------ domain randomisation
 
-def md_set_domain_randomization(ctx, scale=None, tau_mot=None, delay=None):
+def md_set_domain_randomization(ctx, scale=None, tau_mot=None, delay=None, noise=(0.0, 0.0, 0.0, 0.0),
+                                seed=0, obs_delay=None):
     """scale: CUDA float32 [MD_DR_NSCALE][N]; tau_mot: float32 [N] or None;
-    delay: int32 [N] or None.  scale None turns randomisation off.  The
-    tensors must stay alive while the context uses them."""
+    delay: int32 [N] or None; noise: sensor noise sigmas (position,
+    velocity, roll/pitch/yaw, body rates); seed: Philox key of the noise;
+    obs_delay: int32 [N] sensor latency in steps, or None.  scale None turns
+    randomisation off.  The tensors must stay alive while the context uses
+    them."""
     if scale is None:
         check(lib().md_set_domain_randomization(ctx, None), ctx)
         return
@@ -401,8 +416,11 @@ def md_set_domain_randomization(ctx, scale=None, tau_mot=None, delay=None):
     assert scale.dtype == torch.float32 and scale.is_contiguous()
     assert tau_mot is None or (tau_mot.dtype == torch.float32 and tau_mot.is_contiguous())
     assert delay is None or (delay.dtype == torch.int32 and delay.is_contiguous())
+    assert obs_delay is None or (obs_delay.dtype == torch.int32 and obs_delay.is_contiguous())
+    nz = [float(x) for x in noise]
     d = md_dr(scale.data_ptr(), tau_mot.data_ptr() if tau_mot is not None else None,
-              delay.data_ptr() if delay is not None else None)
+              delay.data_ptr() if delay is not None else None, nz[0], nz[1], nz[2], nz[3], int(seed),
+              obs_delay.data_ptr() if obs_delay is not None else None)
     check(lib().md_set_domain_randomization(ctx, ctypes.byref(d)), ctx)
 
 

@@ -234,14 +234,23 @@ DR_HALF_WIDTH = {"m": 0.2, "J": 0.2, "L": 0.02, "kf": 0.15, "km": 0.15, "drag": 
                  "C1": 0.3, "max_rpm": 0.05, "g": 0.02, "bias": 0.05}
 DR_TAU_MOT = (0.005, 0.050)   # s
 DR_LATENCY = (0.0, 0.050)     # s
+# sensors: noise sigmas of position (m), velocity (m/s), roll/pitch/yaw
+# (rad), body rates (rad/s), and the sensor latency range (s)
+DR_NOISE = (0.01, 0.05, float(np.radians(1.0)), 0.05)
+DR_SENSOR_LATENCY = (0.0, 0.020)
 
 
-def domain_randomization(w, seed, lag=True, latency=True):
+def domain_randomization(w, seed, lag=True, latency=True, sensors=True, latency_per="drone"):
     """Seeded draws for the workload's drones: one vehicle per drone (mass,
     inertia, arm, kf, km, drag, C_gnd, C1, MAX_RPM, four motor biases, motor
     time constant, action latency rounded to whole steps), gravity per
-    environment.  Returns float32 scale [14][N], float32 tau_mot [N] (None
-    without lag) and int32 delay [N] (None without latency)."""
+    environment, and with sensors the table's noise levels, a noise seed and
+    a sensor latency per drone rounded to whole steps.  Returns float32 scale
+    [14][N], float32 tau_mot [N] (None without lag), int32 delay [N] (None
+    without latency), noise (4 sigmas, zeros without sensors), seed and int32
+    obs_delay [N] (None without sensors).  latency_per "env" draws the two
+    latencies once per environment (one sensing and radio pipeline per
+    arena) instead of once per drone."""
     rng = np.random.default_rng(seed)
     off = np.asarray(w["env_offsets"], dtype=np.int64)
     n = int(off[-1])
@@ -255,5 +264,19 @@ def domain_randomization(w, seed, lag=True, latency=True):
     a = DR_HALF_WIDTH["bias"]
     scale[10:14] = rng.uniform(1 - a, 1 + a, size=(4, n))
     tau = rng.uniform(*DR_TAU_MOT, size=n).astype(np.float32) if lag else None
-    delay = np.rint(rng.uniform(*DR_LATENCY, size=n) / w["dt"]).astype(np.int32) if latency else None
-    return dict(scale=scale.astype(np.float32), tau_mot=tau, delay=delay)
+    assert latency_per in ("drone", "env")
+    per_env = latency_per == "env"
+
+    def steps(rng_range):
+        x = rng.uniform(*rng_range, size=len(off) - 1 if per_env else n)
+        x = np.repeat(x, np.diff(off)) if per_env else x
+        return np.rint(x / w["dt"]).astype(np.int32)
+
+    delay = steps(DR_LATENCY) if latency else None
+    noise, nseed, obs_delay = (0.0, 0.0, 0.0, 0.0), 0, None
+    if sensors:
+        noise = DR_NOISE
+        nseed = int(rng.integers(0, 2 ** 63))
+        obs_delay = steps(DR_SENSOR_LATENCY)
+    return dict(scale=scale.astype(np.float32), tau_mot=tau, delay=delay, noise=noise, seed=nseed,
+                obs_delay=obs_delay)

@@ -51,9 +51,11 @@ class GpuRun:
         if w.get("dr") is not None:
             dr = w["dr"]
             self.dr = {k: (torch.from_numpy(dr[k]).cuda() if dr.get(k) is not None else None)
-                       for k in ("scale", "tau_mot", "delay")}
+                       for k in ("scale", "tau_mot", "delay", "obs_delay")}
             self.state.add_dr_blocks(ACT[w["act_type"]], w["state"])
-            md.md_set_domain_randomization(self.ctx, self.dr["scale"], self.dr["tau_mot"], self.dr["delay"])
+            md.md_set_domain_randomization(self.ctx, self.dr["scale"], self.dr["tau_mot"], self.dr["delay"],
+                                           noise=dr.get("noise", (0.0, 0.0, 0.0, 0.0)), seed=dr.get("seed", 0),
+                                           obs_delay=self.dr["obs_delay"])
         if w.get("wind") is not None:
             self.state.add_wind_block(w["state"])
             md.md_set_wind(self.ctx, **w["wind"])
@@ -83,7 +85,7 @@ class GpuRun:
 
 
 def to_oracle_state(s32):
-    return {k: np.ascontiguousarray(v, dtype=np.int32 if k == "act_count" else np.float64)
+    return {k: np.ascontiguousarray(v, dtype=np.int32 if k in ("act_count", "obs_count") else np.float64)
             for k, v in s32.items()}
 
 
@@ -117,8 +119,14 @@ def oracle_one_step(w, s32, k, env_subset=None, mask=None, n_steps=1, obs_slots=
     dr = None
     if w.get("dr") is not None:
         pick = (lambda v: v) if idx is None else (lambda v: v[..., idx])
-        dr = {kk: (np.ascontiguousarray(pick(v)) if v is not None else None) for kk, v in w["dr"].items()}
+        dr = {kk: (np.ascontiguousarray(pick(v)) if isinstance(v, np.ndarray) else v)
+              for kk, v in w["dr"].items()}
         dr["scale"] = dr["scale"].astype(np.float64)
+        # the GPU takes float32 noise levels; the draws of a sub-batch keep
+        # the drones' indices in the whole batch
+        dr["noise"] = tuple(float(np.float32(x)) for x in dr.get("noise", (0.0, 0.0, 0.0, 0.0)))
+        if idx is not None:
+            dr["drone_id"] = idx.astype(np.int32)
         if dr.get("tau_mot") is not None:
             dr["tau_mot"] = dr["tau_mot"].astype(np.float64)
     wind = None
@@ -132,9 +140,7 @@ def oracle_one_step(w, s32, k, env_subset=None, mask=None, n_steps=1, obs_slots=
                 wk[key] = f32(wk[key])
         if "v_mean" in wk:
             wk["v_mean"] = tuple(f32(x) for x in wk["v_mean"])
-        wind = orc.make_wind(**wk)
-    if wind is not None and idx is not None:
-        raise ValueError("wind parity runs on whole workloads (the draws are keyed by drone index)")
+        wind = orc.make_wind(**wk, drone_id=idx.astype(np.int32) if idx is not None else None)
     obs = orc.step(P, w["dt"], w["aero_mask"] if mask is None else mask,
                    ORC_ACT[w["act_type"]], w["ctrl_decim"],
                    sub_off, s, np.ascontiguousarray(a, dtype=np.float64), w["action_per_step"],

@@ -1,9 +1,11 @@
 """GPU parity of the domain-randomised step (md_set_domain_randomization)
 against the oracle's orc_step_dr: per-step criterion from GPU snapshots on
 the formation (sampled environments, both neighbour sweeps), the ragged grid
-with per-step rotor-speed actions, and every controller; chunked launches
-equal one launch bitwise (the latency ring carries across launches);
-the autotuner leaves the caller's state untouched; error paths."""
+with per-step rotor-speed actions, and every controller, each with the
+table's sensor noise and sensor latency on the returned rows; chunked
+launches equal one launch bitwise (the action and sensor rings carry across
+launches); sensor noise statistics on the GPU's own draws; the autotuner
+leaves the caller's state untouched; error paths."""
 import numpy as np
 import pytest
 
@@ -36,9 +38,14 @@ def _parity(w, ks, env_subset=None, cfg=None, blocks=pu.BLOCKS):
             a = gobs[0] if idx is None else gobs[0][:, idx]
             sc = np.maximum(np.max(np.abs(robs[0]), axis=0), 1.0)
             assert np.max(np.max(np.abs(a - robs[0]), axis=0) / sc) <= pu.TOL, k
-            if "act_count" in s1:
-                got = s1["act_count"] if idx is None else s1["act_count"][idx]
-                np.testing.assert_array_equal(got, ref["act_count"])
+            for cnt in ("act_count", "obs_count"):
+                if cnt in s1:
+                    got = s1[cnt] if idx is None else s1[cnt][idx]
+                    np.testing.assert_array_equal(got, ref[cnt])
+            if "obs_hist" in s1:
+                gh = s1["obs_hist"] if idx is None else s1["obs_hist"][..., idx]
+                sch = np.maximum(np.max(np.abs(ref["obs_hist"]), axis=(0, 1)), 1.0)
+                assert np.max(np.max(np.abs(gh - ref["obs_hist"]), axis=(0, 1)) / sch) <= pu.TOL, k
             worst = {kk: max(worst.get(kk, 0.0), v) for kk, v in e.items()}
     finally:
         g.close()
@@ -120,6 +127,86 @@ def test_error_paths():
         md.md_step(ctx, st, act, False, None, 0, 1, 0)
     st.add_dr_blocks(md.MD_ACT_PID)
     md.md_step(ctx, st, act, False, None, 0, 1, 0)
+    with pytest.raises(md.MdError):
+        md.md_set_domain_randomization(ctx, sc, noise=(0.01, -0.05, 0.0, 0.0))
+    with pytest.raises(md.MdError):
+        md.md_set_domain_randomization(ctx, sc, noise=(float("nan"), 0.0, 0.0, 0.0))
+    od = torch.zeros(4, dtype=torch.int32, device="cuda")
+    md.md_set_domain_randomization(ctx, sc, obs_delay=od)
+    st2 = md.DeviceState(4)
+    st2.add_dr_blocks(md.MD_ACT_PID)
+    del st2.t["obs_hist"]
+    with pytest.raises(md.MdError):
+        md.md_step(ctx, st2, act, False, None, 0, 1, 0)
     md.md_set_domain_randomization(ctx, None)
     md.md_destroy(ctx)
     torch.cuda.synchronize()
+
+
+def test_sensor_noise_statistics_and_latency_on_the_gpu():
+    """The GPU's own noise draws: rows minus the noise-free rows of the same
+    launch have zero mean and the table's standard deviations; quaternion and
+    rotor rows are exact; the delayed rows repeat earlier rows."""
+    # ground effect and drag only: the grid's same-layer drones make the
+    # literal downwash diverge within a few steps, and values of 1e10 m leave
+    # no bits for centimetre noise
+    w = wl.ragged_grid(pu.hover_rpm(), n_envs=2048, n_steps=12, seed=3)
+    dr = wl.domain_randomization(w, 55)
+    clean = pu.GpuRun(dict(w, dr=dict(dr, noise=(0.0, 0.0, 0.0, 0.0), obs_delay=None)), mask=3)
+    noisy = pu.GpuRun(dict(w, dr=dict(dr, obs_delay=None)), mask=3)
+    late = pu.GpuRun(dict(w, dr=dict(dr, noise=(0.0, 0.0, 0.0, 0.0))), mask=3)
+    try:
+        oc = clean.run(12, obs_slots=12)
+        on = noisy.run(12, obs_slots=12)
+        ol = late.run(12, obs_slots=12)
+        snaps = [g.snapshot() for g in (clean, noisy, late)]
+    finally:
+        for g in (clean, noisy, late):
+            g.close()
+    for k in ("p", "q", "v", "w", "rpm"):  # the sensors never feed back into the state
+        np.testing.assert_array_equal(snaps[1][k], snaps[0][k])
+        np.testing.assert_array_equal(snaps[2][k], snaps[0][k])
+    d = (on - oc).astype(np.float64)
+    np.testing.assert_array_equal(d[:, 3:7], 0)
+    np.testing.assert_array_equal(d[:, 16:20], 0)
+    for rows, sd in ((slice(0, 3), dr["noise"][0]), (slice(10, 13), dr["noise"][1]),
+                     (slice(7, 10), dr["noise"][2]), (slice(13, 16), dr["noise"][3])):
+        z = (d[:, rows] / np.float32(sd)).ravel()
+        assert np.isfinite(z).all()
+        assert abs(z.mean()) < 0.01 and abs(z.std() - 1) < 0.01, (rows, z.mean(), z.std())
+    K = 12
+    for i in np.random.default_rng(0).choice(oc.shape[2], 64, replace=False):
+        src = np.maximum(np.arange(K) - int(dr["obs_delay"][i]), 0)
+        np.testing.assert_array_equal(ol[:, :, i], oc[src][:, :, i])
+
+
+@pytest.mark.parametrize("kind,per", [("rpm_per_step", "drone"), ("pid_held", "drone"), ("pid_held", "env")])
+def test_latency_rings_across_launches_and_slot_counts(kind, per):
+    """Launches of several lengths, each returning fewer or more observation
+    slots than steps, give bitwise the rows and state of one long launch:
+    the delayed actions and rows reach back across launch boundaries through
+    the rings and each slot holds the row of the last step mapped to it."""
+    if kind == "rpm_per_step":
+        w = wl.ragged_grid(pu.hover_rpm(), n_envs=256, n_steps=40, seed=8)
+    else:
+        w = wl.subset_envs(wl.formation(n_envs=8192, n_steps=40, seed=4), 64)
+    w = dict(w, dr=wl.domain_randomization(w, 56, latency_per=per))
+    assert w["dr"]["obs_delay"].max() >= 3 and w["dr"]["delay"].max() >= 8
+    a = pu.GpuRun(w, mask=3)
+    b = pu.GpuRun(w, mask=3)
+    try:
+        ref = a.run(40, obs_slots=40)
+        start = 0
+        for n, S in ((3, 2), (9, 9), (1, 1), (20, 7), (7, 12)):
+            got = b.run(n, obs_slots=S)
+            for s in range(S):
+                ks = [k for k in range(max(n - S, 0), n) if k % S == s]
+                want = ref[start + ks[0]] if ks else np.zeros_like(got[s])
+                np.testing.assert_array_equal(got[s], want, err_msg="launch at %d, %d steps, slot %d" % (start, n, s))
+            start += n
+        sa, sb = a.snapshot(), b.snapshot()
+        for k in sa:
+            np.testing.assert_array_equal(sb[k], sa[k], err_msg=k)
+    finally:
+        a.close()
+        b.close()

@@ -268,3 +268,38 @@ def test_sensor_ring_advances_on_steps_without_observations():
     orc.step(P, H, 0, orc.ACT_RPM, 1, [0, 1, 2, 3], b, act[:6], True, 6, dr=dr)
     last = orc.step(P, H, 0, orc.ACT_RPM, 1, [0, 1, 2, 3], b, act[6:], True, K - 6, step0=6, n_obs_slots=1, dr=dr)
     np.testing.assert_array_equal(last[-1], every[-1])
+
+
+def test_drone_id_keeps_the_draws_of_a_sub_batch():
+    """A sub-batch run with each drone's Philox counter word set to its index
+    in the whole batch reproduces that batch's rows exactly (sensor noise and
+    wind draws are keyed by the counter word, environments are independent)."""
+    P = orc.cf2x()
+    h = orc.derive(P).hover_rpm
+    off = np.array([0, 2, 5, 6], dtype=np.int32)
+    n, K = 6, 9
+    rng = np.random.default_rng(46)
+    base = _state(n)
+    base["p"][:2] += rng.uniform(-0.2, 0.2, (2, n))
+    base["p"][2] += np.array([0.0, 0.1, 0.0, 0.25, 0.5, 0.0])
+    act = h * (1 + rng.uniform(-0.05, 0.05, size=(K, 4, n)))
+    wkw = dict(models=orc.WIND_DRYDEN | orc.WIND_GUST, dryden_sigma=0.5, dryden_airspeed=2.0,
+               gust_prob=0.3, gust_amp=0.02, seed=12)
+
+    def run(idx, o):
+        dr = dict(_ones(n), noise=(0.01, 0.05, 0.02, 0.05), seed=3,
+                  obs_delay=np.array([0, 1, 2, 3, 4, 5], dtype=np.int32))
+        dr = {k: (v[..., idx] if isinstance(v, np.ndarray) else v) for k, v in dr.items()}
+        dr["drone_id"] = idx
+        s = orc.wind_state(orc.dr_state({k: v[..., idx].copy() for k, v in base.items()}, orc.ACT_RPM))
+        obs = orc.step(P, H, 7, orc.ACT_RPM, 1, o, s, act[:, :, idx], True, K, n_obs_slots=K, dr=dr,
+                       wind=orc.make_wind(**wkw, drone_id=idx))
+        return s, obs
+
+    full_s, full_o = run(np.arange(n, dtype=np.int32), off)
+    idx = np.arange(2, 5, dtype=np.int32)
+    sub_s, sub_o = run(idx, np.array([0, 3], dtype=np.int32))
+    np.testing.assert_array_equal(sub_o, full_o[:, :, idx])
+    for k in ("p", "v", "q", "w", "wind"):
+        np.testing.assert_array_equal(sub_s[k], full_s[k][..., idx])
+    assert np.abs(full_s["wind"][0]).max() > 0
