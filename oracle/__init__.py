@@ -68,7 +68,7 @@ class _CWind(ctypes.Structure):
                 ("gust_duration", ctypes.c_double), ("gust_amp", ctypes.c_double),
                 ("dryden_sigma", ctypes.c_double), ("dryden_airspeed", ctypes.c_double),
                 ("sin_amp", ctypes.c_double), ("sin_omega", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("drone_id", ctypes.POINTER(ctypes.c_int32))]
+                ("drone_id", ctypes.POINTER(ctypes.c_int32)), ("v_mean_drone", ctypes.POINTER(ctypes.c_double))]
 
 
 WIND_CONSTANT, WIND_GUST, WIND_DRYDEN, WIND_SINUSOIDAL = 1, 2, 4, 8
@@ -80,7 +80,7 @@ class _CDr(ctypes.Structure):
                 ("delay", ctypes.POINTER(ctypes.c_int32)), ("noise_p", ctypes.c_double),
                 ("noise_v", ctypes.c_double), ("noise_rpy", ctypes.c_double), ("noise_w", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("obs_delay", ctypes.POINTER(ctypes.c_int32)),
-                ("drone_id", ctypes.POINTER(ctypes.c_int32))]
+                ("drone_id", ctypes.POINTER(ctypes.c_int32)), ("obs_bias", ctypes.POINTER(ctypes.c_double))]
 
 
 # Domain randomisation factor rows (orc_dr.scale) and the latency ring depth.
@@ -361,14 +361,17 @@ def philox4x32(ctr, key):
 
 def make_wind(models, v_mean=(0.0, 0.0, 0.0), rho=1.225, cd_area=0.01, gust_prob=0.0, gust_duration=0.5,
               gust_amp=0.0, dryden_sigma=0.0, dryden_airspeed=1.0, sin_amp=0.0, sin_omega=0.0, seed=0,
-              drone_id=None):
+              drone_id=None, v_mean_drone=None):
     """drone_id: optional int32 [N], the first Philox counter word of each
-    drone (default its index), so that a sub-batch keeps its drones' draws."""
+    drone (default its index), so that a sub-batch keeps its drones' draws;
+    v_mean_drone: optional [3][N] per-drone mean wind (default v_mean)."""
     ids = np.ascontiguousarray(drone_id, dtype=np.int32) if drone_id is not None else None
+    vmd = np.ascontiguousarray(v_mean_drone, dtype=np.float64) if v_mean_drone is not None else None
     w = _CWind(int(models), (ctypes.c_double * 3)(*v_mean), rho, cd_area, gust_prob, gust_duration,
                gust_amp, dryden_sigma, dryden_airspeed, sin_amp, sin_omega, int(seed),
-               ids.ctypes.data_as(_I32) if ids is not None else None)
-    w._keep = ids
+               ids.ctypes.data_as(_I32) if ids is not None else None,
+               vmd.ctypes.data_as(_D) if vmd is not None else None)
+    w._keep = (ids, vmd)
     return w
 
 
@@ -380,8 +383,9 @@ def step(P, dt, aero_mask, act_type, ctrl_decim, env_offsets, state, action,
     observation array [slots][20][N] or None.  dr: None, or a dict with
     "scale" [len(DR_ROWS)][N] and optional "tau_mot" [N] (s), "delay" [N]
     (int steps), "noise" (sigma_p, sigma_v, sigma_rpy, sigma_w), "seed",
-    "obs_delay" [N] (int steps) and "drone_id" [N] (Philox counter word) for
-    the domain-randomised Euler step."""
+    "obs_delay" [N] (int steps), "drone_id" [N] (Philox counter word) and
+    "obs_bias" [12][N] (sticky bias on the p, v, rpy, w rows) for the
+    domain-randomised Euler step."""
     off = np.ascontiguousarray(np.asarray(env_offsets, dtype=np.int32))
     n_envs = len(off) - 1
     n = int(off[-1])
@@ -404,11 +408,14 @@ def step(P, dt, aero_mask, act_type, ctrl_decim, env_offsets, state, action,
             dl = np.ascontiguousarray(dr["delay"], dtype=np.int32) if dr.get("delay") is not None else None
             od = np.ascontiguousarray(dr["obs_delay"], dtype=np.int32) if dr.get("obs_delay") is not None else None
             ids = np.ascontiguousarray(dr["drone_id"], dtype=np.int32) if dr.get("drone_id") is not None else None
+            bias = np.ascontiguousarray(dr["obs_bias"], dtype=np.float64) if dr.get("obs_bias") is not None else None
+            assert bias is None or bias.shape == (12, n), bias.shape
             nz = tuple(float(x) for x in (dr.get("noise") or (0.0, 0.0, 0.0, 0.0)))
             cdr = _CDr(_dp(sc), _dp(tau) if tau is not None else None,
                        dl.ctypes.data_as(_I32) if dl is not None else None, nz[0], nz[1], nz[2], nz[3],
                        int(dr.get("seed", 0)), od.ctypes.data_as(_I32) if od is not None else None,
-                       ids.ctypes.data_as(_I32) if ids is not None else None)
+                       ids.ctypes.data_as(_I32) if ids is not None else None,
+                       _dp(bias) if bias is not None else None)
         rc = _load().orc_step_disturbed(*args, ctypes.byref(cdr) if cdr is not None else None,
                                         ctypes.byref(wind) if wind is not None else None)
     else:

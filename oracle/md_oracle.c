@@ -509,13 +509,15 @@ static void wind_words(const orc_wind *W, int32_t i, int64_t t, uint32_t stream,
  *              sin(pi k / n_g) at its k-th step;
  *   SINUSOIDAL F = A [sin w tau, cos w tau, 0.3 sin 2 w tau], tau = t dt;
  *   COMBINED   the sum of the selected models. */
-static void wind_force(const orc_wind *W, double dt, int64_t t, int32_t i, const double p[3],
+static void wind_force(const orc_wind *W, double dt, int64_t t, int32_t i, int32_t li, const double p[3],
                        const double v[3], double *ws, int N, double F[3])
 {
     F[0] = F[1] = F[2] = 0.0;
     const double k = 0.5 * W->rho * W->cd_area;
     if (W->models & ORC_WIND_CONSTANT) {
-        const double u[3] = {W->v_mean[0] - v[0], W->v_mean[1] - v[1], W->v_mean[2] - v[2]};
+        double vm[3];
+        for (int c = 0; c < 3; ++c) vm[c] = W->v_mean_drone ? W->v_mean_drone[(size_t)c * N + li] : W->v_mean[c];
+        const double u[3] = {vm[0] - v[0], vm[1] - v[1], vm[2] - v[2]};
         const double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
         for (int c = 0; c < 3; ++c) F[c] += k * un * u[c];
     }
@@ -567,7 +569,9 @@ static void wind_force(const orc_wind *W, double dt, int64_t t, int32_t i, const
 }
 
 /* The KIN row the sensors deliver under domain randomisation (Table
- * "Recommended domain-randomization ranges", sensors): per-step Gaussian
+ * "Recommended domain-randomization ranges", sensors, and the sticky
+ * per-episode observation bias recommended beside it): the drone's constant
+ * bias, then per-step Gaussian
  * noise added to position, roll/pitch/yaw, velocity and body rates (the
  * quaternion and rotor-speed rows stay exact), twelve normals from Philox
  * streams 2-4 of (drone, global step) by Box-Muller; then the sensor latency:
@@ -578,6 +582,10 @@ static void wind_force(const orc_wind *W, double dt, int64_t t, int32_t i, const
  * is advanced every step whether or not observations are requested. */
 static void sensor_row(const orc_dr *dr, int64_t t, int32_t i, int N, orc_state *s, double row[20])
 {
+    if (dr->obs_bias) {
+        static const int rows[12] = {0, 1, 2, 10, 11, 12, 7, 8, 9, 13, 14, 15};
+        for (int b = 0; b < 12; ++b) row[rows[b]] += dr->obs_bias[(size_t)b * N + i];
+    }
     if (dr->noise_p > 0.0 || dr->noise_v > 0.0 || dr->noise_rpy > 0.0 || dr->noise_w > 0.0) {
         const orc_wind key = {.seed = dr->seed};
         double xi[12];
@@ -756,7 +764,7 @@ static int step_impl(const orc_params *P, double dt, uint32_t aero_mask, int act
                 }
                 if (wind && wind->models) {
                     double Fwind[3];
-                    wind_force(wind, dt, step0 + k, wind->drone_id ? wind->drone_id[i] : i, p, v,
+                    wind_force(wind, dt, step0 + k, wind->drone_id ? wind->drone_id[i] : i, i, p, v,
                                s->wind ? s->wind + i : NULL, N, Fwind);
                     for (int c = 0; c < 3; ++c) Fw[c] += Fwind[c];
                 }
@@ -768,7 +776,7 @@ static int step_impl(const orc_params *P, double dt, uint32_t aero_mask, int act
                 }
                 for (int c = 0; c < 4; ++c) s->q[c * N + i] = q[c];
 
-                const int sensors = dr && (dr->obs_delay || dr->noise_p > 0.0 || dr->noise_v > 0.0 ||
+                const int sensors = dr && (dr->obs_delay || dr->obs_bias || dr->noise_p > 0.0 || dr->noise_v > 0.0 ||
                                             dr->noise_rpy > 0.0 || dr->noise_w > 0.0);
                 if ((obs && n_obs_slots > 0) || sensors) {
                     double rpy[3];

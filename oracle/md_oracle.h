@@ -87,6 +87,8 @@ typedef struct orc_wind {
     const int32_t *drone_id;  /* [n] first Philox counter word of each drone
                                * (nullable: the drone's index), so that a
                                * sub-batch keeps the streams of its drones */
+    const double *v_mean_drone; /* [3][n] per-drone mean wind (nullable:
+                                 * v_mean for every drone) */
 } orc_wind;
 void orc_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
@@ -111,6 +113,8 @@ typedef struct orc_dr {
     uint64_t seed;
     const int32_t *obs_delay;
     const int32_t *drone_id; /* [n] first Philox counter word (nullable: index) */
+    const double *obs_bias;  /* [12][n] sticky bias on the position, velocity,
+                              * roll/pitch/yaw and body-rate rows (nullable) */
 } orc_dr;
 
 enum { ORC_AERO_GND = 1, ORC_AERO_DRAG = 2, ORC_AERO_DW = 4, ORC_AERO_SURROGATE = 8 };

@@ -303,3 +303,30 @@ def test_drone_id_keeps_the_draws_of_a_sub_batch():
     for k in ("p", "v", "q", "w", "wind"):
         np.testing.assert_array_equal(sub_s[k], full_s[k][..., idx])
     assert np.abs(full_s["wind"][0]).max() > 0
+
+
+def test_sticky_observation_bias_is_added_to_the_delayed_rows():
+    """A per-drone constant bias on the p, v, rpy, w rows (the sticky
+    per-episode observation bias recommended with the table) shifts every
+    returned row by exactly that bias, delayed or not, and leaves the state
+    and the quaternion and rotor rows alone."""
+    P = orc.cf2x()
+    h = orc.derive(P).hover_rpm
+    n, K = 4, 10
+    rng = np.random.default_rng(47)
+    act = h * (1 + rng.uniform(-0.05, 0.05, size=(K, 4, n)))
+    bias = rng.normal(0, 0.05, (12, n))
+    rows = [0, 1, 2, 10, 11, 12, 7, 8, 9, 13, 14, 15]
+    for od in (None, np.array([0, 1, 3, 6], dtype=np.int32)):
+        plain_s = orc.dr_state(_state(n), orc.ACT_RPM)
+        plain = orc.step(P, H, 0, orc.ACT_RPM, 1, np.arange(n + 1), plain_s, act, True, K, n_obs_slots=K,
+                         dr=dict(_ones(n), obs_delay=od))
+        s = orc.dr_state(_state(n), orc.ACT_RPM)
+        got = orc.step(P, H, 0, orc.ACT_RPM, 1, np.arange(n + 1), s, act, True, K, n_obs_slots=K,
+                       dr=dict(_ones(n), obs_delay=od, obs_bias=bias))
+        want = plain.copy()
+        for b, r in enumerate(rows):
+            want[:, r] += bias[b]
+        np.testing.assert_array_equal(got, want)
+        for k in ("p", "v", "q", "w", "rpm"):
+            np.testing.assert_array_equal(s[k], plain_s[k])

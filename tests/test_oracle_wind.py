@@ -126,3 +126,31 @@ def test_combined_is_the_sum_of_the_models():
     np.testing.assert_allclose(dv[15], dv[1] + dv[2] + dv[4] + dv[8], rtol=1e-12, atol=1e-18)
     for m in (1, 4, 8):
         assert np.all(np.linalg.norm(dv[m], axis=0) > 1e-9), m
+
+
+def test_per_drone_mean_wind_equals_separate_runs():
+    """Per-drone mean winds (the table's per-episode wind magnitude) give
+    each drone exactly the trajectory of a run with that drone's mean wind
+    for everyone; the quadratic drag still drives each one to its own
+    terminal velocity, the local mean wind."""
+    rng = np.random.default_rng(9)
+    n = 5
+    vm = rng.uniform(-1.0, 1.0, (3, n))
+    vm[2] *= 0.2
+    kw = dict(models=orc.WIND_CONSTANT | orc.WIND_DRYDEN, dryden_sigma=0.3, dryden_airspeed=1.0, seed=4)
+    _, s_all, _ = _hover_run(n, orc.make_wind(**kw, v_mean_drone=vm), 30)
+    for i in range(n):
+        # drone i alone keeps its own counter word through drone_id
+        _, s_i, _ = _hover_run(1, orc.make_wind(**kw, v_mean=tuple(vm[:, i]), drone_id=np.array([i])), 30)
+        for k in ("p", "v", "q", "w", "wind"):
+            np.testing.assert_array_equal(s_i[k][..., 0], s_all[k][..., i], err_msg=k)
+    # from rest the air speed u = v_mean - v keeps its direction and decays as
+    # u0 / (1 + k |u0| t / m), k = rho CdA / 2 (the ODE's solution; the
+    # semi-implicit steps follow it to O(dt))
+    P, s_long, _ = _hover_run(n, orc.make_wind(orc.WIND_CONSTANT, v_mean_drone=vm, cd_area=0.05), 2400)
+    u = vm - s_long["v"]
+    sp = np.linalg.norm(vm, axis=0)
+    k = 0.5 * 1.225 * 0.05
+    want = sp / (1 + k * sp * 2400 * H / P.m)
+    np.testing.assert_allclose(np.linalg.norm(u, axis=0), want, rtol=5e-3)
+    np.testing.assert_allclose(np.sum(u * vm, axis=0) / (np.linalg.norm(u, axis=0) * sp), 1.0, atol=1e-9)
