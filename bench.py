@@ -182,9 +182,11 @@ def timed_rollouts(args, w, p, with_obs, mask=None, integrator=None, surrogate_w
             state.add_dr_blocks(act)
             md.md_set_domain_randomization(ctx, dr_t["scale"], dr_t["tau_mot"], dr_t["delay"],
                                            noise=dr_t["noise"], seed=dr_t["seed"], obs_delay=dr_t["obs_delay"])
+        wind_t = None
         if wind is not None:
             state.add_wind_block()
-            md.md_set_wind(ctx, **wind)
+            wind_t = {k: (torch.from_numpy(v).cuda() if isinstance(v, np.ndarray) else v) for k, v in wind.items()}
+            md.md_set_wind(ctx, **wind_t)
         action = torch.from_numpy(np.ascontiguousarray(w["action"], dtype=np.float32)).cuda()
         obs = torch.empty((K, 20, n), dtype=torch.float32, device="cuda") if with_obs else None
         n_slots = K if with_obs else 0
@@ -263,18 +265,22 @@ def surrogate_leg(args, w, p, with_obs):
             "weights": os.path.relpath(path, ROOT)}
 
 
+DR_SEED = 50
+
+
 def dr_leg(args, w, p, with_obs):
-    """The same rollouts with per-drone domain randomisation (Table
-    "Recommended domain-randomization ranges": factors, motor lag, action
-    latency through the history ring, sensor noise and sensor latency)."""
+    """The same rollouts under every row of the domain-randomisation table
+    (Table "Recommended domain-randomization ranges"): initial-state draws,
+    per-drone factors, motor lag, action and sensor latency, sensor noise and
+    sticky bias, and COMBINED wind with a per-environment mean."""
     from paper_2606_08039_amd import workloads as wl
     n = int(w["env_offsets"][-1])
     # latencies drawn per environment (one sensing and radio pipeline per
     # arena); the per-vehicle draw is timed beside it
-    wall, kernel_ms, cfg, _, chk = timed_rollouts(args, w, p, with_obs,
-                                                  dr=wl.domain_randomization(w, 50, latency_per="env"))
-    wall_d, kernel_ms_d, cfg_d, _, _ = timed_rollouts(args, w, p, with_obs,
-                                                      dr=wl.domain_randomization(w, 50, latency_per="drone"))
+    we = wl.randomized(w, DR_SEED, latency_per="env")
+    wall, kernel_ms, cfg, _, chk = timed_rollouts(args, we, p, with_obs, dr=we["dr"], wind=we["wind"])
+    wd = wl.randomized(w, DR_SEED, latency_per="drone")
+    wall_d, kernel_ms_d, cfg_d, _, _ = timed_rollouts(args, wd, p, with_obs, dr=wd["dr"], wind=wd["wind"])
     return {"value": float(n) * w["n_steps"] * args.steps / wall, "unit": "drone-steps/s",
             "ms_per_step": wall / args.steps * 1e3, "kernel_ms_avg": float(np.mean(kernel_ms)),
             "launch_config": cfg, "final_state": chk, "latency_per": "environment",

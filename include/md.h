@@ -191,6 +191,10 @@ md_status md_step(md_ctx *ctx, const md_state *s, const float *d_action, int act
  *     24-bit uniforms of Philox4x32-10 blocks with counter (i, t low word,
  *     t high word, 2 + b), b = 0, 1, 2, key = seed (low word, high word), in
  *     the order p xyz, v xyz, rpy, w xyz;
+ *   obs_bias [12][n_drones] a constant per-drone bias (the sticky
+ *     per-episode observation bias recommended with the table) on the
+ *     position, velocity, roll/pitch/yaw and body-rate rows, in that order,
+ *     added before the noise, nullable;
  *   obs_delay [n_drones] sensor latency in steps, 0..MD_DR_OBS_HIST-1
  *     (clamped), nullable: the row returned at step k is the (noisy) row of
  *     step k - min(obs_delay, obs_count - 1), obs_count counting the rows of
@@ -227,6 +231,7 @@ typedef struct md_dr {
     float noise_p, noise_v, noise_rpy, noise_w;
     uint64_t seed;
     const int32_t *obs_delay;
+    const float *obs_bias;
 } md_dr;
 md_status md_set_domain_randomization(md_ctx *ctx, const md_dr *dr);
 
@@ -250,7 +255,10 @@ md_status md_set_domain_randomization(md_ctx *ctx, const md_dr *dr);
  * the gust trigger and heading; uniforms are the top 24 bits x 2^-24.  State:
  * md_state.wind [5][N] = Dryden x, y, z (m/s), gust step (-1 idle), gust
  * heading (rad), caller-owned, required with GUST or DRYDEN (start it at
- * 0, 0, 0, -1, 0).  NULL or models 0 turns wind off.  Errors:
+ * 0, 0, 0, -1, 0).  v_mean_drone: nullable device array [3][n_drones] of
+ * per-drone mean winds replacing v_mean (the per-episode wind magnitude of
+ * Table "Recommended domain-randomization ranges"), owned by the caller and
+ * read by every later md_step.  NULL or models 0 turns wind off.  Errors:
  * MD_E_INVALID_ARG for unknown bits or negative parameters, MD_E_UNSUPPORTED
  * with MD_AERO_SURROGATE or MD_INTEG_RK4. */
 #define MD_WIND_CONSTANT 1u
@@ -266,6 +274,7 @@ typedef struct md_wind {
     float dryden_sigma, dryden_airspeed;
     float sin_amp, sin_omega;
     uint64_t seed;
+    const float *v_mean_drone;
 } md_wind;
 md_status md_set_wind(md_ctx *ctx, const md_wind *w);
 

@@ -526,6 +526,7 @@ md_status md_set_domain_randomization(md_ctx *ctx, const md_dr *dr) {
     d.key0 = (uint32_t)(dr->seed & 0xffffffffull);
     d.key1 = (uint32_t)(dr->seed >> 32);
     d.obs_delay = dr->obs_delay;
+    d.obs_bias = dr->obs_bias;
     ctx->dr = d;
     ctx->dr_on = true;
     return MD_OK;
@@ -560,6 +561,7 @@ md_status md_set_wind(md_ctx *ctx, const md_wind *w) {
     a.sin_wdt = (double)w->sin_omega * (double)ctx->dt;
     a.key0 = (uint32_t)(w->seed & 0xffffffffull);
     a.key1 = (uint32_t)(w->seed >> 32);
+    a.vm_drone = w->v_mean_drone;
     ctx->wind = a;
     return MD_OK;
 }

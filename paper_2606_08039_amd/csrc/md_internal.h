@@ -50,6 +50,7 @@ struct WindArgs {
     float sin_amp;              // N
     double sin_wdt;             // sinusoid phase per step, omega dt (rad)
     uint32_t key0, key1;        // Philox key (seed)
+    const float *vm_drone;      // [3][N] per-drone mean wind or null
 };
 
 // Domain randomisation inputs (md_dr), device pointers.
@@ -61,6 +62,7 @@ struct DrPtr {
     bool noisy;              // any sigma > 0
     uint32_t key0, key1;     // Philox key of the sensor noise (seed)
     const int32_t *obs_delay;  // [N] or null
+    const float *obs_bias;     // [12][N] or null
 };
 
 // Action rows per action type (MD_ACT_DSL carries a feed-forward acceleration).

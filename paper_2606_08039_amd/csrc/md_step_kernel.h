@@ -85,13 +85,19 @@ __device__ __forceinline__ float unit24(uint32_t x) { return (float)(x >> 8) * (
 // World-frame wind force of one drone at global step t (pre-step state d);
 // ws = the drone's wind state (Dryden x, y, z; gust step, -1 idle; gust
 // heading), updated in place.  Models as documented at md_set_wind.
-__device__ __forceinline__ void wind_force(const WindArgs &W, float dt, long long t, int di, const Drone &d,
+__device__ __forceinline__ void wind_force(const WindArgs &W, float dt, long long t, int di, int N, const Drone &d,
                                            float ws[5], float &Fx, float &Fy, float &Fz) {
     Fx = Fy = Fz = 0.f;
     const uint32_t tl = (uint32_t)((unsigned long long)t & 0xffffffffull);
     const uint32_t th = (uint32_t)((unsigned long long)t >> 32);
     if (W.models & MD_WIND_CONSTANT) {
-        const float ux = W.vm[0] - d.vx, uy = W.vm[1] - d.vy, uz = W.vm[2] - d.vz;
+        float vx = W.vm[0], vy = W.vm[1], vz = W.vm[2];
+        if (W.vm_drone != nullptr) {
+            vx = W.vm_drone[di];
+            vy = W.vm_drone[N + di];
+            vz = W.vm_drone[2 * N + di];
+        }
+        const float ux = vx - d.vx, uy = vy - d.vy, uz = vz - d.vz;
         const float kn = W.kd * fsqrt(ux * ux + uy * uy + uz * uz);
         Fx += kn * ux;
         Fy += kn * uy;
@@ -375,7 +381,7 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         // ---- wind
         if (windy && valid) {
             float wx, wy, wz;
-            wind_force(a.wind, c.dt, a.step0 + step, di, d, ws, wx, wy, wz);
+            wind_force(a.wind, c.dt, a.step0 + step, di, N, d, ws, wx, wy, wz);
             Fx += wx;
             Fy += wy;
             Fz += wz;
@@ -389,6 +395,11 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
             euler_zyx(d, roll, pitch, yaw);
             float orow[20] = {d.px, d.py, d.pz, d.qw, d.qx, d.qy, d.qz, roll, pitch, yaw,
                               d.vx, d.vy, d.vz, d.wx, d.wy, d.wz, n[0], n[1], n[2], n[3]};
+            if (rnd && a.dr.obs_bias != nullptr) {
+                const float *ob = a.dr.obs_bias + di;
+#pragma unroll
+                for (int b = 0; b < 12; ++b) orow[b < 3 ? b : (b < 6 ? b + 7 : (b < 9 ? b + 1 : b + 4))] += ob[(long long)b * N];
+            }
             if (noisy) sensor_noise(a.dr, di, a.step0 + step, orow);
             if (!oring) {
                 store_obs(a.obs, oslot, N, di, orow);

@@ -60,7 +60,7 @@ class md_wind(ctypes.Structure):
                 ("cd_area", ctypes.c_float), ("gust_prob", ctypes.c_float), ("gust_duration", ctypes.c_float),
                 ("gust_amp", ctypes.c_float), ("dryden_sigma", ctypes.c_float),
                 ("dryden_airspeed", ctypes.c_float), ("sin_amp", ctypes.c_float), ("sin_omega", ctypes.c_float),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("v_mean_drone", ctypes.c_void_p)]
 
 
 MD_WIND_CONSTANT, MD_WIND_GUST, MD_WIND_DRYDEN, MD_WIND_SINUSOIDAL = 1, 2, 4, 8
@@ -70,7 +70,7 @@ MD_WIND_COMBINED = 15
 class md_dr(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("scale", "tau_mot", "delay")] + [
         (n, ctypes.c_float) for n in ("noise_p", "noise_v", "noise_rpy", "noise_w")] + [
-        ("seed", ctypes.c_uint64), ("obs_delay", ctypes.c_void_p)]
+        ("seed", ctypes.c_uint64), ("obs_delay", ctypes.c_void_p), ("obs_bias", ctypes.c_void_p)]
 
 
 MD_DR_ROWS = ("m", "J", "L", "kf", "km", "drag", "C_gnd", "C1", "max_rpm", "g",
@@ -402,11 +402,12 @@ def md_judge_reset(ctx):
 # ------------------------------------------------------------------ domain randomisation
 
 def md_set_domain_randomization(ctx, scale=None, tau_mot=None, delay=None, noise=(0.0, 0.0, 0.0, 0.0),
-                                seed=0, obs_delay=None):
+                                seed=0, obs_delay=None, obs_bias=None):
     """scale: CUDA float32 [MD_DR_NSCALE][N]; tau_mot: float32 [N] or None;
     delay: int32 [N] or None; noise: sensor noise sigmas (position,
     velocity, roll/pitch/yaw, body rates); seed: Philox key of the noise;
-    obs_delay: int32 [N] sensor latency in steps, or None.  scale None turns
+    obs_delay: int32 [N] sensor latency in steps, or None; obs_bias: float32
+    [12][N] sticky bias on the p, v, rpy, w rows, or None.  scale None turns
     randomisation off.  The tensors must stay alive while the context uses
     them."""
     if scale is None:
@@ -417,10 +418,12 @@ def md_set_domain_randomization(ctx, scale=None, tau_mot=None, delay=None, noise
     assert tau_mot is None or (tau_mot.dtype == torch.float32 and tau_mot.is_contiguous())
     assert delay is None or (delay.dtype == torch.int32 and delay.is_contiguous())
     assert obs_delay is None or (obs_delay.dtype == torch.int32 and obs_delay.is_contiguous())
+    assert obs_bias is None or (obs_bias.dtype == torch.float32 and obs_bias.is_contiguous())
     nz = [float(x) for x in noise]
     d = md_dr(scale.data_ptr(), tau_mot.data_ptr() if tau_mot is not None else None,
               delay.data_ptr() if delay is not None else None, nz[0], nz[1], nz[2], nz[3], int(seed),
-              obs_delay.data_ptr() if obs_delay is not None else None)
+              obs_delay.data_ptr() if obs_delay is not None else None,
+              obs_bias.data_ptr() if obs_bias is not None else None)
     check(lib().md_set_domain_randomization(ctx, ctypes.byref(d)), ctx)
 
 
@@ -428,13 +431,19 @@ def md_set_domain_randomization(ctx, scale=None, tau_mot=None, delay=None, noise
 
 def md_set_wind(ctx, models=0, v_mean=(0.0, 0.0, 0.0), rho=1.225, cd_area=0.01, gust_prob=0.0,
                 gust_duration=0.5, gust_amp=0.0, dryden_sigma=0.0, dryden_airspeed=1.0, sin_amp=0.0,
-                sin_omega=0.0, seed=0):
-    """models 0 turns wind off."""
+                sin_omega=0.0, seed=0, v_mean_drone=None):
+    """models 0 turns wind off.  v_mean_drone: CUDA float32 [3][N] per-drone
+    mean wind replacing v_mean, or None; it must stay alive while the
+    context uses it."""
     if not models:
         check(lib().md_set_wind(ctx, None), ctx)
         return
+    if v_mean_drone is not None:
+        import torch
+        assert v_mean_drone.dtype == torch.float32 and v_mean_drone.is_contiguous()
     w = md_wind(int(models), (ctypes.c_float * 3)(*v_mean), rho, cd_area, gust_prob, gust_duration, gust_amp,
-                dryden_sigma, dryden_airspeed, sin_amp, sin_omega, int(seed))
+                dryden_sigma, dryden_airspeed, sin_amp, sin_omega, int(seed),
+                v_mean_drone.data_ptr() if v_mean_drone is not None else None)
     check(lib().md_set_wind(ctx, ctypes.byref(w)), ctx)
 
 

@@ -273,10 +273,71 @@ def domain_randomization(w, seed, lag=True, latency=True, sensors=True, latency_
         return np.rint(x / w["dt"]).astype(np.int32)
 
     delay = steps(DR_LATENCY) if latency else None
-    noise, nseed, obs_delay = (0.0, 0.0, 0.0, 0.0), 0, None
+    noise, nseed, obs_delay, obs_bias = (0.0, 0.0, 0.0, 0.0), 0, None, None
     if sensors:
         noise = DR_NOISE
         nseed = int(rng.integers(0, 2 ** 63))
         obs_delay = steps(DR_SENSOR_LATENCY)
+        # sticky bias: one draw per drone and episode, with the noise levels
+        sig = np.repeat(np.asarray(DR_NOISE), 3)[:, None]
+        obs_bias = (sig * rng.standard_normal((12, n))).astype(np.float32)
     return dict(scale=scale.astype(np.float32), tau_mot=tau, delay=delay, noise=noise, seed=nseed,
-                obs_delay=obs_delay)
+                obs_delay=obs_delay, obs_bias=obs_bias)
+
+
+# Table "Recommended domain-randomization ranges", initial state: position,
+# roll/pitch/yaw and velocity offsets (uniform half-widths, m / rad / m/s).
+DR_INIT = (0.2, 0.1, 0.5)
+# COMBINED wind for randomisation: the mean wind of each environment has a
+# uniform magnitude in [0, 1] m/s and a uniform horizontal heading; gusts,
+# Dryden turbulence and the sinusoid keep fixed levels.
+DR_WIND = dict(models=15, rho=1.225, cd_area=0.01, gust_prob=0.002, gust_duration=0.5, gust_amp=0.02,
+               dryden_sigma=0.3, dryden_airspeed=0.9, sin_amp=0.005, sin_omega=1.0)
+
+
+def perturb_initial_state(w, seed):
+    """The table's initial-state draws on a workload whose drones start level
+    (yaw-only attitudes): per drone, position, roll, pitch, yaw and velocity
+    offsets uniform within DR_INIT."""
+    rng = np.random.default_rng(seed)
+    s = {k: v.copy() for k, v in w["state"].items()}
+    n = s["p"].shape[1]
+    assert np.all(s["q"][1:3] == 0), "level start expected"
+    dp, da, dv = DR_INIT
+    s["p"] += rng.uniform(-dp, dp, (3, n)).astype(np.float32)
+    s["v"] += rng.uniform(-dv, dv, (3, n)).astype(np.float32)
+    roll, pitch, dyaw = rng.uniform(-da, da, (3, n))
+    yaw = 2.0 * np.arctan2(s["q"][3].astype(np.float64), s["q"][0].astype(np.float64)) + dyaw
+    cr, sr = np.cos(0.5 * roll), np.sin(0.5 * roll)
+    cp, sp = np.cos(0.5 * pitch), np.sin(0.5 * pitch)
+    cy, sy = np.cos(0.5 * yaw), np.sin(0.5 * yaw)
+    # q = q_z(yaw) q_y(pitch) q_x(roll), the ZYX convention of the observation
+    s["q"] = np.stack([cr * cp * cy + sr * sp * sy, sr * cp * cy - cr * sp * sy,
+                       cr * sp * cy + sr * cp * sy, cr * cp * sy - sr * sp * cy]).astype(np.float32)
+    return dict(w, state=s)
+
+
+def dr_wind(w, seed):
+    """COMBINED wind with a per-environment mean wind (DR_WIND), as the
+    keyword arguments of md_set_wind plus the per-drone array
+    v_mean_drone [3][N] float32."""
+    rng = np.random.default_rng(seed)
+    off = np.asarray(w["env_offsets"], dtype=np.int64)
+    m = np.diff(off)
+    mag = rng.uniform(0.0, 1.0, len(m))
+    head = rng.uniform(0.0, 2.0 * np.pi, len(m))
+    vm = np.stack([np.repeat(mag * np.cos(head), m), np.repeat(mag * np.sin(head), m),
+                   np.zeros(int(off[-1]))]).astype(np.float32)
+    return dict(DR_WIND, seed=int(rng.integers(0, 2 ** 63)), v_mean_drone=vm)
+
+
+def randomized(w, seed, latency_per="env"):
+    """The workload under every row of the domain-randomisation table: the
+    initial-state draws, the per-drone factors, motor lag, latencies,
+    sensor noise and bias (domain_randomization) and the COMBINED wind with
+    a per-environment mean (dr_wind).  Returns the workload dict with "dr"
+    and "wind" entries."""
+    out = perturb_initial_state(w, seed)
+    out["dr"] = domain_randomization(w, seed + 1, latency_per=latency_per)
+    out["wind"] = dr_wind(w, seed + 2)
+    return out

@@ -51,14 +51,19 @@ class GpuRun:
         if w.get("dr") is not None:
             dr = w["dr"]
             self.dr = {k: (torch.from_numpy(dr[k]).cuda() if dr.get(k) is not None else None)
-                       for k in ("scale", "tau_mot", "delay", "obs_delay")}
+                       for k in ("scale", "tau_mot", "delay", "obs_delay", "obs_bias")}
             self.state.add_dr_blocks(ACT[w["act_type"]], w["state"])
             md.md_set_domain_randomization(self.ctx, self.dr["scale"], self.dr["tau_mot"], self.dr["delay"],
                                            noise=dr.get("noise", (0.0, 0.0, 0.0, 0.0)), seed=dr.get("seed", 0),
-                                           obs_delay=self.dr["obs_delay"])
+                                           obs_delay=self.dr["obs_delay"], obs_bias=self.dr["obs_bias"])
+        self.wind_arrays = None
         if w.get("wind") is not None:
             self.state.add_wind_block(w["state"])
-            md.md_set_wind(self.ctx, **w["wind"])
+            wk = dict(w["wind"])
+            if wk.get("v_mean_drone") is not None:
+                self.wind_arrays = torch.from_numpy(np.ascontiguousarray(wk["v_mean_drone"], dtype=np.float32)).cuda()
+                wk["v_mean_drone"] = self.wind_arrays
+            md.md_set_wind(self.ctx, **wk)
         self.action = torch.from_numpy(np.ascontiguousarray(w["action"], dtype=np.float32)).cuda()
         self.step_index = 0
 
@@ -140,6 +145,9 @@ def oracle_one_step(w, s32, k, env_subset=None, mask=None, n_steps=1, obs_slots=
                 wk[key] = f32(wk[key])
         if "v_mean" in wk:
             wk["v_mean"] = tuple(f32(x) for x in wk["v_mean"])
+        if wk.get("v_mean_drone") is not None:
+            vmd = np.asarray(wk["v_mean_drone"], dtype=np.float32).astype(np.float64)
+            wk["v_mean_drone"] = vmd if idx is None else np.ascontiguousarray(vmd[:, idx])
         wind = orc.make_wind(**wk, drone_id=idx.astype(np.int32) if idx is not None else None)
     obs = orc.step(P, w["dt"], w["aero_mask"] if mask is None else mask,
                    ORC_ACT[w["act_type"]], w["ctrl_decim"],

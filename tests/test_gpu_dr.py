@@ -52,6 +52,24 @@ def _parity(w, ks, env_subset=None, cfg=None, blocks=pu.BLOCKS):
     return worst
 
 
+@pytest.mark.parametrize("per", ["env", "drone"])
+def test_full_table_formation_as_benchmarked(per):
+    """The benchmark's randomised formation (every row of the table: initial
+    draws, factors, lag, latencies, sensor noise and bias, COMBINED wind with
+    per-environment means) at full size, in the autotuned launch
+    configuration, on sampled environments."""
+    import bench
+    w = wl.randomized(wl.formation(n_envs=8192, n_steps=1000, seed=4), bench.DR_SEED, latency_per=per)
+    g = pu.GpuRun(w)
+    md.md_autotune(g.ctx, g.state, g.action_slice(0, 50), w["action_per_step"], n_steps=50, cache_path="")
+    cfg = md.md_get_launch_config(g.ctx)
+    g.close()
+    rng = np.random.default_rng(3)
+    envs = np.sort(rng.choice(8192, 32, replace=False))
+    worst = _parity(w, [0, 1, 4, 5, 17, 333], env_subset=envs, cfg=cfg, blocks=pu.BLOCKS + EXTRA)
+    print("full-table formation 8192x32 (%s latencies, 32 sampled envs)" % per, cfg, "worst:", worst)
+
+
 @pytest.mark.parametrize("cfg", [SYM, LPD2], ids=["sym", "lpd2"])
 def test_formation_full_size_sampled(cfg):
     w = _dr(wl.formation(n_envs=8192, n_steps=1000, seed=4), 50)

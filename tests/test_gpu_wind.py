@@ -2,7 +2,8 @@
 (orc_step_disturbed): both sides draw from their own Philox4x32-10 keyed by
 (drone, global step), so gust triggers agree exactly and the Dryden normals
 to rounding.  Per-step criterion from GPU snapshots, including the wind
-state block; wind together with domain randomisation; error paths."""
+state block; per-environment mean winds; wind together with domain
+randomisation; error paths."""
 import numpy as np
 import pytest
 
@@ -40,6 +41,15 @@ def test_combined_wind_on_formation_subset():
     w = dict(wl.subset_envs(wl.formation(n_envs=8192, n_steps=1000, seed=4), 256), wind=COMBINED)
     worst = _parity(w, [0, 1, 2, 5, 61, 62, 200, 333], pu.BLOCKS + ("pid_int", "wind"))
     print("combined wind, formation 256 envs, worst:", worst)
+
+
+def test_per_environment_mean_wind():
+    """COMBINED wind whose mean differs per environment (the table's
+    per-episode wind magnitude): md_wind.v_mean_drone."""
+    base = wl.subset_envs(wl.formation(n_envs=8192, n_steps=1000, seed=4), 256)
+    w = dict(base, wind=wl.dr_wind(base, 8))
+    assert np.ptp(w["wind"]["v_mean_drone"][0]) > 0.5
+    _parity(w, [0, 1, 2, 61, 200], pu.BLOCKS + ("pid_int", "wind"))
 
 
 def test_wind_with_domain_randomization():
