@@ -335,7 +335,7 @@ def main():
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported "
+        print("bench.py: measures one GPU; --gpus %d is not supported "
               "(environments shard across GPUs with no per-step exchange)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)

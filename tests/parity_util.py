@@ -31,7 +31,7 @@ def hover_rpm():
     return md.md_derive(md.md_default_params_cf2x()).hover_rpm
 
 
-class GpuRun:
+class DeviceRun:
     """A libmd context plus device buffers for one workload dict."""
 
     def __init__(self, w, p=None, mask=None, cfg=None):

@@ -18,7 +18,7 @@ def _hover_thrust():
 @pytest.mark.parametrize("kind", ["vel", "attitude", "dsl"])
 def test_controller_per_step_parity(kind):
     w = wl.commanded(kind, _hover_thrust(), n_envs=1024, n_steps=480, seed=5)
-    g = pu.GpuRun(w)
+    g = pu.DeviceRun(w)
     worst = {}
     try:
         for k in (0, 1, 4, 5, 6, 10, 97, 240, 479):
@@ -39,7 +39,7 @@ def test_controller_per_step_parity(kind):
 def test_vel_command_is_tracked_on_gpu():
     w = wl.commanded("vel", _hover_thrust(), n_envs=256, n_steps=2400, seed=6)
     w = dict(w, aero_mask=0)
-    g = pu.GpuRun(w)
+    g = pu.DeviceRun(w)
     g.run(2400)
     s = g.snapshot()
     g.close()
@@ -51,7 +51,7 @@ def test_vel_command_is_tracked_on_gpu():
 
 def test_dsl_setpoint_block_reaches_waypoints():
     w = wl.commanded("dsl", _hover_thrust(), n_envs=256, n_steps=2400, seed=7)
-    g = pu.GpuRun(w)
+    g = pu.DeviceRun(w)
     g.run(2400)
     s = g.snapshot()
     g.close()

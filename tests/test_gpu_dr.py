@@ -25,7 +25,7 @@ def _dr(w, seed, **kw):
 
 def _parity(w, ks, env_subset=None, cfg=None, blocks=pu.BLOCKS):
     worst = {}
-    g = pu.GpuRun(w, cfg=cfg)
+    g = pu.DeviceRun(w, cfg=cfg)
     try:
         for k in ks:
             if k > g.step_index:
@@ -60,7 +60,7 @@ def test_full_table_formation_as_benchmarked(per):
     configuration, on sampled environments."""
     import bench
     w = wl.randomized(wl.formation(n_envs=8192, n_steps=1000, seed=4), bench.DR_SEED, latency_per=per)
-    g = pu.GpuRun(w)
+    g = pu.DeviceRun(w)
     md.md_autotune(g.ctx, g.state, g.action_slice(0, 50), w["action_per_step"], n_steps=50, cache_path="")
     cfg = md.md_get_launch_config(g.ctx)
     g.close()
@@ -95,11 +95,11 @@ def test_controllers(kind):
 
 def test_chunked_launches_equal_one_launch():
     w = _dr(wl.ragged_grid(pu.hover_rpm(), n_envs=200, n_steps=40, seed=7), 53)
-    a = pu.GpuRun(w)
+    a = pu.DeviceRun(w)
     a.run(40)
     sa = a.snapshot()
     a.close()
-    b = pu.GpuRun(w)
+    b = pu.DeviceRun(w)
     for k in (7, 13, 20):
         b.run(k)
     sb = b.snapshot()
@@ -111,7 +111,7 @@ def test_chunked_launches_equal_one_launch():
 def test_autotune_leaves_state_untouched_and_keeps_parity():
     import torch
     w = _dr(wl.subset_envs(wl.formation(n_envs=8192, n_steps=1000, seed=4), 256), 54)
-    g = pu.GpuRun(w)
+    g = pu.DeviceRun(w)
     g.run(3)
     before = g.snapshot()
     md.md_autotune(g.ctx, g.state, g.action_slice(0, 1), w["action_per_step"], n_steps=8, cache_path="")
@@ -170,9 +170,9 @@ def test_sensor_noise_statistics_and_latency_on_the_gpu():
     # no bits for centimetre noise
     w = wl.ragged_grid(pu.hover_rpm(), n_envs=2048, n_steps=12, seed=3)
     dr = wl.domain_randomization(w, 55)
-    clean = pu.GpuRun(dict(w, dr=dict(dr, noise=(0.0, 0.0, 0.0, 0.0), obs_delay=None)), mask=3)
-    noisy = pu.GpuRun(dict(w, dr=dict(dr, obs_delay=None)), mask=3)
-    late = pu.GpuRun(dict(w, dr=dict(dr, noise=(0.0, 0.0, 0.0, 0.0))), mask=3)
+    clean = pu.DeviceRun(dict(w, dr=dict(dr, noise=(0.0, 0.0, 0.0, 0.0), obs_delay=None)), mask=3)
+    noisy = pu.DeviceRun(dict(w, dr=dict(dr, obs_delay=None)), mask=3)
+    late = pu.DeviceRun(dict(w, dr=dict(dr, noise=(0.0, 0.0, 0.0, 0.0))), mask=3)
     try:
         oc = clean.run(12, obs_slots=12)
         on = noisy.run(12, obs_slots=12)
@@ -210,8 +210,8 @@ def test_latency_rings_across_launches_and_slot_counts(kind, per):
         w = wl.subset_envs(wl.formation(n_envs=8192, n_steps=40, seed=4), 64)
     w = dict(w, dr=wl.domain_randomization(w, 56, latency_per=per))
     assert w["dr"]["obs_delay"].max() >= 3 and w["dr"]["delay"].max() >= 8
-    a = pu.GpuRun(w, mask=3)
-    b = pu.GpuRun(w, mask=3)
+    a = pu.DeviceRun(w, mask=3)
+    b = pu.DeviceRun(w, mask=3)
     try:
         ref = a.run(40, obs_slots=40)
         start = 0

@@ -29,7 +29,7 @@ def _rk(w):
 
 def _parity(w, ks, env_subset=None, mask=None, cfg=None, extra=()):
     worst = {}
-    g = pu.GpuRun(w, mask=mask, cfg=cfg)
+    g = pu.DeviceRun(w, mask=mask, cfg=cfg)
     try:
         for k in ks:
             if k > g.step_index:
@@ -89,7 +89,7 @@ def test_symmetric_and_all_pairs_sweeps_are_bitwise_equal():
     w = _rk(_ragged_lattice(300, 10))
     out = []
     for cfg in (ALL, SYM, dict(ALL, waves_per_group=2, unroll=1)):
-        g = pu.GpuRun(w, cfg=cfg)
+        g = pu.DeviceRun(w, cfg=cfg)
         g.run(30)  # the held PID waypoints serve every step
         out.append(g.snapshot())
         g.close()
@@ -100,7 +100,7 @@ def test_symmetric_and_all_pairs_sweeps_are_bitwise_equal():
 
 def test_single_drone_trajectory_and_difference_from_euler():
     w = _rk(wl.single(pu.hover_rpm(), n_steps=240, seed=0))
-    g = pu.GpuRun(w)
+    g = pu.DeviceRun(w)
     g.run(240)
     got = g.snapshot()
     g.close()

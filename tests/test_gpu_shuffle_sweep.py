@@ -17,7 +17,7 @@ def shfl(waves=1, unroll=2):
 
 
 def _snap_parity(w, ks, cfg, blocks=pu.BLOCKS, env_subset=None):
-    g = pu.GpuRun(w, cfg=cfg)
+    g = pu.DeviceRun(w, cfg=cfg)
     worst = {}
     try:
         for k in ks:
@@ -52,7 +52,7 @@ def test_environments_up_to_64_drones():
 
 def test_coplanar_grid_per_step():
     w = wl.ragged_grid(pu.hover_rpm(), n_envs=300, n_steps=10, seed=7)
-    g = pu.GpuRun(w, cfg=shfl(1))
+    g = pu.DeviceRun(w, cfg=shfl(1))
     obs = g.run(10, obs_slots=10)
     g.close()
     prev = w["state"]
@@ -76,11 +76,11 @@ def test_bitwise_invariance_to_order_and_chunking():
     rng = np.random.default_rng(3)
     perm = rng.permutation(len(w["env_offsets"]) - 1)
     wp = wl.permute_envs(w, perm)
-    a = pu.GpuRun(w, cfg=shfl(2))
+    a = pu.DeviceRun(w, cfg=shfl(2))
     a.run(25)
     sa = a.snapshot()
     a.close()
-    b = pu.GpuRun(wp, cfg=shfl(4))
+    b = pu.DeviceRun(wp, cfg=shfl(4))
     for k in (5, 20):
         b.run(k)
     sb = b.snapshot()
@@ -92,7 +92,7 @@ def test_bitwise_invariance_to_order_and_chunking():
 
 def test_environments_above_64_are_rejected():
     w = _ragged(4, 11, shape=(5, 5, 3), m_lo=70)
-    g = pu.GpuRun(w)
+    g = pu.DeviceRun(w)
     with pytest.raises(md.MdError):
         md.md_set_launch_config(g.ctx, **shfl(2))
     g.close()

@@ -30,7 +30,7 @@ def _per_step_from_obs(w, obs, s0, steps):
 
 def test_single_drone_rpm_per_step():
     w = wl.single(pu.hover_rpm(), n_steps=240, seed=0)
-    g = pu.GpuRun(w)
+    g = pu.DeviceRun(w)
     obs = g.run(240, obs_slots=240)
     g.close()
     worst = _per_step_from_obs(w, obs, w["state"], range(240))
@@ -39,7 +39,7 @@ def test_single_drone_rpm_per_step():
 
 def test_single_drone_hover_1000_steps_trajectory():
     w = wl.single(pu.hover_rpm(), n_steps=1000, jitter=0.0, seed=0)
-    g = pu.GpuRun(w)
+    g = pu.DeviceRun(w)
     g.run(1000)
     got = g.snapshot()
     g.close()
@@ -53,7 +53,7 @@ def test_single_drone_hover_1000_steps_trajectory():
 
 def test_single_drone_rpm_trajectory_240_steps():
     w = wl.single(pu.hover_rpm(), n_steps=240, seed=0)
-    g = pu.GpuRun(w)
+    g = pu.DeviceRun(w)
     g.run(240)
     got = g.snapshot()
     g.close()
@@ -65,7 +65,7 @@ def _snapshot_parity(w, ks, env_subset=None, mask=None, obs=False):
     """Launch [0, k) then one more step; compare that step with the oracle
     stepped from the GPU snapshot (optionally on a subset of environments)."""
     worst = {kk: 0.0 for kk in pu.BLOCKS}
-    g = pu.GpuRun(w, mask=mask)
+    g = pu.DeviceRun(w, mask=mask)
     try:
         for k in ks:
             if k > g.step_index:
@@ -103,7 +103,7 @@ def test_pid_field_full_size_sampled():
 
 def test_ragged_downwash_full_size_per_step():
     w = wl.ragged_grid(pu.hover_rpm(), n_envs=1024, n_steps=100, seed=2)
-    g = pu.GpuRun(w)
+    g = pu.DeviceRun(w)
     obs = g.run(100, obs_slots=100)
     g.close()
     worst = _per_step_from_obs(w, obs, w["state"], range(100))
@@ -129,7 +129,7 @@ def test_lattice8_sampled():
 @pytest.mark.parametrize("mask", [0, 1, 2, 4, 7])
 def test_each_aero_term_on_ragged_layout(mask):
     w = wl.ragged_grid(pu.hover_rpm(), n_envs=64, n_steps=20, seed=5)
-    g = pu.GpuRun(w, mask=mask)
+    g = pu.DeviceRun(w, mask=mask)
     obs = g.run(20, obs_slots=20)
     g.close()
     w = dict(w, aero_mask=mask)
@@ -140,7 +140,7 @@ def test_packing_is_bitwise_invariant_to_environment_order():
     w = wl.ragged_grid(pu.hover_rpm(), n_envs=300, n_steps=30, seed=6)
     perm = np.random.default_rng(7).permutation(300)
     wp = wl.permute_envs(w, perm)
-    g1, g2 = pu.GpuRun(w), pu.GpuRun(wp)
+    g1, g2 = pu.DeviceRun(w), pu.DeviceRun(wp)
     g1.run(30)
     g2.run(30)
     a, b = g1.snapshot(), g2.snapshot()
@@ -153,7 +153,7 @@ def test_packing_is_bitwise_invariant_to_environment_order():
 def test_chunked_launches_equal_one_launch():
     # PID phase carried by step0; held actions; bitwise equal
     w = wl.lattice(n_envs=256, shape=(2, 2, 2), n_steps=60, seed=8)
-    g1, g2 = pu.GpuRun(w), pu.GpuRun(w)
+    g1, g2 = pu.DeviceRun(w), pu.DeviceRun(w)
     g1.run(60)
     for k in (7, 13, 1, 39):
         g2.run(k)
@@ -166,7 +166,7 @@ def test_chunked_launches_equal_one_launch():
 
 def test_observation_ring_keeps_last_steps():
     w = wl.ragged_grid(pu.hover_rpm(), n_envs=16, n_steps=10, seed=9)
-    g1, g2 = pu.GpuRun(w), pu.GpuRun(w)
+    g1, g2 = pu.DeviceRun(w), pu.DeviceRun(w)
     full = g1.run(10, obs_slots=10)
     ring = g2.run(10, obs_slots=4)
     g1.close()
@@ -179,7 +179,7 @@ def test_held_action_equals_repeated_per_step_action():
     w = wl.ragged_grid(pu.hover_rpm(), n_envs=32, n_steps=1, seed=10)
     w_rep = dict(w, action=np.repeat(w["action"], 12, axis=0), action_per_step=True)
     w_hold = dict(w, action=w["action"], action_per_step=False)
-    g1, g2 = pu.GpuRun(w_rep), pu.GpuRun(w_hold)
+    g1, g2 = pu.DeviceRun(w_rep), pu.DeviceRun(w_hold)
     g1.run(12)
     g2.run(12)
     a, b = g1.snapshot(), g2.snapshot()
@@ -199,7 +199,7 @@ def test_edge_layouts(sizes):
     act = (pu.hover_rpm() * (1 + rng.uniform(-0.1, 0.1, size=(5, 4, n)))).astype(np.float32)
     w = dict(name="edge", env_offsets=off, state=s, action=act, action_per_step=True,
              aero_mask=7, act_type="rpm", ctrl_decim=1, n_steps=5, dt=wl.DT)
-    g = pu.GpuRun(w)
+    g = pu.DeviceRun(w)
     obs = g.run(5, obs_slots=5)
     g.close()
     _per_step_from_obs(w, obs, s, range(5))
@@ -207,7 +207,7 @@ def test_edge_layouts(sizes):
 
 def test_zero_steps_and_zero_drones_are_no_ops():
     w = wl.ragged_grid(pu.hover_rpm(), n_envs=8, n_steps=1, seed=12)
-    g = pu.GpuRun(w)
+    g = pu.DeviceRun(w)
     before = g.snapshot()
     g.run(0)
     after = g.snapshot()

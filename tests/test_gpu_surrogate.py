@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 def _datagen(w, steps_before=0):
     import torch
-    g = pu.GpuRun(w)
+    g = pu.DeviceRun(w)
     if steps_before:
         g.run(steps_before)
     s = g.snapshot()
@@ -90,7 +90,7 @@ def _random_net(rng, scale=0.5):
     return flat, np.concatenate([xm, xs, ym, ys]).astype(np.float32)
 
 
-class SurRun(pu.GpuRun):
+class SurRun(pu.DeviceRun):
     def __init__(self, w, flat, norm, dz_ood=1e-3, judge_stride=0):
         import torch
         self.w = w

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _run_cfg(w, cfg, steps):
-    g = pu.GpuRun(w)
+    g = pu.DeviceRun(w)
     if cfg is not None:
         md.md_set_launch_config(g.ctx, **cfg)
     g.run(steps)
@@ -46,7 +46,7 @@ def test_one_lane_configs_are_bitwise_identical(name):
 def test_multi_lane_sweeps_match_the_oracle_per_step():
     w = wl.ragged_grid(pu.hover_rpm(), n_envs=200, n_steps=10, seed=7)
     for lpd in (2, 4):
-        g = pu.GpuRun(w)
+        g = pu.DeviceRun(w)
         md.md_set_launch_config(g.ctx, lanes_per_drone=lpd, unroll=2, waves_per_group=2)
         obs = g.run(10, obs_slots=10)
         g.close()
@@ -60,7 +60,7 @@ def test_multi_lane_sweeps_match_the_oracle_per_step():
 
 def test_invalid_configs_are_rejected():
     w = wl.ragged_grid(pu.hover_rpm(), n_envs=8, n_steps=1, seed=8)
-    g = pu.GpuRun(w)
+    g = pu.DeviceRun(w)
     with pytest.raises(md.MdError):
         md.md_set_launch_config(g.ctx, lanes_per_drone=4, waves_per_group=1)  # 16 slots < 32 drones
     with pytest.raises(md.MdError):
@@ -72,7 +72,7 @@ def test_invalid_configs_are_rejected():
 
 def test_autotune_keeps_state_and_caches_choice(tmp_path):
     w = wl.subset_envs(wl.formation(n_envs=8192, seed=4), 256)
-    g = pu.GpuRun(w)
+    g = pu.DeviceRun(w)
     before = g.snapshot()
     cache = str(tmp_path / "tune.json")
     cfg = md.md_autotune(g.ctx, g.state, g.action, False, n_steps=10, cache_path=cache)
@@ -82,7 +82,7 @@ def test_autotune_keeps_state_and_caches_choice(tmp_path):
     rec = json.load(open(cache))
     assert len(rec) == 1 and rec[0]["lpd"] == cfg["lanes_per_drone"] and rec[0]["sym"] == cfg["pair_symmetric"]
     # a second context with the same layout takes the cached choice
-    g2 = pu.GpuRun(w)
+    g2 = pu.DeviceRun(w)
     md.md_set_launch_config(g2.ctx, lanes_per_drone=1, unroll=1, waves_per_group=1)
     cfg2 = md.md_autotune(g2.ctx, g2.state, g2.action, False, n_steps=10, cache_path=cache)
     assert cfg2 == cfg
@@ -99,7 +99,7 @@ def test_autotune_keeps_state_and_caches_choice(tmp_path):
 def test_graph_replays_equal_eager_launches():
     import torch
     w = wl.subset_envs(wl.formation(n_envs=8192, seed=4), 128)
-    ge, gg = pu.GpuRun(w), pu.GpuRun(w)
+    ge, gg = pu.DeviceRun(w), pu.DeviceRun(w)
     graph = md.md_rollout_graph_create(gg.ctx, gg.state, gg.action, False, None, 0,
                                        steps_per_launch=10, n_launches=3, step0=0)
     for rep in range(3):

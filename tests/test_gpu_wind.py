@@ -19,7 +19,7 @@ COMBINED = dict(models=md.MD_WIND_COMBINED, v_mean=(0.9, -0.4, 0.0), rho=1.225, 
 
 def _parity(w, ks, blocks):
     worst = {}
-    g = pu.GpuRun(w)
+    g = pu.DeviceRun(w)
     try:
         for k in ks:
             if k > g.step_index:
@@ -77,7 +77,7 @@ def test_gusts_start_and_end_on_schedule():
     round(duration / dt) steps, then a new one starts."""
     w = dict(wl.subset_envs(wl.formation(n_envs=8192, n_steps=1000, seed=4), 8),
              wind=dict(models=md.MD_WIND_GUST, gust_prob=1.0, gust_duration=0.1, gust_amp=0.02, seed=3))
-    g = pu.GpuRun(w)
+    g = pu.DeviceRun(w)
     g.run(23)
     assert np.all(g.snapshot()["wind"][3] == 23)  # 23 gust steps taken
     g.run(1)
