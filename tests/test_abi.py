@@ -53,3 +53,38 @@ def test_create_rejects_bad_arguments_before_touching_a_device():
     assert out.value is None
     assert "SURROGATE" in md.md_last_error(None)
     assert L.md_step(None, None, None, 0, None, 0, 1, 0, None) == md.MD_E_INVALID_ARG
+
+
+STRUCTS = ("md_params", "md_derived", "md_state", "md_dr", "md_wind", "md_launch_config", "md_judge")
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every public struct of include/md.h has the size and field offsets the
+    Python binding declares (a C program built with gcc against the header
+    prints them)."""
+    import os
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    lines = ['#include <stdio.h>', '#include "md.h"', "int main(void) {"]
+    for s in STRUCTS:
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (s, s))
+        for f, _ in getattr(md, s)._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (s, f, s, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call([gcc, "-std=c11", "-I", inc, str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        a, b, c = line.split()
+        got[(a, b)] = int(c)
+    for s in STRUCTS:
+        cls = getattr(md, s)
+        assert got[(s, "size")] == ctypes.sizeof(cls), s
+        for f, _ in cls._fields_:
+            assert got[(s, f)] == getattr(cls, f).offset, (s, f)

@@ -330,3 +330,37 @@ def test_sticky_observation_bias_is_added_to_the_delayed_rows():
         np.testing.assert_array_equal(got, want)
         for k in ("p", "v", "q", "w", "rpm"):
             np.testing.assert_array_equal(s[k], plain_s[k])
+
+
+def test_oracle_structs_match_their_c_layout(tmp_path):
+    """The ctypes mirrors of the oracle's structs have the C header's sizes
+    and field offsets, so that every field (counts, rings, counter words,
+    bias) reaches the C code where it is meant to."""
+    import ctypes
+    import os
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    here = os.path.dirname(os.path.abspath(orc.__file__))
+    pairs = (("orc_params", orc.Params), ("orc_derived", orc.Derived), ("orc_net", orc.Net),
+             ("orc_state", orc._CState), ("orc_wind", orc._CWind), ("orc_dr", orc._CDr))
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "md_oracle.h"', "int main(void) {"]
+    for cname, cls in pairs:
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call([gcc, "-std=c11", "-I", here, str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        a, b, c = line.split()
+        got[(a, b)] = int(c)
+    for cname, cls in pairs:
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
