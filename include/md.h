@@ -304,8 +304,9 @@ md_status md_get_integrator(const md_ctx *ctx, int *out);
  * the same physics: lanes_per_drone 1 with pair_symmetric 0 or 1 and any
  * waves_per_group give bitwise identical results; lanes_per_drone 2 or 4
  * split each neighbour sum into interleaved partial sums, and
- * pair_symmetric 2 sums each drone's terms shift by shift (different but
- * fixed summation orders, independent of how environments are packed). */
+ * pair_symmetric 2 and 3 sum each drone's terms shift by shift (different but
+ * fixed summation orders, independent of how environments are packed; 2 and
+ * 3 are bitwise identical). */
 typedef struct md_launch_config {
     int lanes_per_drone; /* 1, 2 or 4 lanes share one drone's neighbour sweep */
     int unroll;          /* neighbour-loop unroll: 1, 2 or 4 */
@@ -313,14 +314,19 @@ typedef struct md_launch_config {
     int pair_symmetric;  /* 0: all ordered pairs; 1: each unordered pair once, terms routed
                             through an LDS matrix; 2: each unordered pair once, terms routed
                             between lanes by wave permutes (environments of at most 64
-                            drones, packed so that none crosses a wavefront).  1 and 2
+                            drones, packed so that none crosses a wavefront); 3: the
+                            pairs of 2 as rotations of the whole wave, for layouts whose
+                            non-empty environments all have one power-of-two size 2..64
+                            (environments interleaved in their wave; unroll 1, the sweep
+                            is unrolled in full; semi-implicit Euler only).  1, 2 and 3
                             need lanes_per_drone 1. */
 } md_launch_config;
 
 md_status md_get_launch_config(const md_ctx *ctx, md_launch_config *out);
 /* MD_E_INVALID_ARG if the configuration cannot hold the bound layout's
- * largest environment or its LDS need exceeds 64 KB, or if lanes_per_drone
- * is not 1 for MD_INTEG_RK4 with the downwash term. */
+ * largest environment or its LDS need exceeds 64 KB, if lanes_per_drone
+ * is not 1 for MD_INTEG_RK4 with the downwash term, or if pair_symmetric 3
+ * does not fit the layout or the integrator. */
 md_status md_set_launch_config(md_ctx *ctx, md_launch_config *cfg);
 
 /* Time every valid launch configuration for the bound layout on scratch

@@ -196,8 +196,34 @@ static void pack_bins_wave_aligned(const std::vector<int32_t> &off, int slots, s
     }
 }
 
-md_status build_bins(md_ctx *ctx, int slots, bool wave_aligned, BinSet **out) {
-    const int key = slots * 2 + (wave_aligned ? 1 : 0);
+// Bins for the rotation sweep: every non-empty environment has the same
+// power-of-two size M <= 64; E = 64 / M consecutive environments share a
+// wave, drone li of the wave's e-th environment in lane E li + e; waves are
+// grouped in order into workgroups of slots / 64.  A wave that receives
+// fewer than E environments (the last one) keeps idle lanes in the missing
+// residues, and each bin reports M with the uniform flag.
+static void pack_bins_interleaved(const std::vector<int32_t> &off, int M, int slots, std::vector<int2> &tab,
+                                  std::vector<int> &mmax, int &n_bins) {
+    const int E = 64 / M, W = slots / 64;
+    std::vector<int> envs;
+    for (int e = 0; e + 1 < (int)off.size(); ++e)
+        if (off[e + 1] > off[e]) envs.push_back(e);
+    const int n_waves = ((int)envs.size() + E - 1) / E;
+    n_bins = (n_waves + W - 1) / W;
+    tab.assign((size_t)n_bins * slots, make_int2(-1, 0));
+    mmax.assign(n_bins, M | 0x10000);
+    for (size_t k = 0; k < envs.size(); ++k) {
+        const int wave = (int)k / E, e = (int)k % E;
+        const int b = wave / W, w = wave % W;
+        for (int li = 0; li < M; ++li) {
+            const int lane = E * li + e;
+            tab[(size_t)b * slots + 64 * w + lane] = make_int2(off[envs[k]] + li, ((64 * w + e) << 16) | M);
+        }
+    }
+}
+
+md_status build_bins(md_ctx *ctx, int slots, int mode, BinSet **out) {
+    const int key = slots * 4 + mode;
     auto it = ctx->binsets.find(key);
     if (it != ctx->binsets.end()) {
         *out = &it->second;
@@ -211,10 +237,18 @@ md_status build_bins(md_ctx *ctx, int slots, bool wave_aligned, BinSet **out) {
     std::vector<int2> tab;
     std::vector<int> mm;
     BinSet bs;
-    if (wave_aligned)
+    if (mode == BIN_INTERLEAVED) {
+        const int M = ctx->uniform_m;
+        if (M < 2 || M > 64 || (M & (M - 1)) || slots % 64) {
+            ctx->err = "interleaved bins need environments of one power-of-two size 2..64";
+            return MD_E_UNSUPPORTED;
+        }
+        pack_bins_interleaved(ctx->off, M, slots, tab, mm, bs.n_bins);
+    } else if (mode == BIN_WAVE_ALIGNED) {
         pack_bins_wave_aligned(ctx->off, slots, tab, mm, bs.n_bins);
-    else
+    } else {
         pack_bins(ctx->off, slots, tab, mm, bs.n_bins);
+    }
     bs.slots = slots;
     if (bs.n_bins > 0) {
         hipError_t e = hipMalloc(&bs.d_slot, sizeof(int2) * tab.size());
@@ -252,8 +286,9 @@ int slots_for(const md_ctx *ctx, const LaunchCfg &cfg) {
     return 64 * cfg.waves / lpd;
 }
 
-bool wave_aligned_for(const md_ctx *ctx, const LaunchCfg &cfg) {
-    return (ctx->mask & MD_AERO_DW) && cfg.sym == 2;
+int bin_mode_for(const md_ctx *ctx, const LaunchCfg &cfg) {
+    if (!(ctx->mask & MD_AERO_DW)) return BIN_PACKED;
+    return cfg.sym == 3 ? BIN_INTERLEAVED : cfg.sym == 2 ? BIN_WAVE_ALIGNED : BIN_PACKED;
 }
 
 LaunchCfg default_cfg(const md_ctx *ctx) {
@@ -271,16 +306,16 @@ md_status prepare_launch(md_ctx *ctx) {
     if (ctx->mask & MD_AERO_SURROGATE) {
         int waves = 1;
         while (64 * waves < ctx->max_m) waves *= 2;
-        return build_bins(ctx, 64 * waves, false, &bs);
+        return build_bins(ctx, 64 * waves, BIN_PACKED, &bs);
     }
-    return build_bins(ctx, slots_for(ctx, ctx->cfg), wave_aligned_for(ctx, ctx->cfg), &bs);
+    return build_bins(ctx, slots_for(ctx, ctx->cfg), bin_mode_for(ctx, ctx->cfg), &bs);
 }
 
 md_status launch(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
                  float *d_obs, int n_obs_slots, int n_steps, int64_t step0, hipStream_t st,
                  const LaunchCfg &cfg) {
     BinSet *bs = nullptr;
-    md_status rc = build_bins(ctx, slots_for(ctx, cfg), wave_aligned_for(ctx, cfg), &bs);
+    md_status rc = build_bins(ctx, slots_for(ctx, cfg), bin_mode_for(ctx, cfg), &bs);
     if (rc != MD_OK) return rc;
     StepArgs a;
     a.c = ctx->kc;
@@ -470,10 +505,15 @@ md_status md_bind_layout(md_ctx *ctx, const int32_t *h_env_offsets, int n_envs, 
     ctx->n_envs = n_envs;
     ctx->n_drones = n_drones;
     ctx->max_m = maxm;
+    ctx->uniform_m = maxm;
+    for (int e = 0; e < n_envs; ++e) {
+        const int m = h_env_offsets[e + 1] - h_env_offsets[e];
+        if (m != 0 && m != maxm) ctx->uniform_m = 0;
+    }
     ctx->has_layout = true;
     ctx->cfg = md::default_cfg(ctx);
     md::BinSet *bs = nullptr;
-    return md::build_bins(ctx, md::slots_for(ctx, ctx->cfg), md::wave_aligned_for(ctx, ctx->cfg), &bs);
+    return md::build_bins(ctx, md::slots_for(ctx, ctx->cfg), md::bin_mode_for(ctx, ctx->cfg), &bs);
 }
 
 md_status md_set_integrator(md_ctx *ctx, int integrator) {

@@ -44,7 +44,8 @@ struct md_ctx {
     bool has_layout = false;
     int n_envs = 0, n_drones = 0, max_m = 0;
     std::vector<int32_t> off;
-    std::map<int, md::BinSet> binsets;  // keyed by 2 x slots per bin + wave-aligned packing
+    int uniform_m = 0;  // the common size of all non-empty environments, or 0
+    std::map<int, md::BinSet> binsets;  // keyed by 4 x slots per bin + packing mode (BinMode)
     md::LaunchCfg cfg{1, 4, 1, 0};
     bool tuned = false;
     // optional subsystems
@@ -54,10 +55,14 @@ struct md_ctx {
 
 namespace md {
 
-md_status build_bins(md_ctx *ctx, int slots, bool wave_aligned, BinSet **out);
+// Packing of environments into bins: contiguous runs (best fit decreasing),
+// contiguous runs that never cross a wavefront, or interleaved inside each
+// wave (uniform power-of-two environments, the rotation sweep).
+enum BinMode { BIN_PACKED = 0, BIN_WAVE_ALIGNED = 1, BIN_INTERLEAVED = 2 };
+md_status build_bins(md_ctx *ctx, int slots, int mode, BinSet **out);
 void free_bins(md_ctx *ctx);
 int slots_for(const md_ctx *ctx, const LaunchCfg &cfg);
-bool wave_aligned_for(const md_ctx *ctx, const LaunchCfg &cfg);
+int bin_mode_for(const md_ctx *ctx, const LaunchCfg &cfg);
 LaunchCfg default_cfg(const md_ctx *ctx);
 md_status launch(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
                  float *d_obs, int n_obs_slots, int n_steps, int64_t step0, hipStream_t st,

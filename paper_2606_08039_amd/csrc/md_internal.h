@@ -106,7 +106,8 @@ struct LaunchCfg {
     int lpd;     // lanes per drone in the neighbour sweep: 1, 2 or 4
     int unroll;  // neighbour-loop unroll: 1, 2, 4 or 8
     int waves;   // waves per workgroup (bin size 64 * waves / lpd slots)
-    int sym;     // 1: evaluate each unordered pair once (lpd must be 1)
+    int sym;     // pair-symmetric sweep (lpd must be 1): 1 LDS term matrix, 2 wave permutes,
+                 // 3 whole-wave rotation on interleaved uniform bins
 };
 
 hipError_t launch_step(const StepArgs &a, uint32_t mask, int act, const LaunchCfg &cfg,

@@ -307,7 +307,14 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     for (int step = 0; step < a.n_steps; ++step) {
         float4 *buf = lds_pos + (step & 1) * (2 * slots);
         if (MASK & 4u) {
-            if (sub == 0) buf[slot] = make_float4(d.px, d.py, d.pz, 0.f);
+            if (SYM == 3) {
+                // interleaved uniform bins: each wave's positions twice (128 entries)
+                const int lane = slot & 63;
+                float4 *own = buf + 2 * (slot - lane) + lane;
+                own[0] = own[64] = make_float4(d.px, d.py, d.pz, 0.f);
+            } else if (sub == 0) {
+                buf[slot] = make_float4(d.px, d.py, d.pz, 0.f);
+            }
             __syncthreads();
         }
         // ---- rotor speeds
@@ -498,6 +505,11 @@ hipError_t launch_l(const StepArgs &a, const LaunchCfg &cfg, int n_bins, int thr
     }
     if (cfg.sym) {
         if (cfg.lpd != 1) return hipErrorInvalidValue;
+        if (cfg.sym == 3) {
+            // the rotation sweep is fully unrolled: no unroll variants
+            hipLaunchKernelGGL((step_kernel<MASK, ACT, 1, 1, 3, DR>), dim3(n_bins), dim3(threads), lds, st, a);
+            return hipGetLastError();
+        }
         return cfg.sym == 2 ? launch_u<MASK, ACT, 1, 2, DR>(a, cfg.unroll, n_bins, threads, lds, st)
                             : launch_u<MASK, ACT, 1, 1, DR>(a, cfg.unroll, n_bins, threads, lds, st);
     }

@@ -656,7 +656,7 @@ md_status surrogate_step(md_ctx *ctx, const md_state *s, const float *d_action, 
     int waves = 1;
     while (64 * waves < ctx->max_m) waves *= 2;
     BinSet *bs = nullptr;
-    md_status rc = build_bins(ctx, 64 * waves, false, &bs);
+    md_status rc = build_bins(ctx, 64 * waves, BIN_PACKED, &bs);
     if (rc != MD_OK) return rc;
     SurArgs sa;
     sa.s.c = ctx->kc;
@@ -695,7 +695,7 @@ md_status datagen(md_ctx *ctx, const md_state *s, uint32_t mask, float *d_X, flo
     int waves = 1;
     while (64 * waves < ctx->max_m) waves *= 2;
     BinSet *bs = nullptr;
-    md_status rc = build_bins(ctx, 64 * waves, false, &bs);
+    md_status rc = build_bins(ctx, 64 * waves, BIN_PACKED, &bs);
     if (rc != MD_OK) return rc;
     GenArgs g;
     g.c = ctx->kc;

@@ -134,17 +134,75 @@ __device__ __forceinline__ float dw_pairs_shfl(const KConst &c0, const float4 *b
     return acc;
 }
 
+// The same pairs, shifts, routing and summation order as dw_pairs_shfl, for
+// bins whose environments all have one power-of-two size M = 64 / E and sit
+// interleaved in their wave: drone li of the wave's environment e in lane
+// E li + e.  Then the partner (li + k) mod M of every lane is lane
+// (lane + E k) mod 64 and the drone whose term arrives is lane
+// (lane - E k) mod 64, for all lanes at once: a rotation of the whole wave.
+// The positions are stored twice per wave (entries lane and 64 + lane of the
+// wave's 128), so the partner's entry is a fixed offset from the lane's own,
+// and the permute address wraps in hardware (lane bits of the byte address);
+// with k unrolled neither costs an instruction.
+template <bool DZMIN, int E>
+__device__ __forceinline__ float dw_pairs_rot(const KConst &c0, const float4 *own, int lane, const Drone &d) {
+    constexpr int M = 64 / E;
+    constexpr int H = (M - 1) / 2;
+    const KConst c = pair_consts(c0);
+    const int pa = 4 * lane;
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+        const float4 q = own[E * k];
+        const float dz = q.z - d.pz;
+        const float t = dw_term<DZMIN>(c, q.x - d.px, q.y - d.py, fabsf(dz));
+        const float mine = dz > 0.f ? t : 0.f;
+        const float theirs = t - mine;
+        const float recv = __int_as_float(__builtin_amdgcn_ds_bpermute(pa + (256 - 4 * E * k), __float_as_int(theirs)));
+        acc += mine;
+        acc += recv;
+    }
+    {
+        // M is even: the pair at distance M / 2 (lane + 32), kept by the lower drone
+        const float4 q = own[32];
+        const float dz = q.z - d.pz;
+        const float t = dw_term<DZMIN>(c, q.x - d.px, q.y - d.py, fabsf(dz));
+        acc += dz > 0.f ? t : 0.f;
+    }
+    return acc;
+}
+
+template <bool DZMIN>
+__device__ __forceinline__ float dw_rot(const KConst &c, const float4 *own, int lane, int m, const Drone &d) {
+    switch (m) {
+        case 64: return dw_pairs_rot<DZMIN, 1>(c, own, lane, d);
+        case 32: return dw_pairs_rot<DZMIN, 2>(c, own, lane, d);
+        case 16: return dw_pairs_rot<DZMIN, 4>(c, own, lane, d);
+        case 8: return dw_pairs_rot<DZMIN, 8>(c, own, lane, d);
+        case 4: return dw_pairs_rot<DZMIN, 16>(c, own, lane, d);
+        default: return dw_pairs_rot<DZMIN, 32>(c, own, lane, d);
+    }
+}
+
 // Downwash sum (without K1) of this slot's drone against the positions in
 // `buf`.  SYM 0: the all-pairs sweep over LPD lanes (their partial sums
 // combined in a fixed order); SYM 1: the pair-symmetric sweep through the LDS
 // term matrix (it contains the barrier between the term writes and the row
 // sums; bitwise equal to SYM 0 with one lane); SYM 2: the pair-symmetric
-// sweep through wave shuffles (environments inside one wave).
+// sweep through wave shuffles (environments inside one wave); SYM 3: the same
+// sweep as a whole-wave rotation on interleaved uniform bins (bitwise equal
+// to SYM 2).
 template <int LPD, int UNROLL, int SYM>
 __device__ __forceinline__ float dw_sum(const KConst &c, const float4 *buf, float *tmat, int ts, int slot,
                                         int sub, int lo, int mmax, int menv, bool uniform, const Drone &d) {
     float acc = 0.f;
-    if (SYM == 2) {
+    if (SYM == 3) {
+        // interleaved uniform bins (see dw_pairs_rot): `buf` holds each wave's
+        // positions twice, 128 entries per wave
+        const int lane = slot & 63;
+        const float4 *own = buf + 2 * (slot - lane) + lane;
+        acc = c.dz_min > 0.f ? dw_rot<true>(c, own, lane, mmax, d) : dw_rot<false>(c, own, lane, mmax, d);
+    } else if (SYM == 2) {
         // `uniform` and dz_min are the same for the whole workgroup: the
         // permutes inside run with every lane of the wave
         if (uniform)

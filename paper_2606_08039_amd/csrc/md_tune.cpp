@@ -42,9 +42,15 @@ static std::string signature(const md_ctx *ctx) {
 bool cfg_valid(const md_ctx *ctx, const LaunchCfg &c) {
     const int slots = 64 * c.waves / c.lpd;
     if (slots < ctx->max_m || slots < 1) return false;
-    if (c.sym < 0 || c.sym > 2) return false;
+    if (c.sym < 0 || c.sym > 3) return false;
     if (c.sym && c.lpd != 1) return false;
     if (c.sym == 2 && ctx->max_m > 64) return false;  // environments inside one wave
+    if (c.sym == 3) {
+        // one power-of-two environment size 2..64, the semi-implicit Euler step
+        const int m = ctx->uniform_m;
+        if (m < 2 || m > 64 || (m & (m - 1)) || ctx->integ == MD_INTEG_RK4) return false;
+        if (c.unroll != 1) return false;  // fully unrolled
+    }
     if (ctx->integ == MD_INTEG_RK4 && (ctx->mask & MD_AERO_DW) && c.lpd != 1) return false;
     if (c.sym == 1) {
         const size_t lds = 16 * 4 * (size_t)slots + 4 * (size_t)slots * (size_t)pair_stride(ctx->max_m);
@@ -62,7 +68,7 @@ static std::vector<LaunchCfg> candidates(const md_ctx *ctx) {
         if (out.empty()) out.push_back(default_cfg(ctx));
         return out;
     }
-    for (int sym : {0, 1, 2})
+    for (int sym : {0, 1, 2, 3})
         for (int lpd : {1, 2, 4})
             for (int w : {1, 2, 4, 8, 16})
                 for (int u : {1, 2, 4}) {

@@ -61,11 +61,11 @@ def test_single_drone_rpm_trajectory_240_steps():
     assert np.max(np.abs(got["p"] - ref["p"])) <= 1e-3
 
 
-def _snapshot_parity(w, ks, env_subset=None, mask=None, obs=False):
+def _snapshot_parity(w, ks, env_subset=None, mask=None, obs=False, cfg=None):
     """Launch [0, k) then one more step; compare that step with the oracle
     stepped from the GPU snapshot (optionally on a subset of environments)."""
     worst = {kk: 0.0 for kk in pu.BLOCKS}
-    g = pu.DeviceRun(w, mask=mask)
+    g = pu.DeviceRun(w, mask=mask, cfg=cfg)
     try:
         for k in ks:
             if k > g.step_index:
@@ -110,12 +110,24 @@ def test_ragged_downwash_full_size_per_step():
     print("ragged grid 1024 envs, worst:", worst)
 
 
-def test_formation_full_size_sampled():
+@pytest.mark.parametrize("cfg", ["default", "autotuned", "rotation"])
+def test_formation_full_size_sampled(cfg):
+    """The benchmark workload at full size: the default configuration, the
+    one the autotuner picks (the benchmark's), and the rotation sweep."""
     w = wl.formation(n_envs=8192, n_steps=1000, seed=4)
+    if cfg == "default":
+        c = None
+    elif cfg == "rotation":
+        c = dict(lanes_per_drone=1, unroll=1, waves_per_group=8, pair_symmetric=3)
+    else:
+        g = pu.DeviceRun(w)
+        md.md_autotune(g.ctx, g.state, g.action_slice(0, 50), w["action_per_step"], n_steps=50, cache_path="")
+        c = md.md_get_launch_config(g.ctx)
+        g.close()
     rng = np.random.default_rng(0)
     envs = np.sort(rng.choice(8192, 48, replace=False))
-    worst = _snapshot_parity(w, [0, 1, 5, 333, 999], env_subset=envs, obs=True)
-    print("formation 8192x32 (48 sampled envs), worst:", worst)
+    worst = _snapshot_parity(w, [0, 1, 5, 333, 999], env_subset=envs, obs=True, cfg=c)
+    print("formation 8192x32 (48 sampled envs), %s %s, worst:" % (cfg, c), worst)
 
 
 def test_lattice8_sampled():
