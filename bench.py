@@ -365,10 +365,11 @@ def main():
     hbm = bytes_ / kavg / 1e9
     alu = flop / kavg / 1e12
     traffic = measured_traffic(args.workload)
-    # The step kernel is bound by vector-ALU issue (its instruction stream, not
-    # its 80 B per drone-step of observations, sets the time): roofline is the
-    # algorithmic FP32 rate against the chip's FP32 vector peak, with the HBM
-    # view (algorithmic bytes per launch) beside it.
+    # Two limits meet in the step kernel: its vector-ALU instruction stream
+    # (the launch without observation writes, `plain_no_obs`, is bound by it)
+    # and the observation write stream.  roofline is the algorithmic FP32 rate
+    # against the chip's FP32 vector peak, with the HBM view (algorithmic
+    # bytes per launch) beside it.
     roof = {"bound": "alu", "achieved": round(alu, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(alu / FP32_PEAK_TFLOPS, 4), "traffic": traffic}
     roof_hbm = {"bound": "hbm", "achieved": round(hbm, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -398,6 +399,16 @@ def main():
         "algorithmic_bytes_per_launch": bytes_,
         "algorithmic_flop_per_launch": flop,
     }
+    if with_obs:
+        # the same launches without observation writes, in the same launch
+        # configuration: the compute side of the step kernel alone
+        wall0, kms0, _, _, _ = timed_rollouts(args, w, p, False, tune=False, config=launch_cfg)
+        flop0, _ = algorithmic_counts(w, False)
+        k0 = float(np.mean(kms0)) * 1e-3
+        out["plain_no_obs"] = {"value": ds / wall0, "unit": "drone-steps/s", "kernel_ms_avg": k0 * 1e3,
+                               "alu_tflops": round(flop0 / k0 / 1e12, 3),
+                               "frac_fp32_peak": round(flop0 / k0 / 1e12 / FP32_PEAK_TFLOPS, 4),
+                               "frac_fp32_non_packed_peak": round(flop0 / k0 / 1e12 / (FP32_PEAK_TFLOPS / 2), 4)}
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(args, w, p, with_obs)
         if out["surrogate"].get("value"):
