@@ -318,15 +318,14 @@ typedef struct md_launch_config {
                             pairs of 2 as rotations of the whole wave, for layouts whose
                             non-empty environments all have one power-of-two size 2..64
                             (environments interleaved in their wave; unroll 1, the sweep
-                            is unrolled in full; semi-implicit Euler only).  1, 2 and 3
-                            need lanes_per_drone 1. */
+                            is unrolled in full).  1, 2 and 3 need lanes_per_drone 1. */
 } md_launch_config;
 
 md_status md_get_launch_config(const md_ctx *ctx, md_launch_config *out);
 /* MD_E_INVALID_ARG if the configuration cannot hold the bound layout's
  * largest environment or its LDS need exceeds 64 KB, if lanes_per_drone
  * is not 1 for MD_INTEG_RK4 with the downwash term, or if pair_symmetric 3
- * does not fit the layout or the integrator. */
+ * does not fit the layout. */
 md_status md_set_launch_config(md_ctx *ctx, md_launch_config *cfg);
 
 /* Time every valid launch configuration for the bound layout on scratch

@@ -12,7 +12,7 @@
 //   p' = v, v' = F / m, q' = q (x) [0, w] / 2, w' = J^-1 (tau - w x J w),
 // with the rotation of a stage taken from its normalised quaternion; the
 // quaternion is renormalised after the step.  One lane per drone; the
-// neighbour sweep is the all-pairs or the pair-symmetric one.
+// neighbour sweep is the all-pairs or one of the pair-symmetric ones.
 #include "md_sweep.h"
 
 namespace md {
@@ -103,7 +103,14 @@ __global__ void __launch_bounds__(1024) rk4_kernel(StepArgs a) {
         for (int st = 0; st < 4; ++st) {
             float4 *buf = lds_pos + (st & 1) * (2 * slots);
             if (MASK & 4u) {
-                buf[slot] = make_float4(d.px, d.py, d.pz, 0.f);
+                if (SYM == 3) {
+                    // interleaved uniform bins: each wave's positions twice (128 entries)
+                    const int lane = slot & 63;
+                    float4 *own = buf + 2 * (slot - lane) + lane;
+                    own[0] = own[64] = make_float4(d.px, d.py, d.pz, 0.f);
+                } else {
+                    buf[slot] = make_float4(d.px, d.py, d.pz, 0.f);
+                }
                 __syncthreads();
             }
             const float qi = rsqrtf(d.qw * d.qw + d.qx * d.qx + d.qy * d.qy + d.qz * d.qz);
@@ -219,6 +226,10 @@ hipError_t launch_l(const StepArgs &a, const LaunchCfg &cfg, int n_bins, int thr
         case 0: return launch_u<MASK, ACT, 0>(a, cfg.unroll, n_bins, threads, lds, st);
         case 1: return launch_u<MASK, ACT, 1>(a, cfg.unroll, n_bins, threads, lds, st);
         case 2: return launch_u<MASK, ACT, 2>(a, cfg.unroll, n_bins, threads, lds, st);
+        case 3:
+            // the rotation sweep is fully unrolled: no unroll variants
+            hipLaunchKernelGGL((rk4_kernel<MASK, ACT, 1, 3>), dim3(n_bins), dim3(threads), lds, st, a);
+            return hipGetLastError();
         default: return hipErrorInvalidValue;
     }
 }

@@ -46,9 +46,9 @@ bool cfg_valid(const md_ctx *ctx, const LaunchCfg &c) {
     if (c.sym && c.lpd != 1) return false;
     if (c.sym == 2 && ctx->max_m > 64) return false;  // environments inside one wave
     if (c.sym == 3) {
-        // one power-of-two environment size 2..64, the semi-implicit Euler step
+        // one power-of-two environment size 2..64
         const int m = ctx->uniform_m;
-        if (m < 2 || m > 64 || (m & (m - 1)) || ctx->integ == MD_INTEG_RK4) return false;
+        if (m < 2 || m > 64 || (m & (m - 1))) return false;
         if (c.unroll != 1) return false;  // fully unrolled
     }
     if (ctx->integ == MD_INTEG_RK4 && (ctx->mask & MD_AERO_DW) && c.lpd != 1) return false;

@@ -2,8 +2,9 @@
 environments all have one power-of-two size, interleaved in their wave, it
 gives bitwise the rows and state of the wave-permute sweep (pair_symmetric
 2) for every size 2..64, partially filled waves, empty environments, several
-waves per workgroup, domain randomisation and wind; per-step parity with the
-oracle; the configuration is refused where it does not apply."""
+waves per workgroup, domain randomisation and wind, and in the RK4 kernel;
+per-step parity with the oracle; the configuration is refused where it does
+not apply."""
 import numpy as np
 import pytest
 
@@ -95,8 +96,9 @@ def test_refused_where_it_does_not_apply():
     with pytest.raises(md.MdError):
         md.md_set_launch_config(g.ctx, lanes_per_drone=1, unroll=2, waves_per_group=1, pair_symmetric=3)
     md.md_set_launch_config(g.ctx, **cfg(3))
-    md.md_set_integrator(g.ctx, md.MD_INTEG_RK4)  # falls back to a configuration the RK4 kernel runs
-    assert md.md_get_launch_config(g.ctx)["pair_symmetric"] != 3
-    with pytest.raises(md.MdError):
-        md.md_set_launch_config(g.ctx, **cfg(3))
     g.close()
+
+
+def test_rk4_bitwise_equal_to_wave_permute_sweep():
+    _same(dict(_uniform(32, 37, 75), integrator="rk4"), 2)
+    _same(dict(_uniform(8, 37, 76), integrator="rk4"), 1)
