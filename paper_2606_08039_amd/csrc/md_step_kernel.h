@@ -7,7 +7,8 @@
 // HBM sees the state once in and once out, the per-step actions (RPM mode)
 // and the per-step observation rows.  Positions are published to LDS every
 // step (double buffered, one barrier per step) so that each drone can sweep
-// its environment for the pairwise downwash of Eq. 6.
+// its environment for the pairwise downwash of Eq. 6 with one of the sweeps
+// of md_sweep.h.
 //
 // Physics per step (paper: Sec. "Quadrotor Dynamics", Sec. "Physics Modes"):
 //   rotor speeds   RPM action clipped to [0, MAX_RPM] or a controller (Sec. "Control")
@@ -25,8 +26,12 @@
 // an actuator chain before the motor model: action latency through a ring of
 // MD_DR_HIST past actions, per-motor bias, clip to the drone's MAX_RPM, and a
 // first-order motor lag n <- n + (1 - e^{-dt/tau})(c - n).  Controllers keep
-// the nominal constants.  Wind (Sec. "Wind and turbulence"): constant-wind
-// drag, gusts, Dryden turbulence and a sinusoid, with per-drone state in
+// the nominal constants.  The returned observation rows carry the sensor
+// side: a sticky per-drone bias, per-step Gaussian noise and a sensor
+// latency ring of MD_DR_OBS_HIST rows.  Both latency rings are read and
+// written only across launch boundaries (see the step loop).  Wind (Sec.
+// "Wind and turbulence"): constant-wind drag (optionally a mean wind per
+// drone), gusts, Dryden turbulence and a sinusoid, with per-drone state in
 // registers and Philox4x32-10 draws keyed by (drone, global step).
 #pragma once
 
