@@ -326,6 +326,8 @@ def main():
     ap.add_argument("--no-rk4", action="store_true", help="skip the Runge-Kutta leg")
     ap.add_argument("--no-dr", action="store_true", help="skip the domain-randomisation leg")
     ap.add_argument("--no-wind", action="store_true", help="skip the wind leg")
+    ap.add_argument("--no-compute-only", action="store_true",
+                    help="skip plain_no_obs (the same launches without observation writes)")
     ap.add_argument("--no-tune", action="store_true", help="default launch configuration, no autotuning")
     ap.add_argument("--config", default=None,
                     help="launch configuration lanes_per_drone,unroll,waves_per_group,pair_symmetric "
@@ -399,7 +401,7 @@ def main():
         "algorithmic_bytes_per_launch": bytes_,
         "algorithmic_flop_per_launch": flop,
     }
-    if with_obs:
+    if with_obs and not args.no_compute_only:
         # the same launches without observation writes, in the same launch
         # configuration: the compute side of the step kernel alone
         wall0, kms0, _, _, _ = timed_rollouts(args, w, p, False, tune=False, config=launch_cfg)
