@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmd.so")
 
-HIP_SOURCES = ["md_step.hip", "md_step_dr.hip", "md_rk4.hip", "md_mlp.hip", "md_surrogate.hip"]
+HIP_SOURCES = ["md_step.hip", "md_step_dr.hip", "md_step_wind.hip", "md_rk4.hip", "md_mlp.hip", "md_surrogate.hip"]
 CPP_SOURCES = ["md_api.cpp", "md_extras.cpp", "md_tune.cpp"]
 
 ARCH = "gfx950"

@@ -333,8 +333,9 @@ md_status launch(md_ctx *ctx, const md_state *s, const float *d_action, int acti
     a.bins = BinTables{bs->d_slot, bs->d_mmax};
     a.tstride = pair_stride(ctx->max_m);
     hipError_t e = (ctx->integ == MD_INTEG_RK4) ? launch_step_rk4(a, ctx->mask, ctx->act, cfg, bs->n_bins, bs->slots, st)
-                   : (ctx->dr_on || ctx->wind.models) ? launch_step_dr(a, ctx->mask, ctx->act, cfg, bs->n_bins, bs->slots, st)
-                                               : launch_step(a, ctx->mask, ctx->act, cfg, bs->n_bins, bs->slots, st);
+                   : ctx->dr_on ? launch_step_dr(a, ctx->mask, ctx->act, cfg, bs->n_bins, bs->slots, st)
+                   : ctx->wind.models ? launch_step_wind(a, ctx->mask, ctx->act, cfg, bs->n_bins, bs->slots, st)
+                                      : launch_step(a, ctx->mask, ctx->act, cfg, bs->n_bins, bs->slots, st);
     if (e != hipSuccess) {
         ctx->err = hip_msg("step kernel launch", e);
         return MD_E_HIP;

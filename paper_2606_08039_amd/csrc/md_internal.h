@@ -115,6 +115,8 @@ hipError_t launch_step(const StepArgs &a, uint32_t mask, int act, const LaunchCf
 // Same contract with per-drone domain randomisation (a.dr).
 hipError_t launch_step_dr(const StepArgs &a, uint32_t mask, int act, const LaunchCfg &cfg,
                           int n_bins, int slots, hipStream_t stream);
+hipError_t launch_step_wind(const StepArgs &a, uint32_t mask, int act, const LaunchCfg &cfg,
+                          int n_bins, int slots, hipStream_t stream);
 // Same contract with the classic Runge-Kutta integrator (lanes per drone 1).
 hipError_t launch_step_rk4(const StepArgs &a, uint32_t mask, int act, const LaunchCfg &cfg,
                            int n_bins, int slots, hipStream_t stream);

@@ -6,7 +6,7 @@ namespace md {
 
 hipError_t launch_step(const StepArgs &a, uint32_t mask, int act, const LaunchCfg &cfg,
                        int n_bins, int slots, hipStream_t stream) {
-    return launch_step_t<false>(a, mask, act, cfg, n_bins, slots, stream);
+    return launch_step_t<0>(a, mask, act, cfg, n_bins, slots, stream);
 }
 
 }  // namespace md

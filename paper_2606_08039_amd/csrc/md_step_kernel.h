@@ -18,7 +18,9 @@
 //   downwash       sum over higher drones j of -C1 (r_p/4dz)^2 exp(-(dxy/beta)^2/2) (Eq. 6)
 //   integrator     semi-implicit Euler, body-rate exponential map, renormalise (Eq. 7)
 //
-// Disturbed instantiation (DR = true): domain randomisation and wind.
+// Disturbed instantiations: DIST = 2 domain randomisation (with or without
+// wind), DIST = 1 wind alone (without the randomisation's registers),
+// DIST = 0 the nominal step.
 // Domain randomisation (Sec. "Domain randomization", Table
 // "Recommended domain-randomization ranges"): each drone carries its own
 // physical constants (mass, inertia, arm length, kf, km, drag, C_gnd, C1, g,
@@ -199,7 +201,7 @@ __device__ __forceinline__ void store_obs_lane(float *obs, int slot, int N, int 
     for (int k = 0; k < 20; ++k) b[(long long)k * N] = row[k];
 }
 
-template <uint32_t MASK, int ACT, int LPD, int UNROLL, int SYM, bool DR>
+template <uint32_t MASK, int ACT, int LPD, int UNROLL, int SYM, int DIST>
 __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     extern __shared__ float4 lds_pos[];  // [2][2 * slots] positions; then T [slots][tstride] (SYM)
     const KConst &c = a.c;
@@ -241,21 +243,21 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     } else {
         d.qw = 1.f;
     }
-    // Physical constants of this drone (the nominal ones unless DR).
+    // Physical constants of this drone (the nominal ones without randomisation).
     KConst cl = c;
     float bias[4] = {1.f, 1.f, 1.f, 1.f};
     float lag = 1.f;            // 1 - e^{-dt/tau}
     bool has_lag = false;
     int delay = 0, acnt0 = 0;  // action latency (steps, clamped to the ring) and ring fill at launch
     float cmdh[4] = {0.f, 0.f, 0.f, 0.f};  // controller output held between updates
-    // The disturbed instantiation also serves wind alone: randomisation (the
-    // factor table, lag, latency, the held-command block) is on only when the
+    // Randomisation (the factor table, lag, latencies, the held-command block,
+    // the sensor side) runs only in the DIST = 2 instantiation and when the
     // context has a factor table; otherwise the plain actuator chain runs and
-    // rpm_cmd / act_hist / act_count are never touched.
-    const bool rnd = DR && a.dr.scale != nullptr;
+    // rpm_cmd / act_hist / act_count / obs_hist / obs_count are never touched.
+    const bool rnd = DIST == 2 && a.dr.scale != nullptr;
     const bool ring = rnd && a.dr.delay != nullptr;
     float ws[5] = {0.f, 0.f, 0.f, -1.f, 0.f};  // wind state
-    const bool windy = DR && a.wind.models != 0u;
+    const bool windy = DIST >= 1 && a.wind.models != 0u;
     if (windy && valid && a.s.wind != nullptr)
         for (int k = 0; k < 5; ++k) ws[k] = a.s.wind[k * N + di];
     if (rnd && valid) {
@@ -489,59 +491,59 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     }
 }
 
-template <uint32_t MASK, int ACT, int LPD, int SYM, bool DR>
+template <uint32_t MASK, int ACT, int LPD, int SYM, int DIST>
 hipError_t launch_u(const StepArgs &a, int unroll, int n_bins, int threads, size_t lds, hipStream_t st) {
     switch (unroll) {
-        case 1: hipLaunchKernelGGL((step_kernel<MASK, ACT, LPD, 1, SYM, DR>), dim3(n_bins), dim3(threads), lds, st, a); break;
-        case 2: hipLaunchKernelGGL((step_kernel<MASK, ACT, LPD, 2, SYM, DR>), dim3(n_bins), dim3(threads), lds, st, a); break;
-        case 4: hipLaunchKernelGGL((step_kernel<MASK, ACT, LPD, 4, SYM, DR>), dim3(n_bins), dim3(threads), lds, st, a); break;
+        case 1: hipLaunchKernelGGL((step_kernel<MASK, ACT, LPD, 1, SYM, DIST>), dim3(n_bins), dim3(threads), lds, st, a); break;
+        case 2: hipLaunchKernelGGL((step_kernel<MASK, ACT, LPD, 2, SYM, DIST>), dim3(n_bins), dim3(threads), lds, st, a); break;
+        case 4: hipLaunchKernelGGL((step_kernel<MASK, ACT, LPD, 4, SYM, DIST>), dim3(n_bins), dim3(threads), lds, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <uint32_t MASK, int ACT, bool DR>
+template <uint32_t MASK, int ACT, int DIST>
 hipError_t launch_l(const StepArgs &a, const LaunchCfg &cfg, int n_bins, int threads, size_t lds,
                     hipStream_t st) {
     if (!(MASK & 4u)) {
         // no neighbour sweep: one lane per drone, no loop to tune
-        hipLaunchKernelGGL((step_kernel<MASK, ACT, 1, 1, 0, DR>), dim3(n_bins), dim3(threads), lds, st, a);
+        hipLaunchKernelGGL((step_kernel<MASK, ACT, 1, 1, 0, DIST>), dim3(n_bins), dim3(threads), lds, st, a);
         return hipGetLastError();
     }
     if (cfg.sym) {
         if (cfg.lpd != 1) return hipErrorInvalidValue;
         if (cfg.sym == 3) {
             // the rotation sweep is fully unrolled: no unroll variants
-            hipLaunchKernelGGL((step_kernel<MASK, ACT, 1, 1, 3, DR>), dim3(n_bins), dim3(threads), lds, st, a);
+            hipLaunchKernelGGL((step_kernel<MASK, ACT, 1, 1, 3, DIST>), dim3(n_bins), dim3(threads), lds, st, a);
             return hipGetLastError();
         }
-        return cfg.sym == 2 ? launch_u<MASK, ACT, 1, 2, DR>(a, cfg.unroll, n_bins, threads, lds, st)
-                            : launch_u<MASK, ACT, 1, 1, DR>(a, cfg.unroll, n_bins, threads, lds, st);
+        return cfg.sym == 2 ? launch_u<MASK, ACT, 1, 2, DIST>(a, cfg.unroll, n_bins, threads, lds, st)
+                            : launch_u<MASK, ACT, 1, 1, DIST>(a, cfg.unroll, n_bins, threads, lds, st);
     }
     switch (cfg.lpd) {
-        case 1: return launch_u<MASK, ACT, 1, 0, DR>(a, cfg.unroll, n_bins, threads, lds, st);
-        case 2: return launch_u<MASK, ACT, 2, 0, DR>(a, cfg.unroll, n_bins, threads, lds, st);
-        case 4: return launch_u<MASK, ACT, 4, 0, DR>(a, cfg.unroll, n_bins, threads, lds, st);
+        case 1: return launch_u<MASK, ACT, 1, 0, DIST>(a, cfg.unroll, n_bins, threads, lds, st);
+        case 2: return launch_u<MASK, ACT, 2, 0, DIST>(a, cfg.unroll, n_bins, threads, lds, st);
+        case 4: return launch_u<MASK, ACT, 4, 0, DIST>(a, cfg.unroll, n_bins, threads, lds, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <int ACT, bool DR>
+template <int ACT, int DIST>
 hipError_t launch_m(const StepArgs &a, uint32_t mask, const LaunchCfg &cfg, int n_bins,
                     int threads, size_t lds, hipStream_t st) {
     switch (mask & 7u) {
-        case 0: return launch_l<0, ACT, DR>(a, cfg, n_bins, threads, lds, st);
-        case 1: return launch_l<1, ACT, DR>(a, cfg, n_bins, threads, lds, st);
-        case 2: return launch_l<2, ACT, DR>(a, cfg, n_bins, threads, lds, st);
-        case 3: return launch_l<3, ACT, DR>(a, cfg, n_bins, threads, lds, st);
-        case 4: return launch_l<4, ACT, DR>(a, cfg, n_bins, threads, lds, st);
-        case 5: return launch_l<5, ACT, DR>(a, cfg, n_bins, threads, lds, st);
-        case 6: return launch_l<6, ACT, DR>(a, cfg, n_bins, threads, lds, st);
-        default: return launch_l<7, ACT, DR>(a, cfg, n_bins, threads, lds, st);
+        case 0: return launch_l<0, ACT, DIST>(a, cfg, n_bins, threads, lds, st);
+        case 1: return launch_l<1, ACT, DIST>(a, cfg, n_bins, threads, lds, st);
+        case 2: return launch_l<2, ACT, DIST>(a, cfg, n_bins, threads, lds, st);
+        case 3: return launch_l<3, ACT, DIST>(a, cfg, n_bins, threads, lds, st);
+        case 4: return launch_l<4, ACT, DIST>(a, cfg, n_bins, threads, lds, st);
+        case 5: return launch_l<5, ACT, DIST>(a, cfg, n_bins, threads, lds, st);
+        case 6: return launch_l<6, ACT, DIST>(a, cfg, n_bins, threads, lds, st);
+        default: return launch_l<7, ACT, DIST>(a, cfg, n_bins, threads, lds, st);
     }
 }
 
-template <bool DR>
+template <int DIST>
 hipError_t launch_step_t(const StepArgs &a, uint32_t mask, int act, const LaunchCfg &cfg, int n_bins,
                          int slots, hipStream_t stream) {
     if (n_bins <= 0 || a.n_steps <= 0) return hipSuccess;
@@ -550,11 +552,11 @@ hipError_t launch_step_t(const StepArgs &a, uint32_t mask, int act, const Launch
     size_t lds = (mask & 4u) ? sizeof(float4) * 2 * 2 * (size_t)slots : 0;
     if ((mask & 4u) && cfg.sym == 1) lds += sizeof(float) * (size_t)slots * (size_t)a.tstride;
     switch (act) {
-        case 0: return launch_m<0, DR>(a, mask, cfg, n_bins, threads, lds, stream);
-        case 1: return launch_m<1, DR>(a, mask, cfg, n_bins, threads, lds, stream);
-        case 2: return launch_m<2, DR>(a, mask, cfg, n_bins, threads, lds, stream);
-        case 3: return launch_m<3, DR>(a, mask, cfg, n_bins, threads, lds, stream);
-        default: return launch_m<4, DR>(a, mask, cfg, n_bins, threads, lds, stream);
+        case 0: return launch_m<0, DIST>(a, mask, cfg, n_bins, threads, lds, stream);
+        case 1: return launch_m<1, DIST>(a, mask, cfg, n_bins, threads, lds, stream);
+        case 2: return launch_m<2, DIST>(a, mask, cfg, n_bins, threads, lds, stream);
+        case 3: return launch_m<3, DIST>(a, mask, cfg, n_bins, threads, lds, stream);
+        default: return launch_m<4, DIST>(a, mask, cfg, n_bins, threads, lds, stream);
     }
 }
 
