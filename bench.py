@@ -288,6 +288,56 @@ def dr_leg(args, w, p, with_obs):
                                   "kernel_ms_avg": float(np.mean(kernel_ms_d)), "launch_config": cfg_d}}
 
 
+def ragged_graph_leg(args, p, hover):
+    """The latency-bound ragged layout (1024 environments of 2..32 drones on a
+    coplanar grid, 17.4k drones, per-step rotor speeds, all aero terms): a
+    100-step rollout as 10 launches of 10 steps, replayed from one captured
+    hipGraph against the same launches issued eagerly."""
+    import torch
+    from paper_2606_08039_amd import md, workloads as wl
+    w = wl.ragged_grid(hover, n_envs=1024, n_steps=100, seed=2)
+    n = int(w["env_offsets"][-1])
+    ctx = md.md_create(p, w["dt"], w["aero_mask"], md.MD_ACT_RPM, 1)
+    try:
+        md.md_bind_layout(ctx, w["env_offsets"])
+        state = md.DeviceState.from_numpy(w["state"])
+        action = torch.from_numpy(np.ascontiguousarray(w["action"], dtype=np.float32)).cuda()
+        stream = torch.cuda.current_stream()
+        cfg = md.md_autotune(ctx, state, action[:10].contiguous(), True, n_steps=10, stream=stream, cache_path="")
+        reps = 20
+        # eager: ten 10-step launches per rollout
+        t_eager = []
+        for r in range(reps + 2):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for k in range(10):
+                md.md_step(ctx, state, action[10 * k:10 * k + 10].contiguous(), True, None, 0, 10, 10 * k, stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            if r >= 2:
+                t_eager.append(a.elapsed_time(b))
+        graph = md.md_rollout_graph_create(ctx, state, action, True, None, 0, steps_per_launch=10,
+                                           n_launches=10, step0=0, stream=stream)
+        t_graph = []
+        try:
+            for r in range(reps + 2):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                md.md_graph_launch(graph, stream)
+                b.record(stream)
+                torch.cuda.synchronize()
+                if r >= 2:
+                    t_graph.append(a.elapsed_time(b))
+        finally:
+            md.md_graph_destroy(graph)
+    finally:
+        md.md_destroy(ctx)
+    mg, me = float(np.median(t_graph)), float(np.median(t_eager))
+    return {"value": float(n) * 100 / (mg * 1e-3), "unit": "drone-steps/s", "n_drones": n,
+            "rollout_ms_graph_median": mg, "rollout_ms_eager_median": me, "replays": reps,
+            "launch_config": cfg, "workload": "ragged_grid_1024envs_m2to32_rpm_gnd_drag_dw_100steps"}
+
+
 # Sec. "Wind and turbulence", the paper's hover example: a steady 0.9 m/s
 # wind along +y plus Dryden turbulence (per-drone Philox draws).
 WIND_BENCH = dict(models=1 | 4, v_mean=(0.0, 0.9, 0.0), rho=1.225, cd_area=0.01, dryden_sigma=0.3,
@@ -326,6 +376,7 @@ def main():
     ap.add_argument("--no-rk4", action="store_true", help="skip the Runge-Kutta leg")
     ap.add_argument("--no-dr", action="store_true", help="skip the domain-randomisation leg")
     ap.add_argument("--no-wind", action="store_true", help="skip the wind leg")
+    ap.add_argument("--no-graph", action="store_true", help="skip the ragged-layout hipGraph leg")
     ap.add_argument("--no-compute-only", action="store_true",
                     help="skip plain_no_obs (the same launches without observation writes)")
     ap.add_argument("--no-tune", action="store_true", help="default launch configuration, no autotuning")
@@ -421,6 +472,8 @@ def main():
     if not args.no_dr:
         out["domain_randomization"] = dr_leg(args, w, p, with_obs)
         out["domain_randomization"]["speed_vs_plain"] = out["domain_randomization"]["value"] / value
+    if not args.no_graph:
+        out["ragged_graph"] = ragged_graph_leg(args, p, hover)
     if not args.no_wind:
         out["wind"] = wind_leg(args, w, p, with_obs)
         out["wind"]["speed_vs_plain"] = out["wind"]["value"] / value
