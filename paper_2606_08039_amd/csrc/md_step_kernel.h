@@ -201,6 +201,32 @@ __device__ __forceinline__ void store_obs_lane(float *obs, int slot, int N, int 
     for (int k = 0; k < 20; ++k) b[(long long)k * N] = row[k];
 }
 
+// The previous step's observation row, stored a few rows at a time after the
+// segments of the rotation sweep (rows [s 20 / (H + 1), (s + 1) 20 / (H + 1))
+// after segment s of H + 1).  Stored in one burst per step, the rows of every
+// wave leave the vector ALU and the write stream taking turns; spread through
+// the sweep they overlap.  No branch enters the sweep: the buffer range is
+// the slot's 20 rows (the range check counts the scalar row offset), and an
+// idle lane's offset of 20 N * 4 lies past it for every row, so the hardware
+// drops its stores (the offsets stay below 2^32 for N <= 2^24).
+struct RowSeg {
+    __amdgpu_buffer_rsrc_t rs;
+    int voff, rowbytes;
+    float v[20];
+    __device__ __forceinline__ void all() const {
+#pragma unroll
+        for (int r = 0; r < 20; ++r)
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[r]), rs, voff, r * rowbytes, 0);
+    }
+    template <int H>
+    __device__ __forceinline__ void at(int s) const {
+        const int r0 = s * 20 / (H + 1), r1 = (s + 1) * 20 / (H + 1);
+#pragma unroll
+        for (int r = r0; r < r1; ++r)
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[r]), rs, voff, r * rowbytes, 0);
+    }
+};
+
 template <uint32_t MASK, int ACT, int LPD, int UNROLL, int SYM, int DIST>
 __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     extern __shared__ float4 lds_pos[];  // [2][2 * slots] positions; then T [slots][tstride] (SYM)
@@ -311,6 +337,16 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     int phase = (ACT >= 1) ? (int)(a.step0 % (long long)c.decim) : 0;
     int oslot = 0;
     int hslot = (int)(a.step0 % (long long)MD_DR_HIST);
+    // Nominal step with the rotation sweep: each observation row is stored
+    // during the next step between the sweep's segments (RowSeg); the state
+    // is still that row until the integration, its angles (computed where the
+    // row is complete) and rotor speeds are kept in rpy and nprev, and the
+    // launch's last row is stored after the loop.
+    constexpr bool seg_obs = DIST == 0 && SYM == 3 && (MASK & 4u) && LPD == 1;
+    const bool seg_on = seg_obs && a.obs != nullptr && N <= (1 << 24);  // uniform
+    float nprev[4] = {0.f, 0.f, 0.f, 0.f};
+    float rpy[3] = {0.f, 0.f, 0.f};  // the previous row's angles, computed right after its integration
+    int pslot = 0;
     for (int step = 0; step < a.n_steps; ++step) {
         float4 *buf = lds_pos + (step & 1) * (2 * slots);
         if (MASK & 4u) {
@@ -388,8 +424,24 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         }
         // ---- downwash (Eq. 6): sweep the environment in ascending order
         if (MASK & 4u) {
-            const float acc = dw_sum<LPD, UNROLL, SYM>(c, buf, tmat, a.tstride, slot, sub, lo, mmax, menv,
-                                                       uniform, d);
+            float acc;
+            if (seg_obs) {
+                const int lane = slot & 63;
+                const float4 *own = buf + 2 * (slot - lane) + lane;
+                if (seg_on && step > 0) {
+                    const RowSeg seg{__builtin_amdgcn_make_buffer_rsrc(a.obs + (long long)pslot * 20 * N, (short)0,
+                                                                       20 * N * 4, 0x00020000),
+                                     writer ? di * 4 : 20 * N * 4, N * 4,
+                                     {d.px, d.py, d.pz, d.qw, d.qx, d.qy, d.qz, rpy[0], rpy[1], rpy[2],
+                                      d.vx, d.vy, d.vz, d.wx, d.wy, d.wz, nprev[0], nprev[1], nprev[2], nprev[3]}};
+                    acc = c.dz_min > 0.f ? dw_rot<true>(c, own, lane, mmax, d, seg)
+                                         : dw_rot<false>(c, own, lane, mmax, d, seg);
+                } else {
+                    acc = c.dz_min > 0.f ? dw_rot<true>(c, own, lane, mmax, d) : dw_rot<false>(c, own, lane, mmax, d);
+                }
+            } else {
+                acc = dw_sum<LPD, UNROLL, SYM>(c, buf, tmat, a.tstride, slot, sub, lo, mmax, menv, uniform, d);
+            }
             Fz -= cl.K1 * acc;
         }
         // ---- wind
@@ -404,7 +456,11 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         integrate(cl, d, Fx, Fy, Fz, tx, ty, tz);
         // ---- KIN observation
         const bool otail = oring && step >= a.n_steps - MD_DR_OBS_HIST;
-        if ((a.obs != nullptr || otail) && writer) {
+        if (seg_on) {
+            euler_zyx(d, rpy[0], rpy[1], rpy[2]);
+            for (int k = 0; k < 4; ++k) nprev[k] = n[k];
+            pslot = oslot;
+        } else if ((a.obs != nullptr || otail) && writer) {
             float roll, pitch, yaw;
             euler_zyx(d, roll, pitch, yaw);
             float orow[20] = {d.px, d.py, d.pz, d.qw, d.qx, d.qy, d.qz, roll, pitch, yaw,
@@ -448,6 +504,11 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         }
         oslot = (oslot + 1 == a.n_obs_slots) ? 0 : oslot + 1;
         if (oring) osl = (osl + 1 == MD_DR_OBS_HIST) ? 0 : osl + 1;
+    }
+    if (seg_on && writer && a.n_steps > 0) {
+        const float orow[20] = {d.px, d.py, d.pz, d.qw, d.qx, d.qy, d.qz, rpy[0], rpy[1], rpy[2],
+                                d.vx, d.vy, d.vz, d.wx, d.wy, d.wz, n[0], n[1], n[2], n[3]};
+        store_obs(a.obs, pslot, N, di, orow);
     }
 
     if (writer) {

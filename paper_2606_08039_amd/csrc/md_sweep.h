@@ -144,8 +144,19 @@ __device__ __forceinline__ float dw_pairs_shfl(const KConst &c0, const float4 *b
 // wave's 128), so the partner's entry is a fixed offset from the lane's own,
 // and the permute address wraps in hardware (lane bits of the byte address);
 // with k unrolled neither costs an instruction.
-template <bool DZMIN, int E>
-__device__ __forceinline__ float dw_pairs_rot(const KConst &c0, const float4 *own, int lane, const Drone &d) {
+// `seg.at<H>(s)` runs after each of the H + 1 segments (shifts 1..H, then
+// the half pair), s = 0..H, and `seg.all()` after a sweep that takes no hook:
+// the caller's work to interleave with the sweep (the step kernel's
+// observation stores).
+struct NoSeg {
+    template <int H>
+    __device__ __forceinline__ void at(int) const {}
+    __device__ __forceinline__ void all() const {}
+};
+
+template <bool DZMIN, int E, class Seg = NoSeg>
+__device__ __forceinline__ float dw_pairs_rot(const KConst &c0, const float4 *own, int lane, const Drone &d,
+                                              const Seg &seg = Seg()) {
     constexpr int M = 64 / E;
     constexpr int H = (M - 1) / 2;
     const KConst c = pair_consts(c0);
@@ -161,6 +172,7 @@ __device__ __forceinline__ float dw_pairs_rot(const KConst &c0, const float4 *ow
         const float recv = __int_as_float(__builtin_amdgcn_ds_bpermute(pa + (256 - 4 * E * k), __float_as_int(theirs)));
         acc += mine;
         acc += recv;
+        seg.template at<H>(k - 1);
     }
     {
         // M is even: the pair at distance M / 2 (lane + 32), kept by the lower drone
@@ -169,18 +181,25 @@ __device__ __forceinline__ float dw_pairs_rot(const KConst &c0, const float4 *ow
         const float t = dw_term<DZMIN>(c, q.x - d.px, q.y - d.py, fabsf(dz));
         acc += dz > 0.f ? t : 0.f;
     }
+    seg.template at<H>(H);
     return acc;
 }
 
-template <bool DZMIN>
-__device__ __forceinline__ float dw_rot(const KConst &c, const float4 *own, int lane, int m, const Drone &d) {
+template <bool DZMIN, class Seg = NoSeg>
+__device__ __forceinline__ float dw_rot(const KConst &c, const float4 *own, int lane, int m, const Drone &d,
+                                        const Seg &seg = Seg()) {
     switch (m) {
-        case 64: return dw_pairs_rot<DZMIN, 1>(c, own, lane, d);
-        case 32: return dw_pairs_rot<DZMIN, 2>(c, own, lane, d);
-        case 16: return dw_pairs_rot<DZMIN, 4>(c, own, lane, d);
-        case 8: return dw_pairs_rot<DZMIN, 8>(c, own, lane, d);
-        case 4: return dw_pairs_rot<DZMIN, 16>(c, own, lane, d);
-        default: return dw_pairs_rot<DZMIN, 32>(c, own, lane, d);
+        case 64: {
+            // 31 shifts unrolled leave no registers for interleaved stores
+            const float r = dw_pairs_rot<DZMIN, 1>(c, own, lane, d);
+            seg.all();
+            return r;
+        }
+        case 32: return dw_pairs_rot<DZMIN, 2>(c, own, lane, d, seg);
+        case 16: return dw_pairs_rot<DZMIN, 4>(c, own, lane, d, seg);
+        case 8: return dw_pairs_rot<DZMIN, 8>(c, own, lane, d, seg);
+        case 4: return dw_pairs_rot<DZMIN, 16>(c, own, lane, d, seg);
+        default: return dw_pairs_rot<DZMIN, 32>(c, own, lane, d, seg);
     }
 }
 
