@@ -14,8 +14,9 @@
 //
 // MFMA data flow per wave (64 drones = 4 column tiles of 16 drones):
 //   Z^T[out][drone] = W[out][in] X^T[in][drone].  A operand = weight rows read
-//   from global memory (L2-resident, 84 KB bf16 for all layers), B operand =
-//   activations.  The 16x16 C tile leaves lane l holding rows 4*(l/16)+t of
+//   from global memory (L2-resident, 84 KB bf16 for all layers, stored
+//   fragment-major so that each wave-wide fragment load is 1 KB in order, and
+//   requested one output tile ahead of its use), B operand = activations.  The 16x16 C tile leaves lane l holding rows 4*(l/16)+t of
 //   drone l%16, which is exactly half of the next layer's B fragment for a
 //   32-wide K chunk; the host permutes the K columns of layers 2-4 to match,
 //   so activations never leave registers between layers.
@@ -46,7 +47,7 @@ constexpr int BOFF1 = 0, BOFF2 = 128, BOFF3 = 256, BOFF4 = 384, BTOTAL = 400;
 enum { J_ERR2 = 0, J_REF2, J_TERR2, J_N, J_FALLBACK, J_STEPS, J_NONFINITE, J_COUNT };
 
 struct SurrogateState {
-    bf16 *W = nullptr;      // permuted bf16 weights [WTOTAL]
+    bf16 *W = nullptr;      // permuted bf16 weights [WTOTAL], fragment-major per layer
     float *b = nullptr;     // biases [BTOTAL]
     float *norm = nullptr;  // x_mean[64], x_inv_std[64], y_mean[6], y_std[6]
     double *judge = nullptr;
@@ -219,43 +220,48 @@ __device__ __forceinline__ float tilt_sq(const Drone &d) {
 
 __device__ __forceinline__ float silu(float z) { return z * __builtin_amdgcn_rcpf(1.f + __expf(-z)); }
 
-__device__ __forceinline__ bf16x8 ldw(const bf16 *p) { return *(const bf16x8 *)p; }
+// Weight fragments are read through a global (address space 1) pointer, so
+// that their loads count on the vector-memory counter alone and the wait for
+// one fragment does not also wait for the LDS traffic in flight.
+typedef const __attribute__((address_space(1))) bf16x8 gbf16x8;
+typedef const __attribute__((address_space(1))) f32x4 gf32x4;
 
-__device__ __forceinline__ f32x4 ldb(const float *p) { return *(const f32x4 *)p; }
+__device__ __forceinline__ bf16x8 ldw(const bf16 *p) { return *(gbf16x8 *)p; }
+
+__device__ __forceinline__ f32x4 ldb(const float *p) { return *(gf32x4 *)p; }
 
 // Drone tiles (16 drones each) evaluated together by one pass of the network.
 constexpr int DT = 2;
 
-// One hidden layer for DT drone tiles: hout[ot][dt] = SiLU(W hin + b) as
-// bfloat16, K = 128 (4 chunks of 32), inputs in the permuted fragment order.
-__device__ __forceinline__ void hidden_layer(const bf16 *W, const float *b, const bf16x4 hin[8][DT],
-                                             bf16x4 hout[8][DT], int lane) {
-    const int r = lane & 15, g = lane >> 4;
+// The network as a stream of output-tile jobs: 8 tiles of 16 rows per hidden
+// layer (layers 1-3) and one for the output layer, 25 per pass.  A job needs
+// its weight fragments (A operands, one per 32-wide K chunk: 2 for layer 1,
+// 4 otherwise) and its 16 biases.
+constexpr int N_JOBS = 3 * 8 + 1;
+
+struct WFrag {
+    bf16x8 a[4];
+    f32x4 b;
+};
+
+__device__ __forceinline__ void load_job(WFrag &w, const bf16 *W, const float *b, int j, int r, int g) {
+    const int layer = j / 8, ot = j % 8;
+    const int kcs = layer == 0 ? 2 : 4;
+    const int woff = layer == 0 ? WOFF1 : layer == 1 ? WOFF2 : layer == 2 ? WOFF3 : WOFF4;
+    const int boff = layer == 0 ? BOFF1 : layer == 1 ? BOFF2 : layer == 2 ? BOFF3 : BOFF4;
 #pragma unroll
-    for (int ot = 0; ot < 8; ++ot) {
-        const f32x4 bias = ldb(b + 16 * ot + 4 * g);  // the accumulators start at the bias
-        f32x4 acc[DT];
-#pragma unroll
-        for (int kc = 0; kc < 4; ++kc) {
-            const bf16x8 a = ldw(W + (16 * ot + r) * MLP_H + 32 * kc + 8 * g);
-#pragma unroll
-            for (int dt = 0; dt < DT; ++dt) {
-                const bf16x8 bv = __builtin_shufflevector(hin[2 * kc][dt], hin[2 * kc + 1][dt], 0, 1, 2, 3, 4, 5, 6, 7);
-                acc[dt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, kc == 0 ? bias : acc[dt], 0, 0, 0);
-            }
-        }
-#pragma unroll
-        for (int dt = 0; dt < DT; ++dt) {
-#pragma unroll
-            for (int t = 0; t < 4; ++t) hout[ot][dt][t] = (bf16)silu(acc[dt][t]);
-        }
-    }
+    for (int kc = 0; kc < 4; ++kc)
+        if (kc < kcs) w.a[kc] = ldw(W + woff + ((ot * kcs + kc) * 64 + 16 * g + r) * 8);
+    w.b = ldb(b + boff + 16 * ot + 4 * g);
 }
 
 // The network on the 64 drones of one wave, DT tiles of 16 drones per pass:
 // standardised bfloat16 inputs in feat (row per drone), standardised outputs
 // to out (row per drone, 6 used).  Passes reuse the activation registers;
-// the weights (L2-resident) are read once per pass.
+// the weights (L2-resident) are read once per pass.  The weight stream is
+// software pipelined: the fragments of job j + 1 are requested before the
+// MFMAs of job j, and scheduling fences keep them there, so every L2 round
+// trip overlaps a job's work instead of stalling it.
 __device__ __forceinline__ void mlp_wave(const bf16 *feat, float *out, const bf16 *W, const float *b, int lane) {
     const int r = lane & 15, g = lane >> 4;
 #pragma unroll 1
@@ -267,53 +273,72 @@ __device__ __forceinline__ void mlp_wave(const bf16 *feat, float *out, const bf1
         const bf16 *Wv = W;
         const float *bv_ = b;
         asm volatile("" : "+s"(Wv), "+s"(bv_));
+        WFrag cur, nxt;
+        load_job(cur, Wv, bv_, 0, r, g);
+        // layer 1 B fragments straight from the staged rows (K = 64)
+        bf16x8 x[2][DT];
+#pragma unroll
+        for (int kc = 0; kc < 2; ++kc)
+#pragma unroll
+            for (int dt = 0; dt < DT; ++dt)
+                x[kc][dt] = *(const bf16x8 *)(feat + (16 * (t0 + dt) + r) * FEAT_STRIDE + 32 * kc + 8 * g);
         bf16x4 h1[8][DT], h2[8][DT];
-        // layer 1: K = 64, B fragments straight from the staged rows
-        {
-            bf16x8 x[2][DT];
+        // SiLU epilogue of a hidden-layer job: layers 1 and 3 write h1, layer 2 h2
+        auto epilogue = [&](int jj, const f32x4 (&ac)[DT]) {
+            const int layer = jj / 8, ot = jj % 8;
+            bf16x4(&hout)[8][DT] = layer == 1 ? h2 : h1;
 #pragma unroll
-            for (int kc = 0; kc < 2; ++kc)
+            for (int dt = 0; dt < DT; ++dt)
 #pragma unroll
-                for (int dt = 0; dt < DT; ++dt)
-                    x[kc][dt] = *(const bf16x8 *)(feat + (16 * (t0 + dt) + r) * FEAT_STRIDE + 32 * kc + 8 * g);
+                for (int t = 0; t < 4; ++t) hout[ot][dt][t] = (bf16)silu(ac[dt][t]);
+        };
+        f32x4 prev[DT];
 #pragma unroll
-            for (int ot = 0; ot < 8; ++ot) {
-                const f32x4 bias = ldb(bv_ + BOFF1 + 16 * ot + 4 * g);
-                f32x4 acc[DT];
+        for (int j = 0; j < N_JOBS; ++j) {
+            const int layer = j / 8, ot = j % 8;
+            if (j + 1 < N_JOBS) load_job(nxt, Wv, bv_, j + 1, r, g);
+            // the first job of a layer reads every tile of the previous one
+            if (j > 0 && ot == 0) epilogue(j - 1, prev);
+            __builtin_amdgcn_sched_barrier(0);
+            f32x4 acc[DT];
+            if (layer == 0) {
 #pragma unroll
-                for (int kc = 0; kc < 2; ++kc) {
-                    const bf16x8 a = ldw(Wv + WOFF1 + (16 * ot + r) * MLP_IN + 32 * kc + 8 * g);
+                for (int kc = 0; kc < 2; ++kc)
 #pragma unroll
                     for (int dt = 0; dt < DT; ++dt)
-                        acc[dt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, x[kc][dt], kc == 0 ? bias : acc[dt], 0, 0, 0);
-                }
+                        acc[dt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.a[kc], x[kc][dt], kc == 0 ? cur.b : acc[dt],
+                                                                          0, 0, 0);
+            } else {
+                // layers 2 and 4 read h1, layer 3 reads h2
+                const bf16x4(&hin)[8][DT] = layer == 2 ? h2 : h1;
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+                    for (int dt = 0; dt < DT; ++dt) {
+                        const bf16x8 bv =
+                            __builtin_shufflevector(hin[2 * kc][dt], hin[2 * kc + 1][dt], 0, 1, 2, 3, 4, 5, 6, 7);
+                        acc[dt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.a[kc], bv, kc == 0 ? cur.b : acc[dt], 0,
+                                                                          0, 0);
+                    }
+            }
+            // within a layer the previous job's epilogue runs while this
+            // job's MFMAs occupy the matrix pipe
+            if (ot > 0) epilogue(j - 1, prev);
+            if (j == N_JOBS - 1) {
+                // output layer: rows 0..5 used; bias rows 6..15 are 0
 #pragma unroll
                 for (int dt = 0; dt < DT; ++dt)
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) h1[ot][dt][t] = (bf16)silu(acc[dt][t]);
+                    for (int t = 0; t < 4; ++t) {
+                        const int o = 4 * g + t;
+                        if (o < MLP_OUT) out[(16 * (t0 + dt) + r) * OUT_STRIDE + o] = acc[dt][t];
+                    }
             }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int dt = 0; dt < DT; ++dt) prev[dt] = acc[dt];
+            cur = nxt;
         }
-        hidden_layer(Wv + WOFF2, bv_ + BOFF2, h1, h2, lane);
-        hidden_layer(Wv + WOFF3, bv_ + BOFF3, h2, h1, lane);
-        // output layer: one 16-row tile (rows 0..5 used; bias rows 6..15 are 0)
-        const f32x4 bias = ldb(bv_ + BOFF4 + 4 * g);
-        f32x4 acc[DT];
-#pragma unroll
-        for (int kc = 0; kc < 4; ++kc) {
-            const bf16x8 a = ldw(Wv + WOFF4 + r * MLP_H + 32 * kc + 8 * g);
-#pragma unroll
-            for (int dt = 0; dt < DT; ++dt) {
-                const bf16x8 bv = __builtin_shufflevector(h1[2 * kc][dt], h1[2 * kc + 1][dt], 0, 1, 2, 3, 4, 5, 6, 7);
-                acc[dt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, kc == 0 ? bias : acc[dt], 0, 0, 0);
-            }
-        }
-#pragma unroll
-        for (int dt = 0; dt < DT; ++dt)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int o = 4 * g + t;
-                if (o < MLP_OUT) out[(16 * (t0 + dt) + r) * OUT_STRIDE + o] = acc[dt][t];
-            }
     }
 }
 
@@ -381,14 +406,15 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
             }
             phase = (phase + 1 == c.decim) ? 0 : phase + 1;
         }
-        float T, tx, ty, tz;
-        motor(c, n, T, tx, ty, tz);
-        const Rot R = rot_of(d);
         // ---- features -> standardised bfloat16 row
-        int bj[KNN];
-        knn8(pos, lo, menv, mmax, slot, d.px, d.py, bj);
+        bool ood;
         float f[MLP_IN];
-        bool ood = features(c, d, R, n, pos, vel, bj, sa.dz_ood, sa.ood_rel, f);
+        {
+            const Rot R = rot_of(d);
+            int bj[KNN];
+            knn8(pos, lo, menv, mmax, slot, d.px, d.py, bj);
+            ood = features(c, d, R, n, pos, vel, bj, sa.dz_ood, sa.ood_rel, f);
+        }
         // outside the trained region: fast or tilted drones take the plain terms
         ood |= sa.ood_speed > 0.f &&
                (fabsf(d.vx) > sa.ood_speed || fabsf(d.vy) > sa.ood_speed || fabsf(d.vz) > sa.ood_speed);
@@ -405,6 +431,14 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
         __syncthreads();
         mlp_wave(feat + wbase * FEAT_STRIDE, outs + wbase * OUT_STRIDE, sa.W, sa.b, lane);
         __syncthreads();
+        // the rotation and the rotor terms are formed from the (unchanged)
+        // attitude and rotor speeds after the network instead of being held in
+        // registers across it; the empty asm keeps them from being reused
+        asm volatile("" : "+v"(d.qw), "+v"(d.qx), "+v"(d.qy), "+v"(d.qz), "+v"(n[0]), "+v"(n[1]), "+v"(n[2]),
+                     "+v"(n[3]));
+        float T, tx, ty, tz;
+        motor(c, n, T, tx, ty, tz);
+        const Rot R = rot_of(d);
         float y[MLP_OUT];
 #pragma unroll
         for (int o = 0; o < MLP_OUT; ++o) y[o] = outs[slot * OUT_STRIDE + o] * ysd[o] + ym[o];
@@ -622,6 +656,22 @@ md_status load_surrogate(md_ctx *ctx, const float *params, const float *norm, fl
         for (int kc = 0; kc < 4; ++kc)
             for (int s = 0; s < 32; ++s)
                 W[WOFF4 + o * MLP_H + 32 * kc + s] = (bf16)W4[o * MLP_H + 32 * kc + permuted_unit(s)];
+    // fragment-major order: the A fragment of (output tile, K chunk) for all 64
+    // lanes stored contiguously, lane l = r + 16 g holding row 16 ot + r,
+    // columns 32 kc + 8 g .. + 7, so each wave-wide load reads 1 KB in order
+    std::vector<bf16> F(WTOTAL, (bf16)0.f);
+    const int loff[4] = {WOFF1, WOFF2, WOFF3, WOFF4}, lk[4] = {MLP_IN, MLP_H, MLP_H, MLP_H},
+              lrows[4] = {MLP_H, MLP_H, MLP_H, W4_ROWS};
+    for (int l = 0; l < 4; ++l) {
+        const int kcs = lk[l] / 32;
+        for (int ot = 0; ot < lrows[l] / 16; ++ot)
+            for (int kc = 0; kc < kcs; ++kc)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int t = 0; t < 8; ++t)
+                        F[loff[l] + ((ot * kcs + kc) * 64 + lane) * 8 + t] =
+                            W[loff[l] + (16 * ot + lane % 16) * lk[l] + 32 * kc + 8 * (lane / 16) + t];
+    }
+    W.swap(F);
     for (int i = 0; i < MLP_H; ++i) {
         b[BOFF1 + i] = params[kParamOff[1] + i];
         b[BOFF2 + i] = params[kParamOff[3] + i];
