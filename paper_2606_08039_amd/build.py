@@ -21,6 +21,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
+# per-source options: the surrogate step keeps its MFMA accumulators in
+# ordinary VGPRs, so that the SiLU epilogue reads them without a copy out of
+# the accumulation registers
+EXTRA = {"md_surrogate.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _run(cmd, verbose):
@@ -36,7 +40,7 @@ def build(verbose=False, jobs=8):
     objs, procs = [], []
     for src in HIP_SOURCES:
         obj = os.path.join(bdir, src + ".o")
-        cmd = [hipcc, "-x", "hip", "-c"] + COMMON + DEVICE + [os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc, "-x", "hip", "-c"] + COMMON + DEVICE + EXTRA.get(src, []) + [os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd), src))
