@@ -337,7 +337,7 @@ __device__ __forceinline__ void mlp_wave(const bf16 *feat, float *out, const bf1
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int dt = 0; dt < DT; ++dt) prev[dt] = acc[dt];
-            cur = nxt;
+            if (j + 1 < N_JOBS) cur = nxt;
         }
     }
 }
