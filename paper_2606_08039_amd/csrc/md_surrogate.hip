@@ -124,16 +124,19 @@ __device__ __forceinline__ void knn8(const float4 *pos, int lo, int m, int mmax,
         const float dx = pj.x - px, dy = pj.y - py;
         const float a = dx * dx, b = dy * dy;
         float d2 = a + b;
-        d2 = (jj < m && j != self) ? d2 : __builtin_inff();
+        // masked and non-finite candidates become +inf, which never enters
+        d2 = (jj < m && j != self && d2 < __builtin_inff()) ? d2 : __builtin_inff();
         bool c[KNN];
 #pragma unroll
         for (int t = 0; t < KNN; ++t) c[t] = d2 < bd[t];
 #pragma unroll
         for (int t = KNN - 1; t >= 1; --t) {
-            bd[t] = c[t] ? (c[t - 1] ? bd[t - 1] : d2) : bd[t];
+            // bd is sorted, so the kept, shifted or inserted distance of slot t
+            // is the median of bd[t - 1], bd[t] and d2
+            bd[t] = __builtin_amdgcn_fmed3f(bd[t - 1], bd[t], d2);
             bj[t] = c[t] ? (c[t - 1] ? bj[t - 1] : j) : bj[t];
         }
-        bd[0] = c[0] ? d2 : bd[0];
+        bd[0] = fminf(bd[0], d2);
         bj[0] = c[0] ? j : bj[0];
     }
 }
