@@ -120,10 +120,14 @@ __device__ __forceinline__ void knn8(const float4 *pos, int lo, int m, int mmax,
     }
     for (int jj = 0; jj < mmax; ++jj) {
         const int j = lo + jj;
+        // formed by every lane (the position buffer holds 2 entries per slot,
+        // so lo + jj stays inside it); the empty asm keeps the read and the
+        // arithmetic from being moved under a branch on jj < m
         const float4 pj = pos[j];
         const float dx = pj.x - px, dy = pj.y - py;
         const float a = dx * dx, b = dy * dy;
         float d2 = a + b;
+        asm volatile("" : "+v"(d2));
         // masked and non-finite candidates become +inf, which never enters
         d2 = (jj < m && j != self && d2 < __builtin_inff()) ? d2 : __builtin_inff();
         bool c[KNN];
@@ -136,7 +140,7 @@ __device__ __forceinline__ void knn8(const float4 *pos, int lo, int m, int mmax,
             bd[t] = __builtin_amdgcn_fmed3f(bd[t - 1], bd[t], d2);
             bj[t] = c[t] ? (c[t - 1] ? bj[t - 1] : j) : bj[t];
         }
-        bd[0] = fminf(bd[0], d2);
+        bd[0] = c[0] ? d2 : bd[0];
         bj[0] = c[0] ? j : bj[0];
     }
 }
