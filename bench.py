@@ -196,9 +196,16 @@ def timed_rollouts(args, w, p, with_obs, mask=None, integrator=None, surrogate_w
             md.md_set_launch_config(ctx, **config)
             cfg = md.md_get_launch_config(ctx)
         elif tune and not args.no_tune and surrogate_weights is None:
-            # untimed: choose the launch configuration on scratch copies of the state
-            cfg = md.md_autotune(ctx, state, action, w["action_per_step"], n_steps=min(K, 50),
-                                 stream=stream, cache_path="")
+            # untimed: choose the launch configuration on scratch copies of the
+            # state, with the observation stream when the timed launches write it
+            # (over the full launch length: configurations that tie over a few
+            # dozen steps separate over a thousand)
+            if with_obs:
+                cfg = md.md_autotune_obs(ctx, state, action, w["action_per_step"], obs, n_slots,
+                                         n_steps=K, stream=stream, cache_path="")
+            else:
+                cfg = md.md_autotune(ctx, state, action, w["action_per_step"], n_steps=min(K, 50),
+                                     stream=stream, cache_path="")
         step0 = 0
         for _ in range(args.warmup):
             md.md_step(ctx, state, action, w["action_per_step"], obs, n_slots, K, step0, stream)

@@ -339,6 +339,19 @@ md_status md_set_launch_config(md_ctx *ctx, md_launch_config *cfg);
 md_status md_autotune(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
                       int n_steps, int64_t step0, void *stream, const char *cache_path, int force);
 
+/* md_autotune for callers that write the KIN-20 observation every step
+ * (Sec. 3 observation spaces): every candidate also writes its rows into
+ * d_obs (device, [n_obs_slots][20][n_drones] as for md_step, slot of step k
+ * as md_step places it), so that the choice includes the cost of that write
+ * stream, which some configurations overlap with the compute better than
+ * others.  The contents of d_obs afterwards are unspecified; the caller's
+ * state is not modified.  The choice is cached under the md_autotune
+ * signature with an observation mark.  MD_E_INVALID_ARG for a null d_obs or
+ * n_obs_slots < 1; otherwise as md_autotune. */
+md_status md_autotune_obs(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
+                          float *d_obs, int n_obs_slots, int n_steps, int64_t step0, void *stream,
+                          const char *cache_path, int force);
+
 /* A rollout of n_launches consecutive md_step launches of steps_per_launch
  * steps each (step0 advancing by steps_per_launch; per-step actions and, when
  * n_obs_slots >= steps_per_launch * n_launches, observation slots advance

@@ -71,8 +71,8 @@ md_status launch(md_ctx *ctx, const md_state *s, const float *d_action, int acti
 // Build the bin tables the next md_step will use (synchronous uploads).
 md_status prepare_launch(md_ctx *ctx);
 bool cfg_valid(const md_ctx *ctx, const LaunchCfg &c);
-md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step, int n_steps,
-                   int64_t step0, hipStream_t st, const char *path, int force);
+md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step, float *d_obs,
+                   int n_obs_slots, int n_steps, int64_t step0, hipStream_t st, const char *path, int force);
 
 // Subsystems with per-context resources.
 void destroy_extras(md_ctx *ctx);

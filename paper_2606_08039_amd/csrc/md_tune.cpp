@@ -138,9 +138,10 @@ static void cache_store(const std::string &path, const std::string &sig, const L
     std::rename(tmp.c_str(), path.c_str());
 }
 
-md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step, int n_steps,
-                   int64_t step0, hipStream_t st, const char *path, int force) {
-    const std::string sig = signature(ctx);
+md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step, float *d_obs,
+                   int n_obs_slots, int n_steps, int64_t step0, hipStream_t st, const char *path, int force) {
+    // a choice timed with the observation stream is kept apart from one timed without
+    const std::string sig = signature(ctx) + (d_obs ? "_obs" : "");
     const std::string cp = cache_path(path);
     LaunchCfg cached;
     if (!force && cache_lookup(cp, sig, cached) && cfg_valid(ctx, cached)) {
@@ -213,7 +214,7 @@ md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int ac
             e = hipMemcpyAsync(work, scratch, sizeof(float) * rows * N, hipMemcpyDeviceToDevice, st);
             if (e != hipSuccess) break;
             e = hipEventRecord(a, st);
-            rc = launch(ctx, &ws, d_action, action_per_step, nullptr, 0, n_steps, step0, st, c);
+            rc = launch(ctx, &ws, d_action, action_per_step, d_obs, d_obs ? n_obs_slots : 0, n_steps, step0, st, c);
             if (rc != MD_OK) break;
             e = hipEventRecord(b, st);
             if (e == hipSuccess) e = hipEventSynchronize(b);
@@ -270,7 +271,29 @@ md_status md_autotune(md_ctx *ctx, const md_state *s, const float *d_action, int
         ctx->tuned = true;  // the surrogate kernel has one configuration
         return MD_OK;
     }
-    return md::autotune(ctx, s, d_action, action_per_step, n_steps, step0, (hipStream_t)stream, cache_path, force);
+    return md::autotune(ctx, s, d_action, action_per_step, nullptr, 0, n_steps, step0, (hipStream_t)stream,
+                        cache_path, force);
+}
+
+md_status md_autotune_obs(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step, float *d_obs,
+                          int n_obs_slots, int n_steps, int64_t step0, void *stream, const char *cache_path,
+                          int force) {
+    if (!ctx) return MD_E_INVALID_ARG;
+    if (!ctx->has_layout) {
+        ctx->err = "md_autotune_obs: no layout bound";
+        return MD_E_LAYOUT;
+    }
+    if (!s || !d_action || !d_obs || n_obs_slots < 1 || n_steps < 0 || step0 < 0) {
+        ctx->err = "md_autotune_obs: null state, action or observation buffer, n_obs_slots < 1, or negative "
+                   "n_steps / step0";
+        return MD_E_INVALID_ARG;
+    }
+    if (ctx->mask & MD_AERO_SURROGATE) {
+        ctx->tuned = true;  // the surrogate kernel has one configuration
+        return MD_OK;
+    }
+    return md::autotune(ctx, s, d_action, action_per_step, d_obs, n_obs_slots, n_steps, step0, (hipStream_t)stream,
+                        cache_path, force);
 }
 
 md_status md_get_launch_config(const md_ctx *ctx, md_launch_config *out) {

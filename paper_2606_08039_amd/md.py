@@ -486,6 +486,16 @@ def md_autotune(ctx, state, action, action_per_step, n_steps=20, step0=0, stream
     return md_get_launch_config(ctx)
 
 
+def md_autotune_obs(ctx, state, action, action_per_step, obs, n_obs_slots, n_steps=20, step0=0, stream=None,
+                    cache_path=None, force=False):
+    ms = state.as_md_state() if hasattr(state, "as_md_state") else state
+    cp = cache_path.encode() if cache_path is not None else None
+    check(lib().md_autotune_obs(ctx, ctypes.byref(ms), _VP(action.data_ptr()), int(bool(action_per_step)),
+                                _VP(obs.data_ptr()) if obs is not None else None, int(n_obs_slots),
+                                int(n_steps), int(step0), _stream_ptr(stream), cp, int(bool(force))), ctx)
+    return md_get_launch_config(ctx)
+
+
 def md_rollout_graph_create(ctx, state, action, action_per_step, obs=None, n_obs_slots=0,
                             steps_per_launch=1, n_launches=1, step0=0, stream=None):
     ms = state.as_md_state() if hasattr(state, "as_md_state") else state

@@ -35,6 +35,8 @@ def signatures():
         "md_set_launch_config": (_I32, [_VP, _VP]),
         "md_autotune": (_I32, [_VP, _VP, _VP, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _VP,
                                ctypes.c_char_p, ctypes.c_int]),
+        "md_autotune_obs": (_I32, [_VP, _VP, _VP, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_int64, _VP, ctypes.c_char_p, ctypes.c_int]),
         "md_rollout_graph_create": (_I32, [_VP, _VP, _VP, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_int, ctypes.c_int64, _VP, ctypes.POINTER(_VP)]),
         "md_graph_launch": (_I32, [_VP, _VP]),

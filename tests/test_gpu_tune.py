@@ -96,6 +96,28 @@ def test_autotune_keeps_state_and_caches_choice(tmp_path):
             np.testing.assert_array_equal(a[k], b[k])
 
 
+def test_autotune_with_observations_keeps_state_and_caches_apart(tmp_path):
+    import torch
+    w = wl.subset_envs(wl.formation(n_envs=8192, seed=4), 256)
+    g = pu.DeviceRun(w)
+    before = g.snapshot()
+    cache = str(tmp_path / "tune.json")
+    obs = torch.empty((10, 20, g.n), dtype=torch.float32, device="cuda")
+    cfg = md.md_autotune_obs(g.ctx, g.state, g.action, False, obs, 10, n_steps=10, cache_path=cache)
+    after = g.snapshot()
+    for k in before:
+        np.testing.assert_array_equal(before[k], after[k])
+    assert md.md_get_launch_config(g.ctx) == cfg
+    # the choice timed with observations is cached apart from the one without
+    md.md_autotune(g.ctx, g.state, g.action, False, n_steps=10, cache_path=cache)
+    rec = json.load(open(cache))
+    assert len(rec) == 2 and sum(r["sig"].endswith("_obs") for r in rec) == 1
+    for bad in ((None, 10), (obs, 0)):
+        with pytest.raises(md.MdError):
+            md.md_autotune_obs(g.ctx, g.state, g.action, False, bad[0], bad[1], n_steps=10, cache_path="")
+    g.close()
+
+
 def test_graph_replays_equal_eager_launches():
     import torch
     w = wl.subset_envs(wl.formation(n_envs=8192, seed=4), 128)
