@@ -427,13 +427,17 @@ def main():
     traffic = measured_traffic(args.workload)
     # Two limits meet in the step kernel: its vector-ALU instruction stream
     # (the launch without observation writes, `plain_no_obs`, is bound by it)
-    # and the observation write stream.  roofline is the algorithmic FP32 rate
-    # against the chip's FP32 vector peak, with the HBM view (algorithmic
-    # bytes per launch) beside it.
-    roof = {"bound": "alu", "achieved": round(alu, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(alu / FP32_PEAK_TFLOPS, 4), "traffic": traffic}
+    # and the observation write stream.  Both views are reported; the primary
+    # one follows the roofline model: below the ridge point (FP32 peak over
+    # HBM peak, in FLOP per byte) the algorithmic intensity puts the kernel
+    # under the HBM line, above it under the ALU line.
+    roof_alu = {"bound": "alu", "achieved": round(alu, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(alu / FP32_PEAK_TFLOPS, 4), "traffic": traffic}
     roof_hbm = {"bound": "hbm", "achieved": round(hbm, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": traffic}
+    intensity = flop / bytes_
+    ridge = FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    roof = roof_hbm if intensity < ridge else roof_alu
     out = {
         "metric": METRIC,
         "value": value,
@@ -452,7 +456,10 @@ def main():
                        action="pid waypoints, ctrl_decim %d" % w["ctrl_decim"] if w["act_type"] == "pid"
                        else "rotor speeds per step", path="plain aero"),
         "roofline": roof,
+        "roofline_alu": roof_alu,
         "roofline_hbm": roof_hbm,
+        "intensity_flop_per_byte": round(intensity, 2),
+        "ridge_flop_per_byte": round(ridge, 2),
         "kernel_ms_avg": kavg * 1e3,
         "launch_config": launch_cfg,
         "final_state": check_state,
