@@ -42,7 +42,7 @@ typedef int32_t md_status;
 #define MD_E_INVALID_ARG (-1) /* a null pointer, a negative size, an unknown enum */
 #define MD_E_HIP (-2)         /* a HIP runtime call failed (message has the HIP error) */
 #define MD_E_OOM (-3)         /* the library could not allocate its own device memory */
-#define MD_E_UNSUPPORTED (-4) /* a valid request this build does not implement */
+#define MD_E_UNSUPPORTED (-4) /* a valid request the library does not implement */
 #define MD_E_LAYOUT (-5)      /* no layout bound, or state/layout sizes disagree */
 
 /* Aerodynamic terms (Table "Physics modes" toggles), OR-able. */
