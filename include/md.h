@@ -43,7 +43,7 @@ typedef int32_t md_status;
 #define MD_E_HIP (-2)         /* a HIP runtime call failed (message has the HIP error) */
 #define MD_E_OOM (-3)         /* the library could not allocate its own device memory */
 #define MD_E_UNSUPPORTED (-4) /* a valid request the library does not implement */
-#define MD_E_LAYOUT (-5)      /* no layout bound, or state/layout sizes disagree */
+#define MD_E_LAYOUT (-5)      /* no layout bound, layout sizes disagree, or a stale captured rollout */
 
 /* Aerodynamic terms (Table "Physics modes" toggles), OR-able. */
 #define MD_AERO_GND 1u       /* ground effect, Eq. 4 */
@@ -127,8 +127,9 @@ md_status md_default_params_cf2x(md_params *out);
 md_status md_derive(const md_params *p, md_derived *out);
 
 /* Create a context on the current HIP device.  dt > 0 (s); aero_mask is an OR
- * of MD_AERO_*; act_type MD_ACT_RPM or MD_ACT_PID; ctrl_decim >= 1 is the
- * number of physics steps per PID update (zero-order hold in between).
+ * of MD_AERO_*; act_type one of MD_ACT_RPM, MD_ACT_PID, MD_ACT_VEL,
+ * MD_ACT_ATTITUDE, MD_ACT_DSL; ctrl_decim >= 1 is the number of physics steps
+ * per controller update (zero-order hold in between; unused with MD_ACT_RPM).
  * MD_AERO_SURROGATE needs weights loaded by md_load_surrogate before stepping. */
 md_status md_create(const md_params *p, float dt, uint32_t aero_mask, int act_type,
                     int ctrl_decim, md_ctx **out);
@@ -145,8 +146,10 @@ const char *md_last_error(const md_ctx *ctx);
  * int32, non-decreasing, off[0] = 0, off[n_envs] = n_drones).  Each
  * environment may hold 0..1024 drones, a context up to 2^25 drones
  * (MD_E_UNSUPPORTED beyond).  The library packs environments into
- * wavefront bins and uploads its lane tables (synchronously).  Re-binding
- * replaces the previous layout and invalidates captured graphs. */
+ * wavefront bins and uploads its lane tables (synchronously).  The offsets
+ * are a host array because the packing runs on the host.  Re-binding
+ * replaces the previous layout, frees the previous lane tables and makes the
+ * context's captured rollouts stale (md_graph_launch refuses them). */
 md_status md_bind_layout(md_ctx *ctx, const int32_t *h_env_offsets, int n_envs, int n_drones);
 
 /* Advance every drone n_steps physics steps of dt, asynchronously on stream.
@@ -158,9 +161,13 @@ md_status md_bind_layout(md_ctx *ctx, const int32_t *h_env_offsets, int n_envs, 
  *     (Z-Y-X), v[3], w[3], applied rotor speeds[4];
  *   step0: global index of the first step; controller updates run at steps
  *     with (step0 + k) mod ctrl_decim == 0.
- * Sums over neighbours run in ascending drone order, so results do not depend
- * on how environments are packed.  Errors: MD_E_LAYOUT if no layout is bound,
- * MD_E_INVALID_ARG for null required pointers or n_steps < 0. */
+ * Each drone's downwash terms are summed in an order fixed by the launch
+ * configuration and the drone's place in its environment (ascending drone
+ * order for lanes_per_drone 1 with pair_symmetric 0 or 1; see
+ * md_launch_config), so results do not depend on how environments are packed
+ * or on how a rollout is split into launches.  Errors: MD_E_LAYOUT if no
+ * layout is bound, MD_E_INVALID_ARG for null required pointers or
+ * n_steps < 0. */
 md_status md_step(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
                   float *d_obs, int n_obs_slots, int n_steps, int64_t step0, void *stream);
 
@@ -358,8 +365,16 @@ md_status md_autotune_obs(md_ctx *ctx, const md_state *s, const float *d_action,
  * with it), captured once into a HIP graph.  md_graph_launch replays the
  * whole rollout on a stream with the same pointers and step indices: keep
  * steps_per_launch * n_launches a multiple of ctrl_decim for replays to keep
- * the PID phase.  The graph belongs to the context's current layout and
- * configuration; destroy it before re-binding. */
+ * the PID phase.  The captured kernels hold the context's lane tables and
+ * settings as they were at capture, so the graph goes stale at the next call
+ * that changes the context's layout (md_bind_layout), launch configuration
+ * (md_set_launch_config, or md_autotune / md_autotune_obs choosing another),
+ * integrator, domain randomisation, wind or surrogate (md_load_surrogate*,
+ * md_set_surrogate_ood), and when the context is destroyed: md_graph_launch
+ * then returns MD_E_LAYOUT and launches nothing (the message, while the
+ * context lives, is in md_last_error).  Capture again after such a change.
+ * md_graph_destroy is valid on a stale graph, also after md_destroy of its
+ * context. */
 typedef struct md_graph md_graph;
 md_status md_rollout_graph_create(md_ctx *ctx, const md_state *s, const float *d_action,
                                   int action_per_step, float *d_obs, int n_obs_slots,

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmd.so")
 
 HIP_SOURCES = ["md_step.hip", "md_step_dr.hip", "md_step_wind.hip", "md_rk4.hip", "md_mlp.hip", "md_surrogate.hip"]
-CPP_SOURCES = ["md_api.cpp", "md_extras.cpp", "md_tune.cpp"]
+CPP_SOURCES = ["md_api.cpp", "md_tune.cpp"]
 
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

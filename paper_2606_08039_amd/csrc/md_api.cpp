@@ -462,7 +462,10 @@ md_status md_create(const md_params *p, float dt, uint32_t aero_mask, int act_ty
 void md_destroy(md_ctx *ctx) {
     if (!ctx) return;
     (void)hipDeviceSynchronize();
-    md::destroy_extras(ctx);
+    // captured rollouts outlive their context only as handles md_graph_launch refuses
+    for (md_graph *g : ctx->graphs) g->ctx = nullptr;
+    ctx->graphs.clear();
+    md::free_surrogate(ctx);
     md::free_bins(ctx);
     delete ctx;
 }
@@ -500,7 +503,7 @@ md_status md_bind_layout(md_ctx *ctx, const int32_t *h_env_offsets, int n_envs, 
         return MD_E_UNSUPPORTED;
     }
     (void)hipSetDevice(ctx->device);
-    md::invalidate_layout_users(ctx);
+    md::invalidate_graphs(ctx);  // they point at the bin tables freed here
     md::free_bins(ctx);
     ctx->off.assign(h_env_offsets, h_env_offsets + n_envs + 1);
     ctx->n_envs = n_envs;
@@ -528,6 +531,7 @@ md_status md_set_integrator(md_ctx *ctx, int integrator) {
                    "semi-implicit Euler step only";
         return MD_E_UNSUPPORTED;
     }
+    if (integrator != ctx->integ) md::invalidate_graphs(ctx);
     ctx->integ = integrator;
     if (ctx->has_layout && !md::cfg_valid(ctx, ctx->cfg)) {
         // the Runge-Kutta kernel sweeps neighbours with one lane per drone
@@ -540,6 +544,7 @@ md_status md_set_integrator(md_ctx *ctx, int integrator) {
 md_status md_set_domain_randomization(md_ctx *ctx, const md_dr *dr) {
     if (!ctx) return MD_E_INVALID_ARG;
     if (!dr) {
+        if (ctx->dr_on) md::invalidate_graphs(ctx);
         ctx->dr_on = false;
         ctx->dr = md::DrPtr{};
         return MD_OK;
@@ -570,12 +575,14 @@ md_status md_set_domain_randomization(md_ctx *ctx, const md_dr *dr) {
     d.obs_bias = dr->obs_bias;
     ctx->dr = d;
     ctx->dr_on = true;
+    md::invalidate_graphs(ctx);
     return MD_OK;
 }
 
 md_status md_set_wind(md_ctx *ctx, const md_wind *w) {
     if (!ctx) return MD_E_INVALID_ARG;
     if (!w || w->models == 0) {
+        if (ctx->wind.models) md::invalidate_graphs(ctx);
         ctx->wind = md::WindArgs{};
         return MD_OK;
     }
@@ -604,6 +611,7 @@ md_status md_set_wind(md_ctx *ctx, const md_wind *w) {
     a.key1 = (uint32_t)(w->seed >> 32);
     a.vm_drone = w->v_mean_drone;
     ctx->wind = a;
+    md::invalidate_graphs(ctx);
     return MD_OK;
 }
 

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <map>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -27,6 +28,12 @@ void derive(const md_params &p, md_derived &d);
 }  // namespace md
 
 struct md_ctx {
+    // Bumped by every call that frees or replaces what captured kernels point
+    // at, or changes which kernel md_step launches (layout, launch
+    // configuration, integrator, randomisation, wind, surrogate); a captured
+    // rollout remembers the value it was captured under.
+    uint64_t gen = 1;
+    std::set<md_graph *> graphs;  // live captured rollouts of this context
     md_params P{};
     md_derived D{};
     float dt = 0.f;
@@ -53,6 +60,15 @@ struct md_ctx {
     std::string err;
 };
 
+// A captured rollout (md_rollout_graph_create).  ctx is null once the context
+// is destroyed; gen is the context's generation at capture.
+struct md_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    md_ctx *ctx = nullptr;
+    uint64_t gen = 0;
+};
+
 namespace md {
 
 // Packing of environments into bins: contiguous runs (best fit decreasing),
@@ -74,9 +90,9 @@ bool cfg_valid(const md_ctx *ctx, const LaunchCfg &c);
 md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step, float *d_obs,
                    int n_obs_slots, int n_steps, int64_t step0, hipStream_t st, const char *path, int force);
 
+// Captured rollouts of ctx become stale (md_graph_launch refuses them).
+inline void invalidate_graphs(md_ctx *ctx) { ++ctx->gen; }
 // Subsystems with per-context resources.
-void destroy_extras(md_ctx *ctx);
-void invalidate_layout_users(md_ctx *ctx);
 md_status surrogate_step(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step,
                          float *d_obs, int n_obs_slots, int n_steps, int64_t step0, hipStream_t st);
 void free_surrogate(md_ctx *ctx);

@@ -693,6 +693,7 @@ md_status load_surrogate(md_ctx *ctx, const float *params, const float *norm, fl
         ctx->err = hip_msg("md_load_surrogate", e);
         return MD_E_HIP;
     }
+    invalidate_graphs(ctx);
     S->dz_ood = dz_ood;
     S->ood_speed = S->ood_rel = S->ood_tilt_s = 0.f;
     S->judge_stride = judge_stride;
@@ -833,6 +834,7 @@ md_status md_set_surrogate_ood(md_ctx *ctx, float max_speed, float max_rel_speed
         ctx->err = "md_set_surrogate_ood: bounds must be >= 0 (0 turns a check off)";
         return MD_E_INVALID_ARG;
     }
+    md::invalidate_graphs(ctx);
     const double sh = std::sin(0.5 * (double)max_tilt);
     ctx->sur->ood_speed = max_speed;
     ctx->sur->ood_rel = max_rel_speed;

@@ -138,6 +138,14 @@ static void cache_store(const std::string &path, const std::string &sig, const L
     std::rename(tmp.c_str(), path.c_str());
 }
 
+// A new launch configuration makes the captured rollouts stale.
+static void set_cfg(md_ctx *ctx, const LaunchCfg &c) {
+    const LaunchCfg &o = ctx->cfg;
+    if (o.lpd != c.lpd || o.unroll != c.unroll || o.waves != c.waves || o.sym != c.sym) invalidate_graphs(ctx);
+    ctx->cfg = c;
+    ctx->tuned = true;
+}
+
 md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int action_per_step, float *d_obs,
                    int n_obs_slots, int n_steps, int64_t step0, hipStream_t st, const char *path, int force) {
     // a choice timed with the observation stream is kept apart from one timed without
@@ -145,8 +153,7 @@ md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int ac
     const std::string cp = cache_path(path);
     LaunchCfg cached;
     if (!force && cache_lookup(cp, sig, cached) && cfg_valid(ctx, cached)) {
-        ctx->cfg = cached;
-        ctx->tuned = true;
+        set_cfg(ctx, cached);
         return MD_OK;
     }
     const size_t N = (size_t)ctx->n_drones;
@@ -240,19 +247,12 @@ md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int ac
         ctx->err = hip_msg("autotune", e);
         return MD_E_HIP;
     }
-    ctx->cfg = best;
-    ctx->tuned = true;
+    set_cfg(ctx, best);
     cache_store(cp, sig, best, best_us);
     return MD_OK;
 }
 
 }  // namespace md
-
-struct md_graph {
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    md_ctx *ctx = nullptr;
-};
 
 extern "C" {
 
@@ -319,8 +319,7 @@ md_status md_set_launch_config(md_ctx *ctx, md_launch_config *cfg) {
         ctx->err = "md_set_launch_config: invalid configuration for this layout";
         return MD_E_INVALID_ARG;
     }
-    ctx->cfg = c;
-    ctx->tuned = true;
+    md::set_cfg(ctx, c);
     return MD_OK;
 }
 
@@ -349,6 +348,7 @@ md_status md_rollout_graph_create(md_ctx *ctx, const md_state *s, const float *d
         return MD_E_OOM;
     }
     g->ctx = ctx;
+    g->gen = ctx->gen;
     e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     md_status rc = MD_OK;
     if (e == hipSuccess) {
@@ -381,12 +381,21 @@ md_status md_rollout_graph_create(md_ctx *ctx, const md_state *s, const float *d
         }
         return rc;
     }
+    ctx->graphs.insert(g);
     *out = g;
     return MD_OK;
 }
 
 md_status md_graph_launch(md_graph *g, void *stream) {
     if (!g || !g->exec) return MD_E_INVALID_ARG;
+    // the captured kernels point at the bin tables, surrogate buffers and
+    // settings of the context as it was at capture: refuse a graph whose
+    // context has since changed them or been destroyed (nothing is launched)
+    if (!g->ctx) return MD_E_LAYOUT;
+    if (g->gen != g->ctx->gen) {
+        g->ctx->err = "md_graph_launch: the context's layout or settings changed since capture; capture again";
+        return MD_E_LAYOUT;
+    }
     hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
     if (e != hipSuccess) {
         g->ctx->err = md::hip_msg("hipGraphLaunch", e);
@@ -397,6 +406,7 @@ md_status md_graph_launch(md_graph *g, void *stream) {
 
 void md_graph_destroy(md_graph *g) {
     if (!g) return;
+    if (g->ctx) g->ctx->graphs.erase(g);
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     delete g;

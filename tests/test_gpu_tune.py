@@ -139,3 +139,59 @@ def test_graph_replays_equal_eager_launches():
     md.md_graph_destroy(graph)
     ge.close()
     gg.close()
+
+
+def test_stale_graph_is_refused_on_the_host():
+    """A captured rollout holds the context's lane tables and settings as they
+    were at capture: after re-binding (which frees those tables), a new launch
+    configuration, a settings change or md_destroy, md_graph_launch returns
+    MD_E_LAYOUT without launching anything.  Every check is host-side."""
+    import torch
+    w = wl.subset_envs(wl.formation(n_envs=8192, seed=4), 64)
+
+    def capture(g):
+        return md.md_rollout_graph_create(g.ctx, g.state, g.action, False, None, 0,
+                                          steps_per_launch=5, n_launches=2, step0=0)
+
+    def expect_stale(graph):
+        before = g.snapshot()
+        with pytest.raises(md.MdError) as ei:
+            md.md_graph_launch(graph)
+        assert ei.value.status == md.MD_E_LAYOUT
+        torch.cuda.synchronize()
+        after = g.snapshot()
+        for k in before:
+            np.testing.assert_array_equal(before[k], after[k], err_msg="a stale graph advanced %s" % k)
+
+    g = pu.DeviceRun(w)
+    graph = capture(g)
+    md.md_graph_launch(graph)  # fresh: runs
+    torch.cuda.synchronize()
+    md.md_bind_layout(g.ctx, w["env_offsets"])  # same offsets, new tables
+    expect_stale(graph)
+    md.md_graph_destroy(graph)
+
+    graph = capture(g)
+    cfg = md.md_get_launch_config(g.ctx)
+    other = dict(lanes_per_drone=1, unroll=1, waves_per_group=2, pair_symmetric=0)
+    assert other != cfg
+    md.md_set_launch_config(g.ctx, **other)
+    expect_stale(graph)
+    md.md_graph_destroy(graph)
+
+    # setting the same configuration again keeps a graph valid
+    graph = capture(g)
+    md.md_set_launch_config(g.ctx, **other)
+    md.md_graph_launch(graph)
+    torch.cuda.synchronize()
+    md.md_set_wind(g.ctx, models=md.MD_WIND_CONSTANT, v_mean=(0.1, 0.0, 0.0))
+    expect_stale(graph)
+    md.md_graph_destroy(graph)
+
+    graph = capture(g)
+    md.md_destroy(g.ctx)
+    g.ctx = None
+    with pytest.raises(md.MdError) as ei:
+        md.md_graph_launch(graph)
+    assert ei.value.status == md.MD_E_LAYOUT
+    md.md_graph_destroy(graph)  # valid after the context is gone
