@@ -424,6 +424,25 @@ md_status md_mlp_get_norm(const md_mlp *m, float *h_norm);
  * [B][6] de-standardised outputs (fp32, device).  Asynchronous on stream. */
 md_status md_mlp_forward(md_mlp *m, const float *d_X, int B, float *d_Y, void *stream);
 
+/* md_mlp_forward for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The de-standardised outputs of B <= MD_MLP_NOALLOC_MAX_BATCH samples d_X
+ * [B][64] (raw fp32 features, device) go to d_Y [B][6] (fp32, device,
+ * required), computed by the same kernels as md_mlp_forward (bitwise the
+ * same outputs), with every intermediate (standardised input, hidden
+ * activations, standardised outputs) in a static device buffer of the
+ * library instead of m's buffers: 2.6 MiB per GPU, taken on each GPU the
+ * library runs on and held until the process ends; its address on m's device
+ * is resolved by md_mlp_create.  Calls no allocator.  The activations are
+ * not kept: md_mlp_backward still refers to the last md_mlp_forward.  Every
+ * call on one GPU shares that buffer, so calls that overlap in time on one GPU
+ * (other streams, other host threads) race; calls in order on one stream do
+ * not.  Asynchronous on stream (a stream of m's device).  MD_E_INVALID_ARG
+ * for a null pointer, B < 0 or B > MD_MLP_NOALLOC_MAX_BATCH; MD_E_HIP if
+ * the buffer's address could not be resolved at md_mlp_create. */
+#define MD_MLP_NOALLOC_MAX_BATCH 4096
+md_status md_mlp_forward_noalloc(md_mlp *m, const float *d_X, int B, float *d_Y, void *stream);
+
 /* Gradient of the mean squared error between the standardised outputs of
  * the last forward pass and the standardised targets d_T [B][6] (raw fp32,
  * device) with respect to every parameter, written to the network's gradient

@@ -9,6 +9,7 @@
 // deterministic).  Master weights, gradients and Adam moments are fp32.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -102,7 +103,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
                 switch (g.epi) {
                     case EPI_HIDDEN: {
                         const float z = v + g.bias[n];
-                        g.out_f[o] = z;
+                        if (g.out_f) g.out_f[o] = z;  // pre-activations, kept for the backward pass
                         g.out_h[o] = (bf16)silu_f(z);
                         break;
                     }
@@ -212,6 +213,39 @@ GemmArgs base(int M, int N, int K) {
 // Offsets of the flat parameter vector: W1, b1, W2, b2, W3, b3, W4, b4 (W row-major [out][in]).
 const int kParamOff[8] = {0, 8192, 8320, 24704, 24832, 41216, 41344, 42112};
 
+// Intermediates of md_mlp_forward_noalloc for up to MD_MLP_NOALLOC_MAX_BATCH
+// samples: the standardised bfloat16 input, two bfloat16 hidden activations
+// used in turn by the three hidden layers, and the standardised fp32
+// outputs.  Every part is a multiple of 256 bytes.  One copy per GPU, held
+// until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns on each device.
+constexpr size_t NA_B = MD_MLP_NOALLOC_MAX_BATCH;
+constexpr size_t NA_XB = 0, NA_HA = NA_XB + 2 * NA_B * MLP_IN, NA_HB = NA_HA + 2 * NA_B * MLP_H,
+                 NA_Y = NA_HB + 2 * NA_B * MLP_H, NA_BYTES = NA_Y + 4 * NA_B * MLP_OUT;
+static_assert(NA_HA % 256 == 0 && NA_HB % 256 == 0 && NA_Y % 256 == 0, "scratch parts stay 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_ptr[kMaxDevices];
+
+// The device address of `scratch` on device dev, which must be current;
+// resolved once per device.
+static hipError_t scratch_on(int dev, unsigned char **out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (unsigned char *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 }  // namespace md
 
 using md::bf16;
@@ -230,6 +264,8 @@ struct md_mlp {
     int last_B = 0, fwd_B = 0;
     bool have_fwd = false, have_bwd = false;
     std::vector<void *> allocs;
+    unsigned char *scratch = nullptr;  // this device's static scratch (md_mlp_forward_noalloc)
+    std::string scratch_err;
     std::string err;
 };
 
@@ -291,6 +327,10 @@ md_status md_mlp_create(int max_batch, md_mlp **out) {
         md_mlp_destroy(m);
         return MD_E_OOM;
     }
+    // the address of this device's static scratch, resolved here (set-up)
+    // rather than in the call that must not allocate
+    const hipError_t se = md::scratch_on(m->device, &m->scratch);
+    if (se != hipSuccess) m->scratch_err = md::hip_msg("hipGetSymbolAddress(scratch)", se);
     // identity normalisation until set
     std::vector<float> nrm(md::MLP_NORM, 0.f);
     for (int i = 0; i < md::MLP_IN; ++i) nrm[md::MLP_IN + i] = 1.f;
@@ -349,21 +389,23 @@ md_status md_mlp_get_norm(const md_mlp *m, float *h_norm) {
                : MD_E_HIP;
 }
 
-md_status md_mlp_forward(md_mlp *m, const float *d_X, int B, float *d_Y, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// The forward pass on buffers Xb [B][64], H[l] [B][128] (bf16), Z[l]
+// [B][128] (fp32 pre-activations, or null to keep none) and Y [B][6]
+// (standardised fp32); d_Y (nullable) receives the de-standardised outputs.
+hipError_t mlp_forward_on(const md_mlp *m, const float *d_X, int B, bf16 *Xb, bf16 *const H[3],
+                          float *const Z[3], float *Y, float *d_Y, hipStream_t st) {
     using namespace md;
-    if (!m || !d_X || B < 0) return MD_E_INVALID_ARG;
-    if (B > m->max_batch) return mlp_fail(m, MD_E_INVALID_ARG, "batch exceeds max_batch");
-    if (B == 0) return MD_OK;
-    hipStream_t st = (hipStream_t)stream;
     const float *P = m->params;
     const long long nx = (long long)B * MLP_IN;
     hipLaunchKernelGGL(prep_input_kernel, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, st, d_X, m->norm,
-                       m->norm + MLP_IN, m->Xb, nx);
+                       m->norm + MLP_IN, Xb, nx);
     hipError_t e = hipGetLastError();
-    const bf16 *hin = m->Xb;
+    const bf16 *hin = Xb;
     int din = MLP_IN;
-    bf16 *H[3] = {m->H1, m->H2, m->H3};
-    float *Z[3] = {m->Z1, m->Z2, m->Z3};
     for (int l = 0; l < 3 && e == hipSuccess; ++l) {
         GemmArgs g = base(B, MLP_H, din);
         g.A = hin;
@@ -382,21 +424,58 @@ md_status md_mlp_forward(md_mlp *m, const float *d_X, int B, float *d_Y, void *s
     }
     if (e == hipSuccess) {
         GemmArgs g = base(B, MLP_OUT, MLP_H);
-        g.A = m->H3;
+        g.A = H[2];
         g.lda = MLP_H;
         g.B = P + kParamOff[6];
         g.ldb = MLP_H;
         g.b_trans = 1;
         g.epi = EPI_LINEAR;
         g.bias = P + kParamOff[7];
-        g.out_f = m->Y;
+        g.out_f = Y;
         g.ldo = MLP_OUT;
         e = gemm<bf16, float>(g, 1, st);
     }
-    if (e == hipSuccess && d_Y) e = mlp_destandardize(m->Y, m->norm + 2 * MLP_IN, d_Y, B, st);
+    if (e == hipSuccess && d_Y) e = mlp_destandardize(Y, m->norm + 2 * MLP_IN, d_Y, B, st);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+md_status md_mlp_forward(md_mlp *m, const float *d_X, int B, float *d_Y, void *stream) {
+    using namespace md;
+    if (!m || !d_X || B < 0) return MD_E_INVALID_ARG;
+    if (B > m->max_batch) return mlp_fail(m, MD_E_INVALID_ARG, "batch exceeds max_batch");
+    if (B == 0) return MD_OK;
+    bf16 *const H[3] = {m->H1, m->H2, m->H3};
+    float *const Z[3] = {m->Z1, m->Z2, m->Z3};
+    const hipError_t e = mlp_forward_on(m, d_X, B, m->Xb, H, Z, m->Y, d_Y, (hipStream_t)stream);
     if (e != hipSuccess) return mlp_fail(m, MD_E_HIP, hip_msg("md_mlp_forward", e));
     m->fwd_B = B;
     m->have_fwd = true;
+    return MD_OK;
+}
+
+md_status md_mlp_forward_noalloc(md_mlp *m, const float *d_X, int B, float *d_Y, void *stream) {
+    using namespace md;
+    if (!m || !d_X || !d_Y || B < 0) {
+        if (m) m->err = "md_mlp_forward_noalloc: null input or output, or B < 0";
+        return MD_E_INVALID_ARG;
+    }
+    if (B > MD_MLP_NOALLOC_MAX_BATCH)
+        return mlp_fail(m, MD_E_INVALID_ARG,
+                        "md_mlp_forward_noalloc: batch " + std::to_string(B) + " exceeds its static scratch of " +
+                            std::to_string(MD_MLP_NOALLOC_MAX_BATCH) + " samples");
+    if (!m->scratch) return mlp_fail(m, MD_E_HIP, "md_mlp_forward_noalloc: " + m->scratch_err);
+    if (B == 0) return MD_OK;
+    unsigned char *s = m->scratch;
+    bf16 *Xb = (bf16 *)(s + NA_XB), *Ha = (bf16 *)(s + NA_HA), *Hb = (bf16 *)(s + NA_HB);
+    // inference keeps no pre-activations: the hidden layers alternate between two buffers
+    bf16 *const H[3] = {Ha, Hb, Ha};
+    float *const Z[3] = {nullptr, nullptr, nullptr};
+    const hipError_t e = mlp_forward_on(m, d_X, B, Xb, H, Z, (float *)(s + NA_Y), d_Y, (hipStream_t)stream);
+    if (e != hipSuccess) return mlp_fail(m, MD_E_HIP, hip_msg("md_mlp_forward_noalloc", e));
     return MD_OK;
 }
 

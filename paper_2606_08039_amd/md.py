@@ -324,6 +324,17 @@ def md_mlp_forward(m, X, B=None, Y=None, stream=None):
                                    _stream_ptr(stream)), m)
 
 
+MD_MLP_NOALLOC_MAX_BATCH = 4096
+
+
+def md_mlp_forward_noalloc(m, X, Y, B=None, stream=None):
+    """md_mlp_forward with its intermediates in the library's static device
+    buffer (allocates nothing); Y [B][6] float32 receives the outputs."""
+    B = X.shape[0] if B is None else B
+    mlp_check(lib().md_mlp_forward_noalloc(m, _VP(X.data_ptr()), int(B), _VP(Y.data_ptr()),
+                                           _stream_ptr(stream)), m)
+
+
 def md_mlp_backward(m, T, B=None, stream=None):
     B = T.shape[0] if B is None else B
     mlp_check(lib().md_mlp_backward(m, _VP(T.data_ptr()), int(B), _stream_ptr(stream)), m)

@@ -17,6 +17,7 @@ def signatures():
         "md_mlp_set_norm": (_I32, [_VP, _FP]),
         "md_mlp_get_norm": (_I32, [_VP, _FP]),
         "md_mlp_forward": (_I32, [_VP, _VP, ctypes.c_int, _VP, _VP]),
+        "md_mlp_forward_noalloc": (_I32, [_VP, _VP, ctypes.c_int, _VP, _VP]),
         "md_mlp_backward": (_I32, [_VP, _VP, ctypes.c_int, _VP]),
         "md_mlp_get_grads": (_I32, [_VP, _FP]),
         "md_mlp_loss": (_I32, [_VP, ctypes.POINTER(ctypes.c_double)]),
