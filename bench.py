@@ -120,38 +120,73 @@ def algorithmic_counts(w, with_obs):
     return flop, bytes_
 
 
-def cpu_baseline(w, with_obs, seconds_target=12.0):
-    """The FP64 oracle on a bounded sample of the same workload."""
+def host_cpu():
+    """What the CPU baseline ran on: the CPUs visible to this process, the
+    thread count the job may use, the CPU model."""
+    visible = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    omp = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    # all cores of the job's CPU share: the visible CPUs, or fewer when the
+    # environment limits the job's threads (OMP_NUM_THREADS)
+    share = min(visible, omp) if omp > 0 else visible
+    return {"cpu_count": os.cpu_count(), "nproc": visible, "omp_num_threads": omp or None,
+            "threads_all": share, "model": model}
+
+
+def cpu_baseline(w, with_obs, seconds_one=4.0, seconds_all=3.0, reps=3):
+    """The FP64 oracle (the same C code, built -O3 -march=native for this
+    host) on bounded samples of the same workload: on one thread and on all
+    threads of the job's CPU share, each the median of `reps` runs."""
+    import tempfile
     import oracle as orc
     from paper_2606_08039_amd import workloads as wl
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
+    build = orc.load_native(tempfile.mkdtemp(prefix="oracle_native_"))
+    host = host_cpu()
     P = orc.cf2x()
-    off = np.asarray(w["env_offsets"])
-    # calibration pass on a few environments, then a sample sized to the target
-    def run(n_envs, steps):
+    n_env_total = len(w["env_offsets"]) - 1
+    steps = min(w["n_steps"], 100)
+
+    def run(n_envs, n_steps, threads):
         sub = wl.subset_envs(w, n_envs)
         s = {k: v.astype(np.float64) for k, v in sub["state"].items()}
-        act = sub["action"][:steps] if w["action_per_step"] else sub["action"]
+        act = sub["action"][:n_steps] if w["action_per_step"] else sub["action"]
         n = int(sub["env_offsets"][-1])
         t0 = time.perf_counter()
         orc.step(P, w["dt"], w["aero_mask"], {"rpm": 0, "pid": 1}[w["act_type"]],
                  w["ctrl_decim"], sub["env_offsets"], s, act.astype(np.float64),
-                 w["action_per_step"], steps, n_obs_slots=1 if with_obs else 0,
+                 w["action_per_step"], n_steps, n_obs_slots=1 if with_obs else 0,
                  n_threads=threads)
-        return n * steps, time.perf_counter() - t0
-    n_env_total = len(off) - 1
-    e0 = min(n_env_total, 64)
-    ds, dtm = run(e0, min(10, w["n_steps"]))
-    rate = ds / max(dtm, 1e-9)
-    steps = min(w["n_steps"], 100)
-    want = rate * seconds_target / steps  # drones for ~seconds_target wall
-    per_env = max(1, ds // (e0 * min(10, w["n_steps"])))
-    envs = int(max(1, min(n_env_total, want / per_env)))
-    ds, dtm = run(envs, steps)
-    return {"value": ds / dtm, "unit": "drone-steps/s", "cores": threads, "kind": "oracle",
-            "sample": "%d envs (%d drones) x %d physics steps of the same workload, FP64 C oracle, "
-                      "KIN rows to a 1-slot ring, %d OpenMP threads, %.1f s wall"
-                      % (envs, ds // steps, steps, threads, dtm)}
+        return n * n_steps, time.perf_counter() - t0
+
+    def sized(threads, seconds):
+        # calibrate on a few environments, then size the sample to `seconds`
+        e0 = min(n_env_total, 16 * threads)
+        ds, dt = run(e0, min(10, steps), threads)
+        envs = int(max(1, min(n_env_total, e0 * seconds / max(dt * steps / min(10, steps), 1e-9))))
+        rates, walls, n_ds = [], [], 0
+        for _ in range(reps):
+            n_ds, dt = run(envs, steps, threads)
+            rates.append(n_ds / dt)
+            walls.append(dt)
+        return {"value": float(np.median(rates)), "unit": "drone-steps/s", "threads": threads,
+                "runs": [round(r, 1) for r in rates],
+                "sample": "%d envs (%d drones) x %d physics steps, median of %d runs of %.1f-%.1f s"
+                          % (envs, n_ds // steps, steps, reps, min(walls), max(walls))}
+
+    one = sized(1, seconds_one)
+    allc = sized(host["threads_all"], seconds_all)
+    return {"value": allc["value"], "unit": "drone-steps/s", "cores": host["threads_all"], "kind": "oracle",
+            "sample": "FP64 C oracle (%s), KIN rows to a 1-slot ring; all cores: %s; one core: %s"
+                      % (build, allc["sample"], one["sample"]),
+            "one_core": one, "all_cores": allc, "host": host}
 
 
 def timed_rollouts(args, w, p, with_obs, mask=None, integrator=None, surrogate_weights=None,
@@ -181,7 +216,8 @@ def timed_rollouts(args, w, p, with_obs, mask=None, integrator=None, surrogate_w
             dr_t = {k: (torch.from_numpy(v).cuda() if isinstance(v, np.ndarray) else v) for k, v in dr.items()}
             state.add_dr_blocks(act)
             md.md_set_domain_randomization(ctx, dr_t["scale"], dr_t["tau_mot"], dr_t["delay"],
-                                           noise=dr_t["noise"], seed=dr_t["seed"], obs_delay=dr_t["obs_delay"])
+                                           noise=dr_t["noise"], seed=dr_t["seed"], obs_delay=dr_t["obs_delay"],
+                                           obs_bias=dr_t["obs_bias"])
         wind_t = None
         if wind is not None:
             state.add_wind_block()

@@ -316,12 +316,12 @@ md_status md_get_integrator(const md_ctx *ctx, int *out);
  * 3 are bitwise identical). */
 typedef struct md_launch_config {
     int lanes_per_drone; /* 1, 2 or 4 lanes share one drone's neighbour sweep */
-    int unroll;          /* neighbour-loop unroll: 1, 2 or 4 */
+    int unroll;          /* neighbour-loop unroll: 1, 2 or 4 (1 for pair_symmetric 2 and 3) */
     int waves_per_group; /* 1, 2, 4, 8 or 16 wave64s per workgroup (bin of 64*w/lpd slots) */
     int pair_symmetric;  /* 0: all ordered pairs; 1: each unordered pair once, terms routed
                             through an LDS matrix; 2: each unordered pair once, terms routed
                             between lanes by wave permutes (environments of at most 64
-                            drones, packed so that none crosses a wavefront); 3: the
+                            drones, packed so that none crosses a wavefront; unroll 1); 3: the
                             pairs of 2 as rotations of the whole wave, for layouts whose
                             non-empty environments all have one power-of-two size 2..64
                             (environments interleaved in their wave; unroll 1, the sweep
@@ -505,12 +505,31 @@ md_status md_datagen(md_ctx *ctx, const md_state *s, uint32_t aero_mask, float *
  * n_drone_steps all drone-steps stepped; force_rel_err = sqrt(err2 / ref2)
  * (NaN when nothing was judged); n_nonfinite judged drone-steps whose
  * surrogate or plain force was not finite (left out of the sums and of
- * n_judged). */
+ * n_judged); n_knn_full drone-steps that ranked their whole environment for
+ * the nearest neighbours (the others ranked their candidate list, see
+ * md_set_surrogate_knn_reuse).  The plain terms of judged and fallback
+ * drones are evaluated by the whole wave, one such drone at a time; their
+ * downwash sum is added in a fixed order that depends only on the drone's
+ * place in its environment. */
 typedef struct md_judge {
     double n_judged, force_err2, force_ref2, torque_err2, n_fallback, n_drone_steps;
     double force_rel_err, n_nonfinite;
+    double n_knn_full;
 } md_judge;
 md_status md_judge_stats(md_ctx *ctx, md_judge *out);
+
+/* Neighbour candidate lists of the surrogate step (on after
+ * md_load_surrogate*).  In bins whose largest environment has at least 18
+ * drones, each drone ranks its whole environment only at a rebuild, keeps
+ * its 16 laterally nearest and, until the next rebuild, ranks only those: a
+ * bin rebuilds at the first step of every launch and whenever its largest
+ * lateral displacement since the last rebuild reaches a quarter of its
+ * smallest gap between a drone's 16th and 8th nearest distances (margins
+ * shrunk against float32 rounding), which guarantees the same 8 neighbours
+ * in the same order as ranking the whole environment.  Results are bitwise
+ * those of reuse 0, which ranks every drone every step.  MD_E_INVALID_ARG
+ * without a loaded surrogate. */
+md_status md_set_surrogate_knn_reuse(md_ctx *ctx, int reuse);
 md_status md_judge_reset(md_ctx *ctx);
 
 #ifdef __cplusplus

@@ -95,13 +95,29 @@ _D = ctypes.POINTER(ctypes.c_double)
 _I32 = ctypes.POINTER(ctypes.c_int32)
 
 
+_native_path = None
+
+
+def load_native(directory):
+    """Build the oracle with -march=native for this host into directory and
+    use that build for every later call of this process (the CPU baseline of
+    bench.py: the same C code, compiled for the CPU it is timed on).  Must
+    run before any other oracle call.  Returns the command line's flags."""
+    global _native_path
+    if _lib is not None:
+        raise RuntimeError("oracle already loaded")
+    os.makedirs(directory, exist_ok=True)
+    _native_path = build_oracle.build(native=True, dst=os.path.join(directory, "liboracle_native.so"))
+    return " ".join(["gcc"] + build_oracle.FLAGS + ["-march=native"])
+
+
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    path = build_oracle.LIB
+    path = _native_path or build_oracle.LIB
     src = os.path.join(_HERE, "md_oracle.c")
-    if (not os.path.exists(path)) or os.path.getmtime(path) < os.path.getmtime(src):
+    if _native_path is None and ((not os.path.exists(path)) or os.path.getmtime(path) < os.path.getmtime(src)):
         build_oracle.build()
     lib = ctypes.CDLL(path)
     P = ctypes.POINTER(Params)

@@ -87,9 +87,9 @@ void orc_params_cf2x(orc_params *P)
 
 /* Sec. "Drone Models": HOVER_RPM = sqrt(m g / (4 kf)); MAX_RPM from
  * (m, g, kf, T/W): the speed at which four rotors give T/W times the weight.
- * Reading for h_clip (Sec. "Aerodynamic effects", under Eq. (4), "derived
- * from the propeller radius and the model's maximum thrust"): the height at
- * which one rotor's ground-effect force at MAX_RPM equals MAX_THRUST/15. */
+ * Reading for h_clip (Sec. "Aerodynamic effects", Eq. (4); the text ties the
+ * clip height to r_p and MAX_THRUST without a formula): the height at which
+ * one rotor's ground-effect force at MAX_RPM equals MAX_THRUST/15. */
 void orc_derive(const orc_params *P, orc_derived *D)
 {
     D->hover_rpm = sqrt(P->m * P->g / (4.0 * P->kf));

@@ -225,10 +225,15 @@ hipError_t launch_l(const StepArgs &a, const LaunchCfg &cfg, int n_bins, int thr
     switch (cfg.sym) {
         case 0: return launch_u<MASK, ACT, 0>(a, cfg.unroll, n_bins, threads, lds, st);
         case 1: return launch_u<MASK, ACT, 1>(a, cfg.unroll, n_bins, threads, lds, st);
-        case 2: return launch_u<MASK, ACT, 2>(a, cfg.unroll, n_bins, threads, lds, st);
+        case 2:
         case 3:
-            // the rotation sweep is fully unrolled: no unroll variants
-            hipLaunchKernelGGL((rk4_kernel<MASK, ACT, 1, 3>), dim3(n_bins), dim3(threads), lds, st, a);
+            // the rotation sweep is unrolled in full, the permute sweep not at
+            // all (see cfg_valid): one instantiation each
+            if (cfg.unroll != 1) return hipErrorInvalidValue;
+            if (cfg.sym == 3)
+                hipLaunchKernelGGL((rk4_kernel<MASK, ACT, 1, 3>), dim3(n_bins), dim3(threads), lds, st, a);
+            else
+                hipLaunchKernelGGL((rk4_kernel<MASK, ACT, 1, 2>), dim3(n_bins), dim3(threads), lds, st, a);
             return hipGetLastError();
         default: return hipErrorInvalidValue;
     }

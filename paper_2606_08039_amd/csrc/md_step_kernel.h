@@ -573,13 +573,17 @@ hipError_t launch_l(const StepArgs &a, const LaunchCfg &cfg, int n_bins, int thr
     }
     if (cfg.sym) {
         if (cfg.lpd != 1) return hipErrorInvalidValue;
-        if (cfg.sym == 3) {
-            // the rotation sweep is fully unrolled: no unroll variants
-            hipLaunchKernelGGL((step_kernel<MASK, ACT, 1, 1, 3, DIST>), dim3(n_bins), dim3(threads), lds, st, a);
+        if (cfg.sym >= 2) {
+            // the rotation sweep is unrolled in full, the permute sweep not at
+            // all (see cfg_valid): one instantiation each
+            if (cfg.unroll != 1) return hipErrorInvalidValue;
+            if (cfg.sym == 3)
+                hipLaunchKernelGGL((step_kernel<MASK, ACT, 1, 1, 3, DIST>), dim3(n_bins), dim3(threads), lds, st, a);
+            else
+                hipLaunchKernelGGL((step_kernel<MASK, ACT, 1, 1, 2, DIST>), dim3(n_bins), dim3(threads), lds, st, a);
             return hipGetLastError();
         }
-        return cfg.sym == 2 ? launch_u<MASK, ACT, 1, 2, DIST>(a, cfg.unroll, n_bins, threads, lds, st)
-                            : launch_u<MASK, ACT, 1, 1, DIST>(a, cfg.unroll, n_bins, threads, lds, st);
+        return launch_u<MASK, ACT, 1, 1, DIST>(a, cfg.unroll, n_bins, threads, lds, st);
     }
     switch (cfg.lpd) {
         case 1: return launch_u<MASK, ACT, 1, 0, DIST>(a, cfg.unroll, n_bins, threads, lds, st);

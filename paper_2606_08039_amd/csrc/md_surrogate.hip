@@ -36,15 +36,24 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int KNN = 8;
+// Candidate lists: environments of at least LIST + 2 drones keep per drone its
+// LIST laterally nearest (in ascending slot order) and rank only those while
+// every drone of the bin stays within the list's margin (see knn_list).
+constexpr int LIST = 16;
+constexpr int LIST_MIN_ENV = LIST + 2;
+constexpr int MAX_BIN_WAVES = 4;  // 256 slots
 constexpr int FEAT_STRIDE = MLP_IN + 8;  // bf16 per staged feature row (144 B, 16 B aligned)
-constexpr int OUT_STRIDE = 8;
+// floats between the output rows, which overwrite the start of each drone's
+// input row once the network has read it (inputs and outputs of a pass
+// belong to the same 32 drones, whose inputs are loaded at the pass's start)
+constexpr int OUT_ROW = FEAT_STRIDE / 2;
 constexpr int W4_ROWS = 16;
 // offsets (in bf16 elements) of the permuted device weights
 constexpr int WOFF1 = 0, WOFF2 = WOFF1 + MLP_H * MLP_IN, WOFF3 = WOFF2 + MLP_H * MLP_H,
               WOFF4 = WOFF3 + MLP_H * MLP_H, WTOTAL = WOFF4 + W4_ROWS * MLP_H;
 constexpr int BOFF1 = 0, BOFF2 = 128, BOFF3 = 256, BOFF4 = 384, BTOTAL = 400;
 
-enum { J_ERR2 = 0, J_REF2, J_TERR2, J_N, J_FALLBACK, J_STEPS, J_NONFINITE, J_COUNT };
+enum { J_ERR2 = 0, J_REF2, J_TERR2, J_N, J_FALLBACK, J_STEPS, J_NONFINITE, J_FULLKNN, J_COUNT };
 
 struct SurrogateState {
     bf16 *W = nullptr;      // permuted bf16 weights [WTOTAL], fragment-major per layer
@@ -54,6 +63,7 @@ struct SurrogateState {
     float dz_ood = 1e-3f;
     float ood_speed = 0.f, ood_rel = 0.f, ood_tilt_s = 0.f;  // 0: check off
     int judge_stride = 64;
+    bool knn_reuse = true;
     bool loaded = false;
 };
 
@@ -67,6 +77,7 @@ struct SurArgs {
     float ood_speed, ood_rel;  // world speed / relative speed component bounds (0: off)
     float ood_tilt_s;          // sin^2(max tilt / 2) (0: off)
     int judge_mask;  // judge_stride - 1 (power of two), or -1 for no judging
+    int knn_reuse;   // candidate lists (1) or every drone ranked every step (0)
 };
 
 struct GenArgs {
@@ -100,49 +111,108 @@ __device__ __forceinline__ void load_drone(const StatePtr &s, int N, int di, Dro
     d.wz = s.w[2 * N + di];
 }
 
-// k nearest neighbours by horizontal distance among the environment's slots
-// [lo, lo + m) other than self, ascending, ties to the lower slot (= lower
-// drone index).  Lateral metric: the downwash (Eq. 6) varies with the lateral
-// offset on the centimetre scale of beta and with the height difference on
-// the metre scale, so the laterally closest drones are the ones that matter,
-// and a drone's column partner always lands in the first input slot.  The
-// squared distance is formed as dx*dx + dy*dy with every operation rounded
-// (no fused multiply-add), as the oracle forms it, so both sides take the
-// same integer decisions.
-__device__ __forceinline__ void knn8(const float4 *pos, int lo, int m, int mmax, int self, float px,
-                                     float py, int bj[KNN]) {
+// Squared horizontal distance of a candidate, formed as dx*dx + dy*dy with
+// every operation rounded (no fused multiply-add), as the oracle forms it, so
+// both sides take the same integer decisions.  The empty asm keeps the
+// arithmetic from being moved under the caller's branch on the candidate.
+__device__ __forceinline__ float knn_d2(float4 pj, float px, float py) {
 #pragma clang fp contract(off)
+    const float dx = pj.x - px, dy = pj.y - py;
+    const float a = dx * dx, b = dy * dy;
+    float d2 = a + b;
+    asm volatile("" : "+v"(d2));
+    return d2;
+}
+
+// One candidate into the ascending list (bd, bj) of the K nearest seen so
+// far.  Candidates arrive in ascending slot order and a candidate enters
+// only below a strictly larger distance, so ties go to the lower slot (=
+// the lower drone index).  bd is sorted, so the kept, shifted or inserted
+// distance of slot t is the median of bd[t - 1], bd[t] and d2.
+template <int K>
+__device__ __forceinline__ void knn_insert(float d2, int j, float (&bd)[K], int (&bj)[K]) {
+    // slots from the last down: the comparison of slot t - 1 is taken before
+    // that slot changes, and only two comparisons are live at a time
+    bool cn = d2 < bd[K - 1];
+#pragma unroll
+    for (int t = K - 1; t >= 1; --t) {
+        const bool cp = d2 < bd[t - 1];
+        bd[t] = __builtin_amdgcn_fmed3f(bd[t - 1], bd[t], d2);
+        bj[t] = cn ? (cp ? bj[t - 1] : j) : bj[t];
+        cn = cp;
+    }
+    bd[0] = cn ? d2 : bd[0];
+    bj[0] = cn ? j : bj[0];
+}
+
+// The K nearest neighbours by horizontal distance among the environment's
+// slots [lo, lo + m) other than self, ascending, ties to the lower slot.
+// Lateral metric: the downwash (Eq. 6) varies with the lateral offset on the
+// centimetre scale of beta and with the height difference on the metre
+// scale, so the laterally closest drones are the ones that matter, and a
+// drone's column partner always lands in the first input slot.  Masked and
+// non-finite candidates become +inf, which never enters.
+template <int K>
+__device__ __forceinline__ void knn_sweep(const float4 *pos, int lo, int m, int mmax, int self, float px, float py,
+                                          float (&bd)[K], int (&bj)[K]) {
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        bd[t] = __builtin_inff();
+        bj[t] = -1;
+    }
+    for (int jj = 0; jj < mmax; ++jj) {
+        const int j = lo + jj;
+        // read and formed by every lane (the position buffer holds 2 entries
+        // per slot, so lo + jj stays inside it)
+        float d2 = knn_d2(pos[j], px, py);
+        d2 = (jj < m && j != self && d2 < __builtin_inff()) ? d2 : __builtin_inff();
+        knn_insert<K>(d2, j, bd, bj);
+    }
+}
+
+// The 8 nearest from a drone's candidate list: LIST slot offsets from lo in
+// ascending order (0xff = empty), 4 per word.  Ranking the list in slot order
+// gives exactly knn_sweep's result whenever every drone the sweep would pick
+// is on the list (the caller's margin test).
+__device__ __forceinline__ void knn_list(const float4 *pos, int lo, const uint32_t (&L)[LIST / 4], float px,
+                                         float py, int (&bj)[KNN]) {
     float bd[KNN];
 #pragma unroll
     for (int t = 0; t < KNN; ++t) {
         bd[t] = __builtin_inff();
         bj[t] = -1;
     }
-    for (int jj = 0; jj < mmax; ++jj) {
-        const int j = lo + jj;
-        // formed by every lane (the position buffer holds 2 entries per slot,
-        // so lo + jj stays inside it); the empty asm keeps the read and the
-        // arithmetic from being moved under a branch on jj < m
-        const float4 pj = pos[j];
-        const float dx = pj.x - px, dy = pj.y - py;
-        const float a = dx * dx, b = dy * dy;
-        float d2 = a + b;
-        asm volatile("" : "+v"(d2));
-        // masked and non-finite candidates become +inf, which never enters
-        d2 = (jj < m && j != self && d2 < __builtin_inff()) ? d2 : __builtin_inff();
-        bool c[KNN];
 #pragma unroll
-        for (int t = 0; t < KNN; ++t) c[t] = d2 < bd[t];
-#pragma unroll
-        for (int t = KNN - 1; t >= 1; --t) {
-            // bd is sorted, so the kept, shifted or inserted distance of slot t
-            // is the median of bd[t - 1], bd[t] and d2
-            bd[t] = __builtin_amdgcn_fmed3f(bd[t - 1], bd[t], d2);
-            bj[t] = c[t] ? (c[t - 1] ? bj[t - 1] : j) : bj[t];
-        }
-        bd[0] = c[0] ? d2 : bd[0];
-        bj[0] = c[0] ? j : bj[0];
+    for (int t = 0; t < LIST; ++t) {
+        const uint32_t jj = (L[t >> 2] >> (8 * (t & 3))) & 0xffu;
+        const bool on = jj != 0xffu;
+        const int j = lo + (on ? (int)jj : 0);
+        float d2 = knn_d2(pos[j], px, py);
+        d2 = (on && d2 < __builtin_inff()) ? d2 : __builtin_inff();
+        knn_insert<KNN>(d2, j, bd, bj);
     }
+}
+
+// Fixed-order reductions over the 64 lanes of a wave (all lanes active):
+// pairs, quads, half rows and rows through DPP, then rows 1 and 3 take row
+// 0's and row 2's total (row_bcast:15) and row 3 takes rows 0-1's
+// (row_bcast:31); the result is lane 63's, returned to every lane.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+
+template <class Op>
+__device__ __forceinline__ float wave_reduce(float x, Op op) {
+    x = op(x, dpp_mov<0xb1, 0xf>(x));   // quad_perm [1, 0, 3, 2]
+    x = op(x, dpp_mov<0x4e, 0xf>(x));   // quad_perm [2, 3, 0, 1]
+    x = op(x, dpp_mov<0x141, 0xf>(x));  // row_half_mirror
+    x = op(x, dpp_mov<0x140, 0xf>(x));  // row_mirror
+    const float b15 = dpp_mov<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+    x = (threadIdx.x & 16) ? op(x, b15) : x;
+    const float b31 = dpp_mov<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+    x = (threadIdx.x & 32) ? op(x, b31) : x;
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
 // Raw surrogate inputs (see md.h): v_body, world up in the body frame, n/HOVER,
@@ -215,6 +285,39 @@ __device__ __forceinline__ void plain_aero(const KConst &c, uint32_t mask, const
         }
         Fz -= c.K1 * acc;
     }
+}
+
+// The plain downwash sum (Eq. 6, without K1) of every lane with `need`, the
+// whole wave evaluating one such drone at a time: lane l takes environment
+// slots l, l + 64, ... of that drone's environment, and the 64 partial sums
+// are added in wave_reduce's fixed tree, so a drone's sum depends only on its
+// place in its environment, not on the packing.  Costs one pass per drone
+// that needs it instead of a sweep by every lane of the wave whenever one
+// lane does.  All lanes must be active.
+__device__ __forceinline__ float dw_coop(const KConst &c, const float4 *pos, bool need, int lo, int m,
+                                         const Drone &d) {
+    const int lane = threadIdx.x & 63;
+    uint64_t todo = __ballot(need);
+    float mine = 0.f;
+    while (todo) {
+        const int f = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        const int flo = __builtin_amdgcn_readlane(lo, f), fm = __builtin_amdgcn_readlane(m, f);
+        const float fx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d.px), f));
+        const float fy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d.py), f));
+        const float fz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d.pz), f));
+        float acc = 0.f;
+        for (int base = 0; base < fm; base += 64) {
+            const int j = base + lane;
+            const float4 pj = pos[flo + min(j, fm - 1)];
+            const float t = c.dz_min > 0.f ? dw_term<true>(c, pj.x - fx, pj.y - fy, pj.z - fz)
+                                           : dw_term<false>(c, pj.x - fx, pj.y - fy, pj.z - fz);
+            acc += (j < fm) ? t : 0.f;  // the drone's own slot has dz = 0: no term
+        }
+        const float sum = wave_reduce(acc, [](float a, float b) { return a + b; });
+        mine = (lane == f) ? sum : mine;
+    }
+    return mine;
 }
 
 // qx^2 + qy^2 = sin^2(tilt / 2) with every operation rounded (no fused
@@ -338,7 +441,7 @@ __device__ __forceinline__ void mlp_wave(const bf16 *feat, float *out, const bf1
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
                         const int o = 4 * g + t;
-                        if (o < MLP_OUT) out[(16 * (t0 + dt) + r) * OUT_STRIDE + o] = acc[dt][t];
+                        if (o < MLP_OUT) out[(16 * (t0 + dt) + r) * OUT_ROW + o] = acc[dt][t];
                     }
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -360,11 +463,15 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
     const KConst &c = a.c;
     const int S = blockDim.x;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    float4 *posb = (float4 *)smem;              // [2][2S]
-    float4 *velb = posb + 4 * S;                // [2][2S]
-    bf16 *feat = (bf16 *)(velb + 4 * S);        // [S][FEAT_STRIDE]
-    float *outs = (float *)(feat + S * FEAT_STRIDE);  // [S][OUT_STRIDE]
+    // LDS (240 bytes per slot: eight one-wave workgroups fit a CU's 160 KB)
+    float4 *posb = (float4 *)smem;              // [2][2S] positions, double buffered
+    float4 *vel = posb + 4 * S;                 // [S] velocities (read before the step's second barrier)
+    bf16 *feat = (bf16 *)(vel + S);             // [S][FEAT_STRIDE] network inputs; a row's first
+                                                // 24 bytes then take its outputs (OUT_ROW floats apart)
+    uint4 *lst = (uint4 *)(feat + S * FEAT_STRIDE);   // [S] candidate lists, 16 slot offsets
+    float *wred = (float *)(lst + S);                 // [2][2][MAX_BIN_WAVES] per-wave max / min
     const int slot = threadIdx.x, lane = threadIdx.x & 63, wbase = threadIdx.x & ~63;
+    const int wave = threadIdx.x >> 6, n_waves = S >> 6;
     const int2 tab = a.bins.slot[blockIdx.x * S + slot];
     const int di = tab.x;
     const bool valid = di >= 0;
@@ -393,13 +500,39 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
     if (ACT == 4 && valid)
         for (int k = 0; k < 4; ++k) sp[k] = a.s.ctl[k * N + di];
     double jerr = 0.0, jref = 0.0, jterr = 0.0, jn = 0.0, jfb = 0.0, jnf = 0.0;
+    int nfull = 0;  // drone-steps that ranked the whole environment
     int phase = (ACT >= 1) ? (int)(a.step0 % (long long)c.decim) : 0;
     int oslot = 0;
+    // Candidate lists (bins whose largest environment has at least
+    // LIST_MIN_ENV drones).  At a rebuild every drone ranks its whole
+    // environment, keeps its LIST nearest (lateral distances, in slot order)
+    // and records where it stood (bx, by) and its margin
+    //   slack = (r_LIST - r_8) / 4
+    // (r_k its k-th nearest distance).  While the bin's largest lateral
+    // displacement since the rebuild, D, stays below the bin's smallest
+    // slack, ranking the list gives exactly the sweep's 8 nearest: each of
+    // the 8 nearest at the rebuild is now within r_8 + 2D, so the current
+    // 8th distance is at most that, while a drone off the list is at least
+    // r_LIST - 2D > r_8 + 2D away.  Margins are shrunk by 2^-18 against the
+    // float32 rounding of the distances.  Rebuilds are bin-wide, so that every
+    // displacement counts from the same step.
+    const bool use_list = sa.knn_reuse && mmax >= LIST_MIN_ENV;
+    float bx = d.px, by = d.py;
+    float S2 = -1.f;     // the bin's smallest slack squared (< 0: rebuild)
+    bool fresh = false;  // a rebuild in the previous step left its wave minima in wred
     for (int step = 0; step < a.n_steps; ++step) {
-        float4 *pos = posb + (step & 1) * 2 * S;
-        float4 *vel = velb + (step & 1) * 2 * S;
+        const int par = step & 1;
+        float4 *pos = posb + par * 2 * S;
         pos[slot] = make_float4(d.px, d.py, d.pz, 0.f);
         vel[slot] = make_float4(d.vx, d.vy, d.vz, 0.f);
+        if (use_list) {
+            // lateral displacement since the rebuild (non-finite: +inf, a rebuild)
+            const float ex = d.px - bx, ey = d.py - by;
+            float e2 = valid ? ex * ex + ey * ey : 0.f;
+            e2 = e2 < __builtin_inff() ? e2 : __builtin_inff();
+            const float wmax = wave_reduce(e2, [](float u, float v) { return fmaxf(u, v); });
+            if (lane == 0) wred[(par * 2 + 0) * MAX_BIN_WAVES + wave] = wmax;
+        }
         __syncthreads();
         const float *act = a.action + a.act_step_stride * step;
         if (ACT == 0) {
@@ -413,13 +546,75 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
             }
             phase = (phase + 1 == c.decim) ? 0 : phase + 1;
         }
+        // ---- neighbours: the candidate list, or the whole environment
+        int bj[KNN];
+        bool rebuild = true;
+        if (use_list) {
+            float D2 = 0.f;
+            for (int w = 0; w < n_waves; ++w) D2 = fmaxf(D2, wred[(par * 2 + 0) * MAX_BIN_WAVES + w]);
+            if (fresh) {
+                // the rebuild's wave minima, written before this step's barrier
+                float sm = __builtin_inff();
+                for (int w = 0; w < n_waves; ++w) sm = fminf(sm, wred[((par ^ 1) * 2 + 1) * MAX_BIN_WAVES + w]);
+                S2 = sm > 0.f ? sm * sm : -1.f;
+                fresh = false;
+            }
+            rebuild = !(D2 < S2);
+        }
+        if (!use_list) {
+            float bd[KNN];
+            knn_sweep<KNN>(pos, lo, menv, mmax, slot, d.px, d.py, bd, bj);
+        } else if (rebuild) {
+            float bd[LIST];
+            int bl[LIST];
+            knn_sweep<LIST>(pos, lo, menv, mmax, slot, d.px, d.py, bd, bl);
+#pragma unroll
+            for (int t = 0; t < KNN; ++t) bj[t] = bl[t];
+            // the list in slot order: every candidate at or before the LIST-th
+            // in (distance, slot) order, found by a second pass
+            const float r2 = bd[LIST - 1];
+            const int rj = bl[LIST - 1];
+            uint32_t L[LIST / 4] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
+            int cnt = 0;
+            for (int jj = 0; jj < mmax; ++jj) {
+                const int j = lo + jj;
+                const float d2 = knn_d2(pos[j], d.px, d.py);
+                const bool in = jj < menv && j != slot && d2 < __builtin_inff() &&
+                                (rj < 0 || d2 < r2 || (d2 == r2 && j <= rj));
+                if (in) {
+                    // byte cnt of the list (at most LIST candidates pass)
+                    const int w = cnt >> 2, sh = 8 * (cnt & 3);
+                    const uint32_t v = (uint32_t)jj << sh, keep = ~(0xffu << sh);
+                    L[0] = w == 0 ? ((L[0] & keep) | v) : L[0];
+                    L[1] = w == 1 ? ((L[1] & keep) | v) : L[1];
+                    L[2] = w == 2 ? ((L[2] & keep) | v) : L[2];
+                    L[3] = w == 3 ? ((L[3] & keep) | v) : L[3];
+                    ++cnt;
+                }
+            }
+            lst[slot] = make_uint4(L[0], L[1], L[2], L[3]);
+            // margin of this drone (+inf when the list holds its whole environment)
+            float slack = __builtin_inff();
+            if (valid && r2 < __builtin_inff())
+                slack = 0.25f * (fsqrt(r2) * (1.f - 0x1p-18f) - fsqrt(bd[KNN - 1]) * (1.f + 0x1p-18f));
+            slack = slack == slack ? slack : -1.f;
+            const float wmin = wave_reduce(slack, [](float u, float v) { return fminf(u, v); });
+            if (lane == 0) wred[(par * 2 + 1) * MAX_BIN_WAVES + wave] = wmin;
+            fresh = true;
+            S2 = -1.f;
+            bx = d.px;
+            by = d.py;
+        } else {
+            const uint4 lv = lst[slot];
+            const uint32_t L[LIST / 4] = {lv.x, lv.y, lv.z, lv.w};
+            knn_list(pos, lo, L, d.px, d.py, bj);
+        }
+        nfull += (valid && rebuild) ? 1 : 0;
         // ---- features -> standardised bfloat16 row
         bool ood;
         float f[MLP_IN];
         {
             const Rot R = rot_of(d);
-            int bj[KNN];
-            knn8(pos, lo, menv, mmax, slot, d.px, d.py, bj);
             ood = features(c, d, R, n, pos, vel, bj, sa.dz_ood, sa.ood_rel, f);
         }
         // outside the trained region: fast or tilted drones take the plain terms
@@ -436,7 +631,7 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
             *(bf16x8 *)(row + k) = v;
         }
         __syncthreads();
-        mlp_wave(feat + wbase * FEAT_STRIDE, outs + wbase * OUT_STRIDE, sa.W, sa.b, lane);
+        mlp_wave(feat + wbase * FEAT_STRIDE, (float *)(feat + wbase * FEAT_STRIDE), sa.W, sa.b, lane);
         __syncthreads();
         // the rotation and the rotor terms are formed from the (unchanged)
         // attitude and rotor speeds after the network instead of being held in
@@ -448,7 +643,7 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
         const Rot R = rot_of(d);
         float y[MLP_OUT];
 #pragma unroll
-        for (int o = 0; o < MLP_OUT; ++o) y[o] = outs[slot * OUT_STRIDE + o] * ysd[o] + ym[o];
+        for (int o = 0; o < MLP_OUT; ++o) y[o] = ((const float *)feat)[slot * OUT_ROW + o] * ysd[o] + ym[o];
         float Fx = R.r02 * T, Fy = R.r12 * T, Fz = R.r22 * T - c.mg;
         float ax, ay, az;
         // surrogate force, body -> world
@@ -457,8 +652,14 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
         const float sz = R.r20 * y[0] + R.r21 * y[1] + R.r22 * y[2];
         const bool judge = valid && !ood && sa.judge_mask >= 0 &&
                            (((unsigned)di + (unsigned)(a.step0 + step)) & (unsigned)sa.judge_mask) == 0u;
+        // plain terms for the drones that fall back or are judged: ground
+        // effect and drag per lane, the downwash sweep by the whole wave per drone
         float px_ = 0.f, py_ = 0.f, pz_ = 0.f;
-        if (ood || judge) plain_aero(c, 7u, d, R, n, T, pos, lo, menv, mmax, px_, py_, pz_);
+        const float dws = dw_coop(c, pos, ood || judge, lo, menv, d);
+        if (ood || judge) {
+            plain_aero(c, 3u, d, R, n, T, pos, lo, menv, mmax, px_, py_, pz_);
+            pz_ -= c.K1 * dws;
+        }
         if (ood) {
             ax = px_;
             ay = py_;
@@ -522,7 +723,9 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
         const double s0 = wave_sum(jerr), s1 = wave_sum(jref), s2 = wave_sum(jterr), s3 = wave_sum(jn),
                      s4 = wave_sum(jfb), s5 = wave_sum(jnf);
         const double steps = wave_sum(valid ? (double)a.n_steps : 0.0);
+        const double s6 = wave_sum((double)nfull);
         if (lane == 0) {
+            atomicAdd(sa.judge + J_FULLKNN, s6);
             atomicAdd(sa.judge + J_ERR2, s0);
             atomicAdd(sa.judge + J_REF2, s1);
             atomicAdd(sa.judge + J_TERR2, s2);
@@ -563,7 +766,10 @@ __global__ void __launch_bounds__(256) datagen_kernel(GenArgs g) {
     motor(c, n, T, tx, ty, tz);
     const Rot R = rot_of(d);
     int bj[KNN];
-    knn8(pos, lo, menv, mmax, slot, d.px, d.py, bj);
+    {
+        float bd[KNN];
+        knn_sweep<KNN>(pos, lo, menv, mmax, slot, d.px, d.py, bd, bj);
+    }
     float f[MLP_IN];
     (void)features(c, d, R, n, pos, vel, bj, 0.f, 0.f, f);
     float *x = g.X + (long long)di * MLP_IN;
@@ -588,7 +794,8 @@ __global__ void __launch_bounds__(256) datagen_kernel(GenArgs g) {
 }  // namespace
 
 size_t sur_lds_bytes(int S) {
-    return sizeof(float4) * 8 * (size_t)S + sizeof(bf16) * (size_t)S * FEAT_STRIDE + sizeof(float) * (size_t)S * OUT_STRIDE;
+    return sizeof(float4) * 5 * (size_t)S + sizeof(bf16) * (size_t)S * FEAT_STRIDE + sizeof(uint4) * (size_t)S +
+           sizeof(float) * 4 * MAX_BIN_WAVES;
 }
 
 hipError_t launch_sur_step(const SurArgs &sa, int act, int n_bins, int S, hipStream_t st) {
@@ -625,8 +832,8 @@ static md_status sur_alloc(md_ctx *ctx) {
     hipError_t e = hipMalloc(&S->W, sizeof(bf16) * WTOTAL);
     if (e == hipSuccess) e = hipMalloc(&S->b, sizeof(float) * BTOTAL);
     if (e == hipSuccess) e = hipMalloc(&S->norm, sizeof(float) * MLP_NORM);
-    if (e == hipSuccess) e = hipMalloc(&S->judge, sizeof(double) * 8);
-    if (e == hipSuccess) e = hipMemset(S->judge, 0, sizeof(double) * 8);
+    if (e == hipSuccess) e = hipMalloc(&S->judge, sizeof(double) * J_COUNT);
+    if (e == hipSuccess) e = hipMemset(S->judge, 0, sizeof(double) * J_COUNT);
     if (e != hipSuccess) {
         ctx->err = hip_msg("surrogate buffers", e);
         return MD_E_OOM;
@@ -736,6 +943,7 @@ md_status surrogate_step(md_ctx *ctx, const md_state *s, const float *d_action, 
     sa.ood_rel = ctx->sur->ood_rel;
     sa.ood_tilt_s = ctx->sur->ood_tilt_s;
     sa.judge_mask = ctx->sur->judge_stride > 0 ? ctx->sur->judge_stride - 1 : -1;
+    sa.knn_reuse = ctx->sur->knn_reuse ? 1 : 0;
     hipError_t e = launch_sur_step(sa, ctx->act, bs->n_bins, bs->slots, st);
     if (e != hipSuccess) {
         ctx->err = hip_msg("surrogate step launch", e);
@@ -775,7 +983,7 @@ md_status datagen(md_ctx *ctx, const md_state *s, uint32_t mask, float *d_X, flo
 md_status judge_stats(md_ctx *ctx, md_judge *out) {
     std::memset(out, 0, sizeof *out);
     if (!ctx->sur || !ctx->sur->judge) return MD_OK;
-    double h[8];
+    double h[J_COUNT];
     hipError_t e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipMemcpy(h, ctx->sur->judge, sizeof h, hipMemcpyDeviceToHost);
     if (e != hipSuccess) {
@@ -790,12 +998,13 @@ md_status judge_stats(md_ctx *ctx, md_judge *out) {
     out->n_drone_steps = h[J_STEPS];
     out->n_nonfinite = h[J_NONFINITE];
     out->force_rel_err = std::sqrt(h[J_ERR2] / h[J_REF2]);  // NaN when nothing was judged
+    out->n_knn_full = h[J_FULLKNN];
     return MD_OK;
 }
 
 md_status judge_reset(md_ctx *ctx) {
     if (!ctx->sur || !ctx->sur->judge) return MD_OK;
-    if (hipMemset(ctx->sur->judge, 0, sizeof(double) * 8) != hipSuccess) return MD_E_HIP;
+    if (hipMemset(ctx->sur->judge, 0, sizeof(double) * J_COUNT) != hipSuccess) return MD_E_HIP;
     return MD_OK;
 }
 
@@ -839,6 +1048,17 @@ md_status md_set_surrogate_ood(md_ctx *ctx, float max_speed, float max_rel_speed
     ctx->sur->ood_speed = max_speed;
     ctx->sur->ood_rel = max_rel_speed;
     ctx->sur->ood_tilt_s = max_tilt > 0.f ? (float)(sh * sh) : 0.f;
+    return MD_OK;
+}
+
+md_status md_set_surrogate_knn_reuse(md_ctx *ctx, int reuse) {
+    if (!ctx) return MD_E_INVALID_ARG;
+    if (!ctx->sur || !ctx->sur->loaded) {
+        ctx->err = "md_set_surrogate_knn_reuse: no surrogate loaded";
+        return MD_E_INVALID_ARG;
+    }
+    md::invalidate_graphs(ctx);
+    ctx->sur->knn_reuse = reuse != 0;
     return MD_OK;
 }
 

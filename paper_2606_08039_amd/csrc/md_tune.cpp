@@ -45,6 +45,11 @@ bool cfg_valid(const md_ctx *ctx, const LaunchCfg &c) {
     if (c.sym < 0 || c.sym > 3) return false;
     if (c.sym && c.lpd != 1) return false;
     if (c.sym == 2 && ctx->max_m > 64) return false;  // environments inside one wave
+    // the permute loop's trip count is the bin's largest environment, and a
+    // loop of cross-lane permutes cannot be unrolled with a remainder (each
+    // permute must run with the whole wave): its unroll variants would be
+    // the same code, so only unroll 1 exists
+    if (c.sym == 2 && c.unroll != 1) return false;
     if (c.sym == 3) {
         // one power-of-two environment size 2..64
         const int m = ctx->uniform_m;

@@ -376,7 +376,7 @@ def mlp_flatten(parts):
 class md_judge(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("n_judged", "force_err2", "force_ref2", "torque_err2",
                                                 "n_fallback", "n_drone_steps", "force_rel_err",
-                                                "n_nonfinite")]
+                                                "n_nonfinite", "n_knn_full")]
 
 
 def md_load_surrogate(ctx, flat, norm, dz_ood=1e-3, judge_stride=64):
@@ -404,6 +404,10 @@ def md_judge_stats(ctx):
 
 def md_set_surrogate_ood(ctx, max_speed=0.0, max_rel_speed=0.0, max_tilt=0.0):
     check(lib().md_set_surrogate_ood(ctx, float(max_speed), float(max_rel_speed), float(max_tilt)), ctx)
+
+
+def md_set_surrogate_knn_reuse(ctx, reuse=True):
+    check(lib().md_set_surrogate_knn_reuse(ctx, int(bool(reuse))), ctx)
 
 
 def md_judge_reset(ctx):

@@ -12,7 +12,7 @@ from paper_2606_08039_amd import md, workloads as wl
 pytestmark = pytest.mark.gpu
 
 
-def shfl(waves=1, unroll=2):
+def shfl(waves=1, unroll=1):
     return dict(lanes_per_drone=1, unroll=unroll, waves_per_group=waves, pair_symmetric=2)
 
 

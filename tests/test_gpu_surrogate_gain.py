@@ -42,19 +42,34 @@ def test_trained_network_on_held_out_samples():
     print("held-out force error: surrogate %.4f, no aero %.4f (training record %s)"
           % (eps, eps_none, meta.get("eps_held_out")))
     assert eps_none == pytest.approx(1.0)
-    assert eps < 0.05
+    assert eps <= 0.02  # the <= 2 % residual-force error of the surrogate's contract
 
 
-def _rollout(w, mask, flat=None, norm=None, steps=480):
+# Fallback bounds of the trained network's region (lattice flights: speeds
+# below 1 m/s, neighbour relative speeds below 1.2 m/s, tilts below half a
+# degree), with margin: world speed 1.5 m/s, relative speed 2 m/s, tilt 2
+# degrees; and the downwash singularity below 1 mm.
+DZ_OOD, OOD = 1e-3, (1.5, 2.0, float(np.radians(2.0)))
+
+
+def _rollout(w, mask, flat=None, norm=None, steps=480, warm=60):
+    """steps PID steps from the workload's initial state; the judge counts
+    the steps after the first `warm` (the start-up transient, whose first
+    corrections drive rotor speeds outside the range the network was trained
+    on, as the bench's warm-up launches do)."""
     import torch
     p = md.md_default_params_cf2x()
     ctx = md.md_create(p, w["dt"], mask, md.MD_ACT_PID, w["ctrl_decim"])
     md.md_bind_layout(ctx, w["env_offsets"])
     if mask & md.MD_AERO_SURROGATE:
-        md.md_load_surrogate(ctx, flat, norm, 1e-3, 16)
+        md.md_load_surrogate(ctx, flat, norm, DZ_OOD, 16)
+        md.md_set_surrogate_ood(ctx, *OOD)
     st = md.DeviceState.from_numpy(w["state"])
     act = torch.from_numpy(w["action"]).cuda()
-    md.md_step(ctx, st, act, False, None, 0, steps, 0)
+    md.md_step(ctx, st, act, False, None, 0, warm, 0)
+    if mask & md.MD_AERO_SURROGATE:
+        md.md_judge_reset(ctx)
+    md.md_step(ctx, st, act, False, None, 0, steps - warm, warm)
     torch.cuda.synchronize()
     j = md.md_judge_stats(ctx) if mask & md.MD_AERO_SURROGATE else None
     md.md_destroy(ctx)
@@ -72,10 +87,11 @@ def test_in_step_surrogate_tracks_the_plain_model():
     rms = lambda a: float(np.sqrt(np.mean(np.sum((a["p"] - plain["p"]) ** 2, axis=0)[lower])))
     e_sur, e_none = rms(sur), rms(none)
     print("2 s rollouts, RMS position gap to plain aero (lower layer): surrogate %.4g m, "
-          "no aero %.4g m; judge eps %.4f over %d samples"
-          % (e_sur, e_none, judge["force_rel_err"], judge["n_judged"]))
+          "no aero %.4g m; judge eps %.4f over %d samples, %.2f %% of drone-steps on the fallback"
+          % (e_sur, e_none, judge["force_rel_err"], judge["n_judged"],
+             100.0 * judge["n_fallback"] / judge["n_drone_steps"]))
     assert e_sur < 0.2 * e_none
-    assert judge["force_rel_err"] < 0.1
+    assert judge["force_rel_err"] <= 0.02
 
 
 def test_training_pipeline_beats_the_aero_free_baseline():

@@ -67,6 +67,9 @@ def test_invalid_configs_are_rejected():
         md.md_set_launch_config(g.ctx, lanes_per_drone=2, pair_symmetric=1, waves_per_group=2)
     with pytest.raises(md.MdError):
         md.md_set_launch_config(g.ctx, lanes_per_drone=3)
+    with pytest.raises(md.MdError):  # the permute sweep exists with unroll 1 only
+        md.md_set_launch_config(g.ctx, lanes_per_drone=1, unroll=2, pair_symmetric=2)
+    md.md_set_launch_config(g.ctx, lanes_per_drone=1, unroll=1, pair_symmetric=2)
     g.close()
 
 
