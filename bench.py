@@ -210,6 +210,7 @@ def timed_rollouts(args, w, p, with_obs, mask=None, integrator=None, surrogate_w
             flat, norm = surrogate_weights
             md.md_load_surrogate(ctx, flat, norm, SUR_DZ_OOD, 64)
             md.md_set_surrogate_ood(ctx, *SUR_OOD)
+            md.md_set_surrogate_region(ctx, *SUR_REGION)
         state = md.DeviceState.from_numpy(w["state"])
         dr_t = None
         if dr is not None:
@@ -272,12 +273,16 @@ def timed_rollouts(args, w, p, with_obs, mask=None, integrator=None, surrogate_w
     return wall, kernel_ms, cfg, judge, check_state
 
 
-# Surrogate fallback: the downwash singularity (dz below 1 mm) and the edge of
-# the training data (lattice flights: speeds below 1 m/s, neighbour relative
-# speeds below 1.2 m/s, tilts below half a degree): world speed 1.5 m/s,
-# relative speed 2 m/s, tilt 2 degrees.
-SUR_DZ_OOD = 1e-3
+# Surrogate fallback: the downwash singularity (a neighbour above by less
+# than 10 um) and the edge of the training data (lattice flights: speeds below
+# 1 m/s, neighbour relative speeds below 1.2 m/s, tilts below half a degree,
+# column partners 0.8-1.45 m apart vertically, same-layer neighbours at least
+# 0.9 m apart laterally): world speed 1.5 m/s, relative speed 2 m/s, tilt 2
+# degrees, a neighbour inside |dz| < 0.75 m and dxy < 0.85 m (outside it
+# Eq. 6 stays below 1e-4 N for 10 um < dz < 0.75 m) or beyond |dz| > 3 m.
+SUR_DZ_OOD = 1e-5
 SUR_OOD = (1.5, 2.0, float(np.radians(2.0)))
+SUR_REGION = (0.75, 0.85, 3.0)
 
 
 def surrogate_leg(args, w, p, with_obs):
@@ -302,10 +307,51 @@ def surrogate_leg(args, w, p, with_obs):
             "judge_force_rel_err": j["force_rel_err"], "judged_drone_steps": j["n_judged"],
             "judge_nonfinite": j["n_nonfinite"], "final_state": chk,
             "fallback_fraction": j["n_fallback"] / max(j["n_drone_steps"], 1.0),
+            "full_ranking_fraction": j["n_knn_full"] / max(j["n_drone_steps"], 1.0),
             "held_out_force_rel_err": meta.get("eps_held_out"),
             "fallback_bounds": {"dz": SUR_DZ_OOD, "speed": SUR_OOD[0], "rel_speed": SUR_OOD[1],
-                                "tilt_rad": SUR_OOD[2]},
+                                "tilt_rad": SUR_OOD[2], "near_dz": SUR_REGION[0], "near_r": SUR_REGION[1],
+                                "far_dz": SUR_REGION[2]},
             "weights": os.path.relpath(path, ROOT)}
+
+
+# Uniform two-layer lattices (the trained network's neighbourhood: one
+# column partner, the rest of the layer laterally) from 8 to 512 drones per
+# environment, the same number of drones at every size.
+CROSSOVER_SHAPES = {8: (2, 2, 2), 16: (4, 2, 2), 32: (4, 4, 2), 64: (8, 4, 2), 128: (8, 8, 2), 256: (16, 8, 2),
+                    512: (16, 16, 2)}
+
+
+def crossover_leg(args, p, n_drones=262144, steps=250):
+    """Plain full aero (autotuned) against the learned residual on the
+    CROSSOVER_SHAPES lattices: PID waypoints, no observation writes, one
+    warm-up and three timed launches of `steps` steps each; rates from the
+    kernel time.  The plain step's neighbour sweep grows as M, the network's
+    cost per drone does not, so the surrogate would win beyond some M."""
+    from paper_2606_08039_amd import workloads as wl
+
+    class A:
+        pass
+    a = A()
+    a.steps, a.warmup, a.no_tune, a.weights = 3, 1, False, args.weights
+    rows = []
+    for M, shape in CROSSOVER_SHAPES.items():
+        w = wl.lattice(n_envs=n_drones // M, shape=shape, n_steps=steps, seed=40 + M)
+        n = int(w["env_offsets"][-1])
+        _, kms, cfg, _, _ = timed_rollouts(a, w, p, False)
+        plain = n * steps / (float(np.mean(kms)) * 1e-3)
+        sur = surrogate_leg(a, w, p, False)
+        srate = n * steps / (sur["kernel_ms_avg"] * 1e-3) if sur.get("value") else None
+        rows.append({"M": M, "lattice": "x".join(map(str, shape)), "n_envs": n // M,
+                     "plain": plain, "plain_ms": float(np.mean(kms)), "plain_config": cfg,
+                     "surrogate": srate, "surrogate_ms": sur.get("kernel_ms_avg"),
+                     "surrogate_over_plain": (srate / plain) if srate else None,
+                     "judge_force_rel_err": sur.get("judge_force_rel_err"),
+                     "fallback_fraction": sur.get("fallback_fraction"),
+                     "full_ranking_fraction": sur.get("full_ranking_fraction")})
+    won = [r["M"] for r in rows if r["surrogate_over_plain"] and r["surrogate_over_plain"] >= 1.0]
+    return {"unit": "drone-steps/s", "drones": n_drones, "steps_per_launch": steps, "rows": rows,
+            "crossover_M": min(won) if won else None}
 
 
 DR_SEED = 50
@@ -427,6 +473,8 @@ def main():
                     help="launch configuration lanes_per_drone,unroll,waves_per_group,pair_symmetric "
                          "for the plain leg (instead of autotuning)")
     ap.add_argument("--weights", default=None, help="surrogate weights file")
+    ap.add_argument("--crossover", action="store_true",
+                    help="also run plain vs surrogate on uniform lattices of 8..512 drones per environment")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -527,6 +575,8 @@ def main():
     if not args.no_wind:
         out["wind"] = wind_leg(args, w, p, with_obs)
         out["wind"]["speed_vs_plain"] = out["wind"]["value"] / value
+    if args.crossover:
+        out["crossover"] = crossover_leg(args, p)
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)

@@ -518,13 +518,25 @@ typedef struct md_judge {
 } md_judge;
 md_status md_judge_stats(md_ctx *ctx, md_judge *out);
 
+/* Region fallback of the loaded surrogate (each bound 0 = that check off;
+ * loading a network turns both off): a drone with a neighbour among its 8
+ * nearest inside the cylinder |dz| < near_dz, horizontal distance < near_r
+ * (above or below: a near neighbour where Eq. 6 grows without bound and the
+ * network has seen no samples), or farther than far_dz vertically, takes the
+ * plain Eq. 4-6 terms for that step.  dz is the difference of the stored
+ * heights and the squared horizontal distance is formed as for the neighbour
+ * ranking (dx*dx + dy*dy, each operation rounded), compared with the float
+ * of near_r^2.  MD_E_INVALID_ARG without a loaded surrogate or for a
+ * negative bound. */
+md_status md_set_surrogate_region(md_ctx *ctx, float near_dz, float near_r, float far_dz);
+
 /* Neighbour candidate lists of the surrogate step (on after
- * md_load_surrogate*).  In bins whose largest environment has at least 18
+ * md_load_surrogate*).  In bins whose largest environment has at least 14
  * drones, each drone ranks its whole environment only at a rebuild, keeps
- * its 16 laterally nearest and, until the next rebuild, ranks only those: a
+ * its 12 laterally nearest and, until the next rebuild, ranks only those: a
  * bin rebuilds at the first step of every launch and whenever its largest
  * lateral displacement since the last rebuild reaches a quarter of its
- * smallest gap between a drone's 16th and 8th nearest distances (margins
+ * smallest gap between a drone's 12th and 8th nearest distances (margins
  * shrunk against float32 rounding), which guarantees the same 8 neighbours
  * in the same order as ranking the whole environment.  Results are bitwise
  * those of reuse 0, which ranks every drone every step.  MD_E_INVALID_ARG

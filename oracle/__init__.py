@@ -52,7 +52,8 @@ class Derived(ctypes.Structure):
 
 class Net(ctypes.Structure):
     _fields_ = [("W", _D_T * 4), ("b", _D_T * 4), ("norm", _D_T), ("dz_ood", ctypes.c_double),
-                ("ood_speed", ctypes.c_double), ("ood_rel_speed", ctypes.c_double), ("ood_tilt", ctypes.c_double)]
+                ("ood_speed", ctypes.c_double), ("ood_rel_speed", ctypes.c_double), ("ood_tilt", ctypes.c_double),
+                ("near_dz", ctypes.c_double), ("near_r", ctypes.c_double), ("far_dz", ctypes.c_double)]
 
 
 class _CState(ctypes.Structure):
@@ -532,7 +533,8 @@ def bf16_round(x):
     return np.vectorize(f, otypes=[np.float64])(np.asarray(x, dtype=np.float64))
 
 
-def make_net(flat_params, norm, dz_ood, ood_speed=0.0, ood_rel_speed=0.0, ood_tilt=0.0):
+def make_net(flat_params, norm, dz_ood, ood_speed=0.0, ood_rel_speed=0.0, ood_tilt=0.0,
+             near_dz=0.0, near_r=0.0, far_dz=0.0):
     """The surrogate as the oracle evaluates it: weight matrices rounded to
     bfloat16 (as the in-step network stores them), biases and normalisation
     as given (float32 values), fallback thresholds as float32 values.
@@ -556,6 +558,9 @@ def make_net(flat_params, norm, dz_ood, ood_speed=0.0, ood_rel_speed=0.0, ood_ti
     net.ood_speed = float(np.float32(ood_speed))
     net.ood_rel_speed = float(np.float32(ood_rel_speed))
     net.ood_tilt = float(ood_tilt)
+    net.near_dz = float(np.float32(near_dz))
+    net.near_r = float(np.float32(near_r))
+    net.far_dz = float(np.float32(far_dz))
     return net, (Ws, bs, nrm)
 
 

@@ -1326,7 +1326,9 @@ void orc_adam(int n, double *param, const double *grad, double *m1, double *m2, 
  * nearest neighbours (binary32 decisions, see orc_knn) and the raw inputs;
  * fallback -> the plain Eq. (4)-(6) force when a neighbour is above by less
  * than dz_ood, or (each check optional) when the drone leaves the region the
- * network was trained on: a world velocity component beyond ood_speed, a
+ * network was trained on: a neighbour inside the cylinder |dz| < near_dz,
+ * horizontal distance < near_r, or beyond |dz| > far_dz, a world velocity
+ * component beyond ood_speed, a
  * neighbour's relative velocity component beyond ood_rel_speed, or a tilt
  * beyond ood_tilt (qx^2 + qy^2 > sin^2(ood_tilt / 2)).  Every fallback
  * decision is taken in binary32 on quantities the GPU forms exactly the same
@@ -1405,10 +1407,19 @@ int orc_step_surrogate(const orc_params *P, double dt, int act_type, int ctrl_de
                 const int32_t *nb = nbr + (size_t)i * K;
                 int ood = 0;
                 const float vrel = (float)net->ood_rel_speed;
+                const int near_on = net->near_dz > 0.0 && net->near_r > 0.0;
+                const float near_r2 = (float)(net->near_r * net->near_r);
                 for (int t = 0; t < K; ++t) {
                     if (nb[t] < 0) continue;
                     const float dz = (float)p_pre[2 * N + nb[t]] - (float)p_pre[2 * N + i];
                     if (dz > 0.0f && dz < (float)net->dz_ood) ood = 1;
+                    /* the horizontal distance squared as the neighbour ranking forms it */
+                    volatile float dx = (float)p_pre[0 * N + nb[t]] - (float)p_pre[0 * N + i];
+                    volatile float dy = (float)p_pre[1 * N + nb[t]] - (float)p_pre[1 * N + i];
+                    volatile float ax = dx * dx, ay = dy * dy;
+                    volatile float d2 = ax + ay;
+                    if (near_on && fabsf(dz) < (float)net->near_dz && d2 < near_r2) ood = 1;
+                    if (net->far_dz > 0.0 && fabsf(dz) > (float)net->far_dz) ood = 1;
                     for (int c = 0; c < 3 && vrel > 0.0f; ++c) {
                         const float dv = (float)v_pre[c * N + nb[t]] - (float)v_pre[c * N + i];
                         if (fabsf(dv) > vrel) ood = 1;

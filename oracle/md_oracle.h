@@ -198,6 +198,9 @@ typedef struct orc_net {
      * component above ood_speed, a neighbour's relative speed component
      * above ood_rel_speed, tilt above ood_tilt (rad) */
     double ood_speed, ood_rel_speed, ood_tilt;
+    /* region fallback (0 = off): a neighbour among the 8 inside the cylinder
+     * |dz| < near_dz, horizontal distance < near_r, or with |dz| > far_dz */
+    double near_dz, near_r, far_dz;
 } orc_net;
 
 int orc_step_surrogate(const orc_params *P, double dt, int act_type, int ctrl_decim, int n_envs,

@@ -39,9 +39,11 @@ constexpr int KNN = 8;
 // Candidate lists: environments of at least LIST + 2 drones keep per drone its
 // LIST laterally nearest (in ascending slot order) and rank only those while
 // every drone of the bin stays within the list's margin (see knn_list).
-constexpr int LIST = 16;
+constexpr int LIST = 12;
 constexpr int LIST_MIN_ENV = LIST + 2;
-constexpr int MAX_BIN_WAVES = 4;  // 256 slots
+static_assert(LIST % 2 == 0 && LIST <= 12, "a list is at most six words of 16-bit slot offsets");
+constexpr int MAX_SLOTS = 512;  // environments of up to 512 drones
+constexpr int MAX_BIN_WAVES = MAX_SLOTS / 64;
 constexpr int FEAT_STRIDE = MLP_IN + 8;  // bf16 per staged feature row (144 B, 16 B aligned)
 // floats between the output rows, which overwrite the start of each drone's
 // input row once the network has read it (inputs and outputs of a pass
@@ -62,6 +64,7 @@ struct SurrogateState {
     double *judge = nullptr;
     float dz_ood = 1e-3f;
     float ood_speed = 0.f, ood_rel = 0.f, ood_tilt_s = 0.f;  // 0: check off
+    float near_dz = 0.f, near_r2 = 0.f, far_dz = 0.f;         // region fallback, 0: off
     int judge_stride = 64;
     bool knn_reuse = true;
     bool loaded = false;
@@ -75,6 +78,7 @@ struct SurArgs {
     double *judge;
     float dz_ood;
     float ood_speed, ood_rel;  // world speed / relative speed component bounds (0: off)
+    float near_dz, near_r2, far_dz;  // region fallback (near_dz 0: cylinder off; far_dz 0: off)
     float ood_tilt_s;          // sin^2(max tilt / 2) (0: off)
     int judge_mask;  // judge_stride - 1 (power of two), or -1 for no judging
     int knn_reuse;   // candidate lists (1) or every drone ranked every step (0)
@@ -170,11 +174,12 @@ __device__ __forceinline__ void knn_sweep(const float4 *pos, int lo, int m, int 
     }
 }
 
-// The 8 nearest from a drone's candidate list: LIST slot offsets from lo in
-// ascending order (0xff = empty), 4 per word.  Ranking the list in slot order
-// gives exactly knn_sweep's result whenever every drone the sweep would pick
-// is on the list (the caller's margin test).
-__device__ __forceinline__ void knn_list(const float4 *pos, int lo, const uint32_t (&L)[LIST / 4], float px,
+// The 8 nearest from a drone's candidate list: LIST (at most 12) 16-bit slot
+// offsets from lo in ascending order, 2 per word; unused entries hold the
+// drone's own offset (never a member).  Ranking the list in slot order gives
+// exactly knn_sweep's result whenever every drone the sweep would pick is on
+// the list (the caller's margin test).
+__device__ __forceinline__ void knn_list(const float4 *pos, int lo, int self, const uint32_t (&L)[6], float px,
                                          float py, int (&bj)[KNN]) {
     float bd[KNN];
 #pragma unroll
@@ -184,9 +189,8 @@ __device__ __forceinline__ void knn_list(const float4 *pos, int lo, const uint32
     }
 #pragma unroll
     for (int t = 0; t < LIST; ++t) {
-        const uint32_t jj = (L[t >> 2] >> (8 * (t & 3))) & 0xffu;
-        const bool on = jj != 0xffu;
-        const int j = lo + (on ? (int)jj : 0);
+        const int j = lo + (int)((L[t >> 1] >> (16 * (t & 1))) & 0xffffu);
+        const bool on = j != self;
         float d2 = knn_d2(pos[j], px, py);
         d2 = (on && d2 < __builtin_inff()) ? d2 : __builtin_inff();
         knn_insert<KNN>(d2, j, bd, bj);
@@ -218,11 +222,16 @@ __device__ __forceinline__ float wave_reduce(float x, Op op) {
 // Raw surrogate inputs (see md.h): v_body, world up in the body frame, n/HOVER,
 // 8 x (dp, dv) of the nearest neighbours (world frame, zero if missing), z,
 // ground proximity (h_clip / max(z, h_clip))^2, 0-pad.
-// Returns whether a neighbour sits above within (0, dz_ood) or (ood_rel > 0)
-// moves relative to the drone faster than ood_rel along an axis.
+// Returns whether a neighbour sits above within (0, dz_ood), inside the
+// cylinder |dz| < near_dz, dxy^2 < near_r2 (near_dz > 0), beyond |dz| >
+// far_dz (far_dz > 0), or (ood_rel > 0) moves relative to the drone faster
+// than ood_rel along an axis.  dz is the exact difference of the stored
+// heights and dxy^2 is formed as the neighbour ranking forms it, so the oracle
+// takes the same decisions.
 __device__ __forceinline__ bool features(const KConst &c, const Drone &d, const Rot &R, const float n[4],
                                          const float4 *pos, const float4 *vel, const int bj[KNN],
-                                         float dz_ood, float ood_rel, float f[MLP_IN]) {
+                                         float dz_ood, float ood_rel, float near_dz, float near_r2,
+                                         float far_dz, float f[MLP_IN]) {
     f[0] = R.r00 * d.vx + R.r10 * d.vy + R.r20 * d.vz;
     f[1] = R.r01 * d.vx + R.r11 * d.vy + R.r21 * d.vz;
     f[2] = R.r02 * d.vx + R.r12 * d.vy + R.r22 * d.vz;
@@ -249,6 +258,9 @@ __device__ __forceinline__ bool features(const KConst &c, const Drone &d, const 
         f[10 + 6 * t + 4] = h ? vj.y - d.vy : 0.f;
         f[10 + 6 * t + 5] = h ? vj.z - d.vz : 0.f;
         ood |= h && dz > 0.f && dz < dz_ood;
+        const float d2 = knn_d2(pj, d.px, d.py);
+        ood |= h && near_dz > 0.f && fabsf(dz) < near_dz && d2 < near_r2;
+        ood |= h && far_dz > 0.f && fabsf(dz) > far_dz;
         ood |= h && ood_rel > 0.f &&
                (fabsf(f[10 + 6 * t + 3]) > ood_rel || fabsf(f[10 + 6 * t + 4]) > ood_rel ||
                 fabsf(f[10 + 6 * t + 5]) > ood_rel);
@@ -458,18 +470,19 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 template <int ACT>
-__global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
+__global__ void __launch_bounds__(MAX_SLOTS) sur_step_kernel(SurArgs sa) {
     const StepArgs &a = sa.s;
-    const KConst &c = a.c;
+    const KConst &c0 = a.c;
     const int S = blockDim.x;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    // LDS (240 bytes per slot: eight one-wave workgroups fit a CU's 160 KB)
+    // LDS (248 bytes per slot: eight one-wave workgroups fit a CU's 160 KB,
+    // a 512-slot bin 124 KB)
     float4 *posb = (float4 *)smem;              // [2][2S] positions, double buffered
     float4 *vel = posb + 4 * S;                 // [S] velocities (read before the step's second barrier)
     bf16 *feat = (bf16 *)(vel + S);             // [S][FEAT_STRIDE] network inputs; a row's first
                                                 // 24 bytes then take its outputs (OUT_ROW floats apart)
-    uint4 *lst = (uint4 *)(feat + S * FEAT_STRIDE);   // [S] candidate lists, 16 slot offsets
-    float *wred = (float *)(lst + S);                 // [2][2][MAX_BIN_WAVES] per-wave max / min
+    uint2 *lst = (uint2 *)(feat + S * FEAT_STRIDE);   // [3][S] candidate lists, 12 16-bit slot offsets
+    float *wred = (float *)(lst + 3 * S);             // [2][2][MAX_BIN_WAVES] per-wave max / min
     const int slot = threadIdx.x, lane = threadIdx.x & 63, wbase = threadIdx.x & ~63;
     const int wave = threadIdx.x >> 6, n_waves = S >> 6;
     const int2 tab = a.bins.slot[blockIdx.x * S + slot];
@@ -478,7 +491,7 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
     const int lo = tab.y >> 16, menv = tab.y & 0xffff;
     const int mmax = a.bins.bin_mmax[blockIdx.x] & 0xffff;
     const int N = a.N;
-    const float *xm = sa.norm, *xs = sa.norm + MLP_IN, *ym = sa.norm + 2 * MLP_IN, *ysd = ym + MLP_OUT;
+    // device normalisation layout: x_inv_std[64], -x_mean * x_inv_std[64], y_mean[6], y_std[6]
 
     Drone d{};
     d.qw = 1.f;
@@ -499,9 +512,12 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
         for (int k = 0; k < ROWS; ++k) tgt_held[k] = a.action[(long long)k * N + di];
     if (ACT == 4 && valid)
         for (int k = 0; k < 4; ++k) sp[k] = a.s.ctl[k * N + di];
-    double jerr = 0.0, jref = 0.0, jterr = 0.0, jn = 0.0, jfb = 0.0, jnf = 0.0;
+    // per-lane judge sums (a lane judges at most one step in judge_stride)
+    // and counts, combined in double at the end
+    float jerr = 0.f, jref = 0.f, jterr = 0.f;
+    int jn = 0, jfb = 0, jnf = 0;
     int nfull = 0;  // drone-steps that ranked the whole environment
-    int phase = (ACT >= 1) ? (int)(a.step0 % (long long)c.decim) : 0;
+    int phase = (ACT >= 1) ? (int)(a.step0 % (long long)c0.decim) : 0;
     int oslot = 0;
     // Candidate lists (bins whose largest environment has at least
     // LIST_MIN_ENV drones).  At a rebuild every drone ranks its whole
@@ -521,6 +537,7 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
     float S2 = -1.f;     // the bin's smallest slack squared (< 0: rebuild)
     bool fresh = false;  // a rebuild in the previous step left its wave minima in wred
     for (int step = 0; step < a.n_steps; ++step) {
+        const KConst &c = c0;
         const int par = step & 1;
         float4 *pos = posb + par * 2 * S;
         pos[slot] = make_float4(d.px, d.py, d.pz, 0.f);
@@ -574,7 +591,8 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
             // in (distance, slot) order, found by a second pass
             const float r2 = bd[LIST - 1];
             const int rj = bl[LIST - 1];
-            uint32_t L[LIST / 4] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
+            const uint32_t own = (uint32_t)(slot - lo) * 0x00010001u;  // unused entries: self
+            uint32_t L[6] = {own, own, own, own, own, own};
             int cnt = 0;
             for (int jj = 0; jj < mmax; ++jj) {
                 const int j = lo + jj;
@@ -582,17 +600,17 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
                 const bool in = jj < menv && j != slot && d2 < __builtin_inff() &&
                                 (rj < 0 || d2 < r2 || (d2 == r2 && j <= rj));
                 if (in) {
-                    // byte cnt of the list (at most LIST candidates pass)
-                    const int w = cnt >> 2, sh = 8 * (cnt & 3);
-                    const uint32_t v = (uint32_t)jj << sh, keep = ~(0xffu << sh);
-                    L[0] = w == 0 ? ((L[0] & keep) | v) : L[0];
-                    L[1] = w == 1 ? ((L[1] & keep) | v) : L[1];
-                    L[2] = w == 2 ? ((L[2] & keep) | v) : L[2];
-                    L[3] = w == 3 ? ((L[3] & keep) | v) : L[3];
+                    // entry cnt of the list (at most LIST candidates pass)
+                    const int w = cnt >> 1, sh = 16 * (cnt & 1);
+                    const uint32_t v = (uint32_t)jj << sh, keep = ~(0xffffu << sh);
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) L[q] = w == q ? ((L[q] & keep) | v) : L[q];
                     ++cnt;
                 }
             }
-            lst[slot] = make_uint4(L[0], L[1], L[2], L[3]);
+            lst[slot] = make_uint2(L[0], L[1]);
+            lst[S + slot] = make_uint2(L[2], L[3]);
+            lst[2 * S + slot] = make_uint2(L[4], L[5]);
             // margin of this drone (+inf when the list holds its whole environment)
             float slack = __builtin_inff();
             if (valid && r2 < __builtin_inff())
@@ -605,9 +623,9 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
             bx = d.px;
             by = d.py;
         } else {
-            const uint4 lv = lst[slot];
-            const uint32_t L[LIST / 4] = {lv.x, lv.y, lv.z, lv.w};
-            knn_list(pos, lo, L, d.px, d.py, bj);
+            const uint2 l0 = lst[slot], l1 = lst[S + slot], l2 = lst[2 * S + slot];
+            const uint32_t L[6] = {l0.x, l0.y, l1.x, l1.y, l2.x, l2.y};
+            knn_list(pos, lo, slot, L, d.px, d.py, bj);
         }
         nfull += (valid && rebuild) ? 1 : 0;
         // ---- features -> standardised bfloat16 row
@@ -615,7 +633,7 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
         float f[MLP_IN];
         {
             const Rot R = rot_of(d);
-            ood = features(c, d, R, n, pos, vel, bj, sa.dz_ood, sa.ood_rel, f);
+            ood = features(c, d, R, n, pos, vel, bj, sa.dz_ood, sa.ood_rel, sa.near_dz, sa.near_r2, sa.far_dz, f);
         }
         // outside the trained region: fast or tilted drones take the plain terms
         ood |= sa.ood_speed > 0.f &&
@@ -623,11 +641,17 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
         ood |= sa.ood_tilt_s > 0.f && tilt_sq(d) > sa.ood_tilt_s;
         ood = ood && valid;
         bf16 *row = feat + slot * FEAT_STRIDE;
+        // the normalisation is read here each step rather than held in
+        // scalar registers for the launch (the empty asm keeps the loads in
+        // the loop), which leaves the scalar registers to the step's constants
+        const float *nrm = sa.norm;
+        asm volatile("" : "+s"(nrm));
 #pragma unroll
         for (int k = 0; k < MLP_IN; k += 8) {
             bf16x8 v;
 #pragma unroll
-            for (int t = 0; t < 8; ++t) v[t] = valid ? (bf16)((f[k + t] - xm[k + t]) * xs[k + t]) : (bf16)0.f;
+            for (int t = 0; t < 8; ++t)
+                v[t] = valid ? (bf16)fmaf(f[k + t], nrm[k + t], nrm[MLP_IN + k + t]) : (bf16)0.f;
             *(bf16x8 *)(row + k) = v;
         }
         __syncthreads();
@@ -643,7 +667,8 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
         const Rot R = rot_of(d);
         float y[MLP_OUT];
 #pragma unroll
-        for (int o = 0; o < MLP_OUT; ++o) y[o] = ((const float *)feat)[slot * OUT_ROW + o] * ysd[o] + ym[o];
+        for (int o = 0; o < MLP_OUT; ++o)
+            y[o] = ((const float *)feat)[slot * OUT_ROW + o] * nrm[2 * MLP_IN + MLP_OUT + o] + nrm[2 * MLP_IN + o];
         float Fx = R.r02 * T, Fy = R.r12 * T, Fz = R.r22 * T - c.mg;
         float ax, ay, az;
         // surrogate force, body -> world
@@ -664,7 +689,7 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
             ax = px_;
             ay = py_;
             az = pz_;
-            jfb += 1.0;
+            jfb += 1;
         } else {
             ax = sx;
             ay = sy;
@@ -680,11 +705,11 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
             // a non-finite sample (a state that has left every sensible range)
             // is counted apart so that it cannot poison the sums
             const bool fin = __builtin_isfinite(e2) && __builtin_isfinite(r2) && __builtin_isfinite(t2);
-            jerr += fin ? (double)e2 : 0.0;
-            jref += fin ? (double)r2 : 0.0;
-            jterr += fin ? (double)t2 : 0.0;
-            jn += fin ? 1.0 : 0.0;
-            jnf += fin ? 0.0 : 1.0;
+            jerr += fin ? e2 : 0.f;
+            jref += fin ? r2 : 0.f;
+            jterr += fin ? t2 : 0.f;
+            jn += fin ? 1 : 0;
+            jnf += fin ? 0 : 1;
         }
         Fx += ax;
         Fy += ay;
@@ -720,8 +745,8 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
             for (int k = 0; k < 4; ++k) a.s.ctl[k * N + di] = sp[k];
     }
     if (sa.judge != nullptr) {
-        const double s0 = wave_sum(jerr), s1 = wave_sum(jref), s2 = wave_sum(jterr), s3 = wave_sum(jn),
-                     s4 = wave_sum(jfb), s5 = wave_sum(jnf);
+        const double s0 = wave_sum((double)jerr), s1 = wave_sum((double)jref), s2 = wave_sum((double)jterr),
+                     s3 = wave_sum((double)jn), s4 = wave_sum((double)jfb), s5 = wave_sum((double)jnf);
         const double steps = wave_sum(valid ? (double)a.n_steps : 0.0);
         const double s6 = wave_sum((double)nfull);
         if (lane == 0) {
@@ -737,7 +762,7 @@ __global__ void __launch_bounds__(256) sur_step_kernel(SurArgs sa) {
     }
 }
 
-__global__ void __launch_bounds__(256) datagen_kernel(GenArgs g) {
+__global__ void __launch_bounds__(MAX_SLOTS) datagen_kernel(GenArgs g) {
     const KConst &c = g.c;
     const int S = blockDim.x;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -771,7 +796,7 @@ __global__ void __launch_bounds__(256) datagen_kernel(GenArgs g) {
         knn_sweep<KNN>(pos, lo, menv, mmax, slot, d.px, d.py, bd, bj);
     }
     float f[MLP_IN];
-    (void)features(c, d, R, n, pos, vel, bj, 0.f, 0.f, f);
+    (void)features(c, d, R, n, pos, vel, bj, 0.f, 0.f, 0.f, 0.f, 0.f, f);
     float *x = g.X + (long long)di * MLP_IN;
 #pragma unroll
     for (int k = 0; k < MLP_IN; k += 4) *(float4 *)(x + k) = make_float4(f[k], f[k + 1], f[k + 2], f[k + 3]);
@@ -794,20 +819,31 @@ __global__ void __launch_bounds__(256) datagen_kernel(GenArgs g) {
 }  // namespace
 
 size_t sur_lds_bytes(int S) {
-    return sizeof(float4) * 5 * (size_t)S + sizeof(bf16) * (size_t)S * FEAT_STRIDE + sizeof(uint4) * (size_t)S +
+    return sizeof(float4) * 5 * (size_t)S + sizeof(bf16) * (size_t)S * FEAT_STRIDE + sizeof(uint2) * 3 * (size_t)S +
            sizeof(float) * 4 * MAX_BIN_WAVES;
+}
+
+template <int ACT>
+hipError_t launch_sur_act(const SurArgs &sa, int n_bins, int S, size_t lds, hipStream_t st) {
+    if (lds > 65536) {
+        // bins of more than 256 slots take more than 64 KB of LDS
+        const hipError_t e = hipFuncSetAttribute((const void *)sur_step_kernel<ACT>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(sur_step_kernel<ACT>, dim3(n_bins), dim3(S), lds, st, sa);
+    return hipGetLastError();
 }
 
 hipError_t launch_sur_step(const SurArgs &sa, int act, int n_bins, int S, hipStream_t st) {
     const size_t lds = sur_lds_bytes(S);
     switch (act) {
-        case 0: hipLaunchKernelGGL(sur_step_kernel<0>, dim3(n_bins), dim3(S), lds, st, sa); break;
-        case 1: hipLaunchKernelGGL(sur_step_kernel<1>, dim3(n_bins), dim3(S), lds, st, sa); break;
-        case 2: hipLaunchKernelGGL(sur_step_kernel<2>, dim3(n_bins), dim3(S), lds, st, sa); break;
-        case 3: hipLaunchKernelGGL(sur_step_kernel<3>, dim3(n_bins), dim3(S), lds, st, sa); break;
-        default: hipLaunchKernelGGL(sur_step_kernel<4>, dim3(n_bins), dim3(S), lds, st, sa); break;
+        case 0: return launch_sur_act<0>(sa, n_bins, S, lds, st);
+        case 1: return launch_sur_act<1>(sa, n_bins, S, lds, st);
+        case 2: return launch_sur_act<2>(sa, n_bins, S, lds, st);
+        case 3: return launch_sur_act<3>(sa, n_bins, S, lds, st);
+        default: return launch_sur_act<4>(sa, n_bins, S, lds, st);
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_datagen(const GenArgs &g, int n_bins, int S, hipStream_t st) {
@@ -895,7 +931,14 @@ md_status load_surrogate(md_ctx *ctx, const float *params, const float *norm, fl
     SurrogateState *S = ctx->sur;
     hipError_t e = hipMemcpy(S->W, W.data(), sizeof(bf16) * WTOTAL, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(S->b, b.data(), sizeof(float) * BTOTAL, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(S->norm, norm, sizeof(float) * MLP_NORM, hipMemcpyHostToDevice);
+    // standardisation as one fused multiply-add per input: x' = x s + (-m s)
+    std::vector<float> dn(MLP_NORM);
+    for (int i = 0; i < MLP_IN; ++i) {
+        dn[i] = norm[MLP_IN + i];
+        dn[MLP_IN + i] = (float)(-(double)norm[i] * (double)norm[MLP_IN + i]);
+    }
+    for (int o = 0; o < 2 * MLP_OUT; ++o) dn[2 * MLP_IN + o] = norm[2 * MLP_IN + o];
+    if (e == hipSuccess) e = hipMemcpy(S->norm, dn.data(), sizeof(float) * MLP_NORM, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         ctx->err = hip_msg("md_load_surrogate", e);
         return MD_E_HIP;
@@ -903,6 +946,7 @@ md_status load_surrogate(md_ctx *ctx, const float *params, const float *norm, fl
     invalidate_graphs(ctx);
     S->dz_ood = dz_ood;
     S->ood_speed = S->ood_rel = S->ood_tilt_s = 0.f;
+    S->near_dz = S->near_r2 = S->far_dz = 0.f;
     S->judge_stride = judge_stride;
     S->loaded = true;
     return MD_OK;
@@ -914,8 +958,8 @@ md_status surrogate_step(md_ctx *ctx, const md_state *s, const float *d_action, 
         ctx->err = "md_step: surrogate weights not loaded (md_load_surrogate)";
         return MD_E_INVALID_ARG;
     }
-    if (ctx->max_m > 256) {
-        ctx->err = "md_step: the surrogate path supports environments of up to 256 drones";
+    if (ctx->max_m > MAX_SLOTS) {
+        ctx->err = "md_step: the surrogate path supports environments of up to 512 drones";
         return MD_E_UNSUPPORTED;
     }
     int waves = 1;
@@ -941,6 +985,9 @@ md_status surrogate_step(md_ctx *ctx, const md_state *s, const float *d_action, 
     sa.dz_ood = ctx->sur->dz_ood;
     sa.ood_speed = ctx->sur->ood_speed;
     sa.ood_rel = ctx->sur->ood_rel;
+    sa.near_dz = ctx->sur->near_dz;
+    sa.near_r2 = ctx->sur->near_r2;
+    sa.far_dz = ctx->sur->far_dz;
     sa.ood_tilt_s = ctx->sur->ood_tilt_s;
     sa.judge_mask = ctx->sur->judge_stride > 0 ? ctx->sur->judge_stride - 1 : -1;
     sa.knn_reuse = ctx->sur->knn_reuse ? 1 : 0;
@@ -954,8 +1001,8 @@ md_status surrogate_step(md_ctx *ctx, const md_state *s, const float *d_action, 
 
 md_status datagen(md_ctx *ctx, const md_state *s, uint32_t mask, float *d_X, float *d_Y, int32_t *d_nbr,
                   hipStream_t st) {
-    if (ctx->max_m > 256) {
-        ctx->err = "md_datagen: environments of up to 256 drones";
+    if (ctx->max_m > MAX_SLOTS) {
+        ctx->err = "md_datagen: environments of up to 512 drones";
         return MD_E_UNSUPPORTED;
     }
     int waves = 1;
@@ -1048,6 +1095,24 @@ md_status md_set_surrogate_ood(md_ctx *ctx, float max_speed, float max_rel_speed
     ctx->sur->ood_speed = max_speed;
     ctx->sur->ood_rel = max_rel_speed;
     ctx->sur->ood_tilt_s = max_tilt > 0.f ? (float)(sh * sh) : 0.f;
+    return MD_OK;
+}
+
+md_status md_set_surrogate_region(md_ctx *ctx, float near_dz, float near_r, float far_dz) {
+    if (!ctx) return MD_E_INVALID_ARG;
+    if (!ctx->sur || !ctx->sur->loaded) {
+        ctx->err = "md_set_surrogate_region: no surrogate loaded";
+        return MD_E_INVALID_ARG;
+    }
+    if (!(near_dz >= 0.f) || !(near_r >= 0.f) || !(far_dz >= 0.f)) {
+        ctx->err = "md_set_surrogate_region: bounds must be >= 0 (0 turns a check off)";
+        return MD_E_INVALID_ARG;
+    }
+    md::invalidate_graphs(ctx);
+    const bool on = near_dz > 0.f && near_r > 0.f;
+    ctx->sur->near_dz = on ? near_dz : 0.f;
+    ctx->sur->near_r2 = on ? (float)((double)near_r * (double)near_r) : 0.f;
+    ctx->sur->far_dz = far_dz;
     return MD_OK;
 }
 

@@ -406,6 +406,10 @@ def md_set_surrogate_ood(ctx, max_speed=0.0, max_rel_speed=0.0, max_tilt=0.0):
     check(lib().md_set_surrogate_ood(ctx, float(max_speed), float(max_rel_speed), float(max_tilt)), ctx)
 
 
+def md_set_surrogate_region(ctx, near_dz=0.0, near_r=0.0, far_dz=0.0):
+    check(lib().md_set_surrogate_region(ctx, float(near_dz), float(near_r), float(far_dz)), ctx)
+
+
 def md_set_surrogate_knn_reuse(ctx, reuse=True):
     check(lib().md_set_surrogate_knn_reuse(ctx, int(bool(reuse))), ctx)
 

@@ -28,6 +28,7 @@ def signatures():
         "md_judge_stats": (_I32, [_VP, _VP]),
         "md_judge_reset": (_I32, [_VP]),
         "md_set_surrogate_knn_reuse": (_I32, [_VP, ctypes.c_int]),
+        "md_set_surrogate_region": (_I32, [_VP, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
         "md_set_surrogate_ood": (_I32, [_VP, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
         "md_set_integrator": (_I32, [_VP, ctypes.c_int]),
         "md_set_domain_randomization": (_I32, [_VP, _VP]),

@@ -299,11 +299,45 @@ def test_out_of_distribution_fallback_matches_oracle():
     pu.assert_blocks(s1, ref, what="ood step")
 
 
-def _moving_formation(n_envs, shift):
-    """Formation environments whose waypoints lie `shift` metres off in x and
-    y, so that every drone flies off and the bins' candidate lists must be
-    rebuilt along the way."""
-    w = wl.subset_envs(wl.formation(n_envs=8192, seed=4), n_envs)
+def test_region_fallback_matches_oracle():
+    """Drones with a neighbour inside the cylinder (|dz| < 0.6 m, lateral
+    distance < 0.85 m) or more than 3 m away vertically take the plain terms
+    on both sides (binary32 decisions on the stored positions), and the step
+    matches the oracle."""
+    rng = np.random.default_rng(54)
+    flat, norm = _random_net(rng)
+    w = wl.subset_envs(wl.lattice(n_envs=16384, shape=(2, 2, 2), seed=3), 128)
+    st = {k: v.copy() for k, v in w["state"].items()}
+    off = w["env_offsets"]
+    for e in range(0, 128, 4):
+        i0 = off[e]
+        k = (e // 4) % 4
+        st["p"][:, i0 + 1] = st["p"][:, i0] + np.array([[0.5, 0.2, 0.0], [0.1, 0.1, 0.4], [0.0, 0.3, -0.55],
+                                                         [0.1, 0.0, -3.5]][k])
+    w = dict(w, state=st)
+    region = dict(near_dz=0.6, near_r=0.85, far_dz=3.0)
+    g = SurRun(w, flat, norm, dz_ood=0.0, judge_stride=1)
+    md.md_set_surrogate_region(g.ctx, **region)
+    s0 = g.snapshot()
+    md.md_judge_reset(g.ctx)
+    g.run(1)
+    s1 = g.snapshot()
+    j = md.md_judge_stats(g.ctx)
+    g.close()
+    ref, aero, fb, _ = _oracle_sur_step(w, s0, 0, flat, norm, dz_ood=0.0, ood=region)
+    assert fb.sum() >= 64
+    assert j["n_fallback"] == fb.sum()
+    pu.assert_blocks(s1, ref, what="region fallback step")
+
+
+def _moving_formation(n_envs, shift, shape=None):
+    """Formation environments (or lattices of `shape`) whose waypoints lie
+    `shift` metres off in x and y, so that every drone flies off and the bins'
+    candidate lists must be rebuilt along the way."""
+    if shape is None:
+        w = wl.subset_envs(wl.formation(n_envs=8192, seed=4), n_envs)
+    else:
+        w = wl.lattice(n_envs=n_envs, shape=shape, seed=5)
     w = dict(w)
     act = np.array(w["action"], copy=True)
     act[:, 0] += shift
@@ -312,14 +346,16 @@ def _moving_formation(n_envs, shift):
     return w
 
 
-@pytest.mark.parametrize("shift", [0.0, 1.5])
-def test_knn_candidate_lists_equal_full_ranking_bitwise(shift):
+@pytest.mark.parametrize("shift,shape", [(0.0, None), (1.5, None), (1.5, (16, 8, 2)), (1.5, (16, 16, 2))])
+def test_knn_candidate_lists_equal_full_ranking_bitwise(shift, shape):
     """The surrogate step with candidate lists against the same step ranking
     every same-environment drone every step: bitwise equal state after 300
-    steps; with the waypoints moved the lists are rebuilt on the way."""
+    steps; with the waypoints moved the lists are rebuilt on the way.  The
+    formation has one-wave bins; 256- and 512-drone environments fill four-
+    and eight-wave bins (more than 64 KB of LDS)."""
     rng = np.random.default_rng(53)
     flat, norm = _random_net(rng)
-    w = _moving_formation(96, shift)
+    w = _moving_formation(96 if shape is None else 4, shift, shape)
     out = {}
     for reuse in (True, False):
         g = SurRun(w, flat, norm, judge_stride=64)

@@ -47,9 +47,11 @@ def test_trained_network_on_held_out_samples():
 
 # Fallback bounds of the trained network's region (lattice flights: speeds
 # below 1 m/s, neighbour relative speeds below 1.2 m/s, tilts below half a
-# degree), with margin: world speed 1.5 m/s, relative speed 2 m/s, tilt 2
-# degrees; and the downwash singularity below 1 mm.
-DZ_OOD, OOD = 1e-3, (1.5, 2.0, float(np.radians(2.0)))
+# degree, column partners 0.8-1.45 m apart vertically, same-layer neighbours
+# at least 0.9 m apart laterally), with margin: world speed 1.5 m/s, relative
+# speed 2 m/s, tilt 2 degrees; a neighbour inside |dz| < 0.75 m, dxy < 0.85 m
+# or beyond |dz| > 3 m; and the downwash singularity below 10 um.
+DZ_OOD, OOD, REGION = 1e-5, (1.5, 2.0, float(np.radians(2.0))), (0.75, 0.85, 3.0)
 
 
 def _rollout(w, mask, flat=None, norm=None, steps=480, warm=60):
@@ -64,6 +66,7 @@ def _rollout(w, mask, flat=None, norm=None, steps=480, warm=60):
     if mask & md.MD_AERO_SURROGATE:
         md.md_load_surrogate(ctx, flat, norm, DZ_OOD, 16)
         md.md_set_surrogate_ood(ctx, *OOD)
+        md.md_set_surrogate_region(ctx, *REGION)
     st = md.DeviceState.from_numpy(w["state"])
     act = torch.from_numpy(w["action"]).cuda()
     md.md_step(ctx, st, act, False, None, 0, warm, 0)

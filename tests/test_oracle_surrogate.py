@@ -299,3 +299,52 @@ def test_out_of_distribution_fallback_checks():
                 np.testing.assert_allclose(aero[i], Y[i], rtol=1e-12, atol=1e-18)
             else:
                 np.testing.assert_array_equal(aero[i], 0.0)
+
+
+def test_region_fallback_checks():
+    """The region fallback sends exactly the drones with a neighbour (among
+    their 8 nearest) inside the cylinder |dz| < near_dz, dxy < near_r, above
+    or below, or beyond |dz| > far_dz, to the plain terms: checked against the
+    rule evaluated directly on the neighbour lists, on random environments
+    with pairs placed just inside and just outside each bound."""
+    P = orc.cf2x()
+    D = orc.derive(P)
+    rng = np.random.default_rng(71)
+    sizes = [6] * 40
+    off, p = _env_positions(rng, sizes)
+    p *= 2.0
+    n = int(off[-1])
+    near_dz, near_r, far_dz = 0.6, 0.85, 3.0
+    # for each environment: drone 1 relative to drone 0 just inside / outside
+    for e in range(40):
+        i0 = off[e]
+        kind = e % 5
+        dx = {0: 0.80, 1: 0.90, 2: 0.30, 3: 0.30, 4: 0.20}[kind]
+        dz = {0: 0.30, 1: 0.30, 2: 0.59, 3: -0.61, 4: -3.2}[kind]
+        p[:, i0 + 1] = p[:, i0] + np.array([dx, 0.0, dz])
+    p = p.astype(np.float32).astype(np.float64)
+    s = {"p": p, "q": np.tile([[1.0], [0.0], [0.0], [0.0]], (1, n)), "v": np.zeros((3, n)),
+         "w": np.zeros((3, n)), "rpm": np.full((4, n), D.hover_rpm), "pid_int": np.zeros((6, n))}
+    nbr = orc.knn(off, p, 8)
+    p32 = p.astype(np.float32)
+    expect = np.zeros(n, dtype=bool)
+    for i in range(n):
+        for j in nbr[i]:
+            if j < 0:
+                continue
+            dz = np.float32(p32[2, j] - p32[2, i])
+            ddx, ddy = np.float32(p32[0, j] - p32[0, i]), np.float32(p32[1, j] - p32[1, i])
+            d2 = np.float32(np.float32(ddx * ddx) + np.float32(ddy * ddy))
+            if (abs(dz) < np.float32(near_dz) and d2 < np.float32(near_r * near_r)) or abs(dz) > np.float32(far_dz):
+                expect[i] = True
+    assert 10 < expect.sum() < n - 10
+    act = np.full((1, 4, n), D.hover_rpm)
+    net, keep = orc.make_net(_flat_zero(), _norm_identity(), 0.0, near_dz=near_dz, near_r=near_r, far_dz=far_dz)
+    _, aero, fb = orc.step_surrogate(P, 1 / 240, orc.ACT_RPM, 1, off, {k: v.copy() for k, v in s.items()},
+                                     act, False, 1, net)
+    np.testing.assert_array_equal(fb.astype(bool), expect)
+    # each bound off: no region fallback
+    net0, keep0 = orc.make_net(_flat_zero(), _norm_identity(), 0.0)
+    _, _, fb0 = orc.step_surrogate(P, 1 / 240, orc.ACT_RPM, 1, off, {k: v.copy() for k, v in s.items()},
+                                   act, False, 1, net0)
+    assert fb0.sum() == 0
