@@ -380,8 +380,9 @@ def dr_leg(args, w, p, with_obs):
 def ragged_graph_leg(args, p, hover):
     """The latency-bound ragged layout (1024 environments of 2..32 drones on a
     coplanar grid, 17.4k drones, per-step rotor speeds, all aero terms): a
-    100-step rollout as 10 launches of 10 steps, replayed from one captured
-    hipGraph against the same launches issued eagerly."""
+    100-step rollout as one persistent launch of 100 steps (the value), and
+    as 10 launches of 10 steps replayed from one captured hipGraph and issued
+    eagerly."""
     import torch
     from paper_2606_08039_amd import md, workloads as wl
     w = wl.ragged_grid(hover, n_envs=1024, n_steps=100, seed=2)
@@ -405,6 +406,16 @@ def ragged_graph_leg(args, p, hover):
             torch.cuda.synchronize()
             if r >= 2:
                 t_eager.append(a.elapsed_time(b))
+        # one persistent launch of all 100 steps
+        t_one = []
+        for r in range(reps + 2):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            md.md_step(ctx, state, action, True, None, 0, 100, 0, stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            if r >= 2:
+                t_one.append(a.elapsed_time(b))
         graph = md.md_rollout_graph_create(ctx, state, action, True, None, 0, steps_per_launch=10,
                                            n_launches=10, step0=0, stream=stream)
         t_graph = []
@@ -421,9 +432,11 @@ def ragged_graph_leg(args, p, hover):
             md.md_graph_destroy(graph)
     finally:
         md.md_destroy(ctx)
-    mg, me = float(np.median(t_graph)), float(np.median(t_eager))
-    return {"value": float(n) * 100 / (mg * 1e-3), "unit": "drone-steps/s", "n_drones": n,
+    mg, me, m1 = float(np.median(t_graph)), float(np.median(t_eager)), float(np.median(t_one))
+    return {"value": float(n) * 100 / (m1 * 1e-3), "unit": "drone-steps/s", "n_drones": n,
+            "rollout_ms_single_launch_median": m1, "ns_per_step_single_launch": m1 * 1e6 / 100,
             "rollout_ms_graph_median": mg, "rollout_ms_eager_median": me, "replays": reps,
+            "value_graph": float(n) * 100 / (mg * 1e-3),
             "launch_config": cfg, "workload": "ragged_grid_1024envs_m2to32_rpm_gnd_drag_dw_100steps"}
 
 
@@ -473,8 +486,8 @@ def main():
                     help="launch configuration lanes_per_drone,unroll,waves_per_group,pair_symmetric "
                          "for the plain leg (instead of autotuning)")
     ap.add_argument("--weights", default=None, help="surrogate weights file")
-    ap.add_argument("--crossover", action="store_true",
-                    help="also run plain vs surrogate on uniform lattices of 8..512 drones per environment")
+    ap.add_argument("--no-crossover", action="store_true",
+                    help="skip plain vs surrogate on uniform lattices of 8..512 drones per environment")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -575,7 +588,7 @@ def main():
     if not args.no_wind:
         out["wind"] = wind_leg(args, w, p, with_obs)
         out["wind"]["speed_vs_plain"] = out["wind"]["value"] / value
-    if args.crossover:
+    if not args.no_crossover and not args.no_surrogate:
         out["crossover"] = crossover_leg(args, p)
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")

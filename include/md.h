@@ -216,7 +216,10 @@ md_status md_step(md_ctx *ctx, const md_state *s, const float *d_action, int act
  * The arrays are device memory owned by the caller and read by every later
  * md_step until the next call; NULL turns randomisation off.  Errors:
  * MD_E_INVALID_ARG for a null scale or a negative or non-finite noise level,
- * MD_E_UNSUPPORTED with MD_AERO_SURROGATE or MD_INTEG_RK4. */
+ * MD_E_UNSUPPORTED with MD_AERO_SURROGATE or MD_INTEG_RK4, or for a layout
+ * with an environment of more than 512 drones (workgroups of the randomised
+ * step hold at most 512 threads: waves_per_group <= 8; a launch
+ * configuration beyond that is reset to the default). */
 #define MD_DR_M 0
 #define MD_DR_J 1
 #define MD_DR_L 2

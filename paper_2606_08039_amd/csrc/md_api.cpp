@@ -293,7 +293,8 @@ int bin_mode_for(const md_ctx *ctx, const LaunchCfg &cfg) {
 
 LaunchCfg default_cfg(const md_ctx *ctx) {
     LaunchCfg c{1, 4, 1, 0};
-    while (64 * c.waves < ctx->max_m && c.waves < 16) c.waves *= 2;
+    const int max_waves = ctx->dr_on ? MAX_THREADS_DR / 64 : 16;
+    while (64 * c.waves < ctx->max_m && c.waves < max_waves) c.waves *= 2;
     return c;
 }
 
@@ -573,9 +574,18 @@ md_status md_set_domain_randomization(md_ctx *ctx, const md_dr *dr) {
     d.key1 = (uint32_t)(dr->seed >> 32);
     d.obs_delay = dr->obs_delay;
     d.obs_bias = dr->obs_bias;
+    if (ctx->has_layout && ctx->max_m > md::MAX_THREADS_DR) {
+        ctx->err = "md_set_domain_randomization: supported for environments of up to 512 drones";
+        return MD_E_UNSUPPORTED;
+    }
     ctx->dr = d;
     ctx->dr_on = true;
     md::invalidate_graphs(ctx);
+    if (ctx->has_layout && !md::cfg_valid(ctx, ctx->cfg)) {
+        // workgroups of the randomised step hold at most MAX_THREADS_DR threads
+        ctx->cfg = md::default_cfg(ctx);
+        ctx->tuned = false;
+    }
     return MD_OK;
 }
 
@@ -648,6 +658,10 @@ md_status md_step(md_ctx *ctx, const md_state *s, const float *d_action, int act
     if ((ctx->wind.models & (MD_WIND_GUST | MD_WIND_DRYDEN)) && !s->wind) {
         ctx->err = "md_step: wind gusts and turbulence need the wind state block";
         return MD_E_INVALID_ARG;
+    }
+    if (ctx->dr_on && ctx->max_m > md::MAX_THREADS_DR) {
+        ctx->err = "md_step: domain randomisation is supported for environments of up to 512 drones";
+        return MD_E_UNSUPPORTED;
     }
     if (ctx->mask & MD_AERO_SURROGATE) return md::surrogate_step(ctx, s, d_action, action_per_step, d_obs,
                                                                  n_obs_slots, n_steps, step0,

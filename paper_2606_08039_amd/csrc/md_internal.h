@@ -101,6 +101,9 @@ struct StepArgs {
 // writes spreads a wave over the LDS banks.
 __host__ __device__ constexpr int pair_stride(int max_m) { return ((max_m + 3) / 4) * 4 > 0 ? ((max_m + 3) / 4) * 4 : 4; }
 
+// Largest workgroup of the step kernel with domain randomisation (threads).
+constexpr int MAX_THREADS_DR = 512;
+
 // Launch configuration chosen per (shape, mask) by the autotuner.
 struct LaunchCfg {
     int lpd;     // lanes per drone in the neighbour sweep: 1, 2 or 4

@@ -90,21 +90,18 @@ __device__ __forceinline__ uint4 philox4x32(uint4 c, uint32_t k0, uint32_t k1) {
 __device__ __forceinline__ float unit24(uint32_t x) { return (float)(x >> 8) * (1.f / 16777216.f); }
 
 // World-frame wind force of one drone at global step t (pre-step state d);
-// ws = the drone's wind state (Dryden x, y, z; gust step, -1 idle; gust
-// heading), updated in place.  Models as documented at md_set_wind.
-__device__ __forceinline__ void wind_force(const WindArgs &W, float dt, long long t, int di, int N, const Drone &d,
-                                           float ws[5], float &Fx, float &Fy, float &Fz) {
+// vm = its mean wind; ws = the drone's wind state (Dryden x, y, z; gust step,
+// -1 idle; gust heading), updated in place.  Models as documented at
+// md_set_wind.
+__device__ __forceinline__ void wind_force(const WindArgs &W, float dt, long long t, int di, const float vm[3],
+                                           const Drone &d, float ws[5], float &Fx, float &Fy, float &Fz) {
     Fx = Fy = Fz = 0.f;
     const uint32_t tl = (uint32_t)((unsigned long long)t & 0xffffffffull);
     const uint32_t th = (uint32_t)((unsigned long long)t >> 32);
     if (W.models & MD_WIND_CONSTANT) {
-        float vx = W.vm[0], vy = W.vm[1], vz = W.vm[2];
-        if (W.vm_drone != nullptr) {
-            vx = W.vm_drone[di];
-            vy = W.vm_drone[N + di];
-            vz = W.vm_drone[2 * N + di];
-        }
-        const float ux = vx - d.vx, uy = vy - d.vy, uz = vz - d.vz;
+        // vm: the drone's mean wind (per-drone array or the common one),
+        // read once per launch
+        const float ux = vm[0] - d.vx, uy = vm[1] - d.vy, uz = vm[2] - d.vz;
         const float kn = W.kd * fsqrt(ux * ux + uy * uy + uz * uz);
         Fx += kn * ux;
         Fy += kn * uy;
@@ -227,8 +224,12 @@ struct RowSeg {
     }
 };
 
+// Workgroups of up to 1024 threads, 512 with domain randomisation: its
+// per-drone constants, actuator chain and sensor side need more than the 128
+// registers per lane that sixteen waves per workgroup leave (they spilled to
+// scratch memory, which the long launches then streamed through HBM).
 template <uint32_t MASK, int ACT, int LPD, int UNROLL, int SYM, int DIST>
-__global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
+__global__ void __launch_bounds__(DIST == 2 ? MAX_THREADS_DR : 1024) step_kernel(StepArgs a) {
     extern __shared__ float4 lds_pos[];  // [2][2 * slots] positions; then T [slots][tstride] (SYM)
     const KConst &c = a.c;
     const int slots = blockDim.x / LPD;
@@ -286,6 +287,10 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
     const bool windy = DIST >= 1 && a.wind.models != 0u;
     if (windy && valid && a.s.wind != nullptr)
         for (int k = 0; k < 5; ++k) ws[k] = a.s.wind[k * N + di];
+    // the drone's mean wind, held for the launch
+    float vmean[3] = {a.wind.vm[0], a.wind.vm[1], a.wind.vm[2]};
+    if (windy && valid && a.wind.vm_drone != nullptr)
+        for (int k = 0; k < 3; ++k) vmean[k] = a.wind.vm_drone[k * N + di];
     if (rnd && valid) {
         dr_constants(c, a.dr, N, di, cl, bias);
         const float tau = a.dr.tau_mot ? a.dr.tau_mot[di] : 0.f;
@@ -314,6 +319,13 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         ocnt0 = min(max(a.s.obs_count[di], 0), MD_DR_OBS_HIST);
     }
     int osl = oring ? (int)(a.step0 % (long long)MD_DR_OBS_HIST) : 0;
+    // the sticky observation bias (position, velocity, angles, rates), held
+    // for the launch
+    float obias[12];
+    for (int b = 0; b < 12; ++b) obias[b] = 0.f;
+    const bool biased = rnd && a.dr.obs_bias != nullptr;
+    if (biased && valid)
+        for (int b = 0; b < 12; ++b) obias[b] = a.dr.obs_bias[(long long)b * N + di];
 
     float *tmat = (float *)(lds_pos + 4 * slots);
     if (SYM == 1 && (MASK & 4u) && valid) {
@@ -333,6 +345,13 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         for (int k = 0; k < ROWS; ++k) tgt_held[k] = a.action[(long long)k * N + di];
     if (ACT == 4 && valid)
         for (int k = 0; k < 4; ++k) sp[k] = a.s.ctl[k * N + di];
+    // Per-step rotor-speed actions are read one step ahead: the row of step
+    // k + 1 is requested during step k, so its memory latency overlaps the
+    // step instead of opening the next one (short launches of small layouts
+    // are latency-bound).
+    float nact[4] = {0.f, 0.f, 0.f, 0.f};
+    if (ACT == 0 && !rnd && valid && a.n_steps > 0)
+        for (int k = 0; k < 4; ++k) nact[k] = a.action[(long long)k * N + di];
     // controller phase, observation slot and ring slot advance as counters
     int phase = (ACT >= 1) ? (int)(a.step0 % (long long)c.decim) : 0;
     int oslot = 0;
@@ -365,7 +384,11 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         if (!rnd) {
             if (ACT == 0) {
                 if (valid) {
-                    for (int k = 0; k < 4; ++k) n[k] = clampf(act[(long long)k * N + di], 0.f, c.max_rpm);
+                    for (int k = 0; k < 4; ++k) n[k] = clampf(nact[k], 0.f, c.max_rpm);
+                    if (a.act_step_stride != 0 && step + 1 < a.n_steps) {
+                        const float *nx = act + a.act_step_stride;
+                        for (int k = 0; k < 4; ++k) nact[k] = nx[(long long)k * N + di];
+                    }
                 }
             } else {
                 if (phase == 0 && valid) {
@@ -447,7 +470,7 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
         // ---- wind
         if (windy && valid) {
             float wx, wy, wz;
-            wind_force(a.wind, c.dt, a.step0 + step, di, N, d, ws, wx, wy, wz);
+            wind_force(a.wind, c.dt, a.step0 + step, di, vmean, d, ws, wx, wy, wz);
             Fx += wx;
             Fy += wy;
             Fz += wz;
@@ -465,10 +488,9 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs a) {
             euler_zyx(d, roll, pitch, yaw);
             float orow[20] = {d.px, d.py, d.pz, d.qw, d.qx, d.qy, d.qz, roll, pitch, yaw,
                               d.vx, d.vy, d.vz, d.wx, d.wy, d.wz, n[0], n[1], n[2], n[3]};
-            if (rnd && a.dr.obs_bias != nullptr) {
-                const float *ob = a.dr.obs_bias + di;
+            if (biased) {
 #pragma unroll
-                for (int b = 0; b < 12; ++b) orow[b < 3 ? b : (b < 6 ? b + 7 : (b < 9 ? b + 1 : b + 4))] += ob[(long long)b * N];
+                for (int b = 0; b < 12; ++b) orow[b < 3 ? b : (b < 6 ? b + 7 : (b < 9 ? b + 1 : b + 4))] += obias[b];
             }
             if (noisy) sensor_noise(a.dr, di, a.step0 + step, orow);
             if (!oring) {

@@ -62,6 +62,7 @@ bool cfg_valid(const md_ctx *ctx, const LaunchCfg &c) {
         if (lds > 64 * 1024) return false;
     }
     if (64 * c.waves > 1024) return false;
+    if (ctx->dr_on && 64 * c.waves > MAX_THREADS_DR) return false;
     return true;
 }
 
