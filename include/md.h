@@ -520,6 +520,10 @@ typedef struct md_judge {
     double n_knn_full;
 } md_judge;
 md_status md_judge_stats(md_ctx *ctx, md_judge *out);
+/* Zero the judge statistics (synchronous; a no-op without a loaded
+ * surrogate).  MD_E_INVALID_ARG for a null context, MD_E_HIP if the device
+ * reports an error. */
+md_status md_judge_reset(md_ctx *ctx);
 
 /* Region fallback of the loaded surrogate (each bound 0 = that check off;
  * loading a network turns both off): a drone with a neighbour among its 8
@@ -545,7 +549,6 @@ md_status md_set_surrogate_region(md_ctx *ctx, float near_dz, float near_r, floa
  * those of reuse 0, which ranks every drone every step.  MD_E_INVALID_ARG
  * without a loaded surrogate. */
 md_status md_set_surrogate_knn_reuse(md_ctx *ctx, int reuse);
-md_status md_judge_reset(md_ctx *ctx);
 
 #ifdef __cplusplus
 }
