@@ -89,13 +89,21 @@ __device__ __forceinline__ void euler_zyx(const Drone &d, float &roll, float &pi
 // scalar registers): each row is one buffer store with the lane's byte
 // offset and the row offset k N 4 as the scalar offset, no per-row address
 // arithmetic on the vector ALU (n_drones <= 2^25 keeps 80 N within 32 bits).
+// The row offsets are formed by scalar adds beside the stores (the stride is
+// made opaque per call): hoisted out of a step loop, twenty of them overflow
+// the scalar registers and the spilled ones return through the vector ALU.
 __device__ __forceinline__ void store_obs(float *obs, int oslot, int N, int di, const float row[20]) {
     float *base = obs + (long long)oslot * 20 * N;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)0xffffffffu, 0x00020000);
     const int voff = di * 4;
+    uint32_t rb = (uint32_t)N * 4u;
+    asm volatile("" : "+s"(rb));
+    uint32_t so = 0;
 #pragma unroll
-    for (int k = 0; k < 20; ++k)
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(row[k]), rs, voff, (int)((uint32_t)k * (uint32_t)N * 4u), 0);
+    for (int k = 0; k < 20; ++k) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(row[k]), rs, voff, (int)so, 0);
+        so += rb;
+    }
 }
 
 __device__ __forceinline__ float clampf(float x, float lo, float hi) {

@@ -210,17 +210,26 @@ struct RowSeg {
     __amdgpu_buffer_rsrc_t rs;
     int voff, rowbytes;
     float v[20];
-    __device__ __forceinline__ void all() const {
+    // rows [r0, r1) with their scalar offsets r * rowbytes formed by scalar
+    // adds beside the stores: rowbytes is made opaque per call, so the
+    // offsets are not hoisted out of the step loop (twenty of them held for
+    // the whole launch overflowed the scalar registers, and the spilled ones
+    // came back through the vector ALU every step)
+    __device__ __forceinline__ void rows(int r0, int r1) const {
+        int rb = rowbytes;
+        asm volatile("" : "+s"(rb));
+        int so = r0 * rb;
 #pragma unroll
-        for (int r = 0; r < 20; ++r)
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[r]), rs, voff, r * rowbytes, 0);
+        for (int r = r0; r < r1; ++r) {
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[r]), rs, voff, so, 0);
+            so += rb;
+        }
     }
+    __device__ __forceinline__ void all() const { rows(0, 20); }
     template <int H>
     __device__ __forceinline__ void at(int s) const {
         const int r0 = s * 20 / (H + 1), r1 = (s + 1) * 20 / (H + 1);
-#pragma unroll
-        for (int r = r0; r < r1; ++r)
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[r]), rs, voff, r * rowbytes, 0);
+        if (r1 > r0) rows(r0, r1);
     }
 };
 
