@@ -26,20 +26,42 @@ struct Rot {
     float r00, r01, r02, r10, r11, r12, r20, r21, r22;
 };
 
+// The five entries the Z-Y-X angles read.  Their fused multiply-adds are
+// written out and no other contraction is allowed, so each entry rounds the
+// same way wherever it is inlined: the angles formed for the observation and
+// the controller agree bit for bit between the kernels' code paths.
+struct RotZYX {
+    float r00, r10, r20, r21, r22;
+};
+
+__device__ __forceinline__ RotZYX rot_zyx(const Drone &d) {
+#pragma clang fp contract(off)
+    const float w = d.qw, x = d.qx, y = d.qy, z = d.qz;
+    RotZYX e;
+    e.r00 = fmaf(-2.f, fmaf(y, y, z * z), 1.f);
+    e.r10 = 2.f * fmaf(x, y, w * z);
+    e.r20 = 2.f * fmaf(x, z, -(w * y));
+    e.r21 = 2.f * fmaf(y, z, w * x);
+    e.r22 = fmaf(-2.f, fmaf(x, x, y * y), 1.f);
+    return e;
+}
+
 __device__ __forceinline__ Rot rot_of(const Drone &d) {
     const float w = d.qw, x = d.qx, y = d.qy, z = d.qz;
+    const RotZYX e = rot_zyx(d);
     Rot R;
-    R.r00 = 1.f - 2.f * (y * y + z * z);
+    R.r00 = e.r00;
     R.r01 = 2.f * (x * y - w * z);
     R.r02 = 2.f * (x * z + w * y);
-    R.r10 = 2.f * (x * y + w * z);
+    R.r10 = e.r10;
     R.r11 = 1.f - 2.f * (x * x + z * z);
     R.r12 = 2.f * (y * z - w * x);
-    R.r20 = 2.f * (x * z - w * y);
-    R.r21 = 2.f * (y * z + w * x);
-    R.r22 = 1.f - 2.f * (x * x + y * y);
+    R.r20 = e.r20;
+    R.r21 = e.r21;
+    R.r22 = e.r22;
     return R;
 }
+
 
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
@@ -74,14 +96,17 @@ __device__ __forceinline__ float atan2_poly(float y, float x) {
 // asin(s) = atan2(s, sqrt((1 - s)(1 + s))), |s| <= 1
 __device__ __forceinline__ float asin_poly(float s) { return atan2_poly(s, fsqrt((1.f - s) * (1.f + s))); }
 
-// Roll, pitch, yaw (Z-Y-X) of the KIN observation.
-__device__ __forceinline__ void euler_zyx(const Drone &d, float &roll, float &pitch, float &yaw) {
-    const float w = d.qw, x = d.qx, y = d.qy, z = d.qz;
-    float sp = 2.f * (w * y - z * x);
-    sp = fminf(fmaxf(sp, -1.f), 1.f);
-    roll = atan2_poly(2.f * (w * x + y * z), 1.f - 2.f * (x * x + y * y));
+// Roll, pitch, yaw (Z-Y-X) of the KIN observation from the rotation entries:
+// roll = atan2(R21, R22), pitch = asin(-R20), yaw = atan2(R10, R00).
+__device__ __forceinline__ void euler_of(const RotZYX &e, float &roll, float &pitch, float &yaw) {
+    const float sp = fminf(fmaxf(-e.r20, -1.f), 1.f);
+    roll = atan2_poly(e.r21, e.r22);
     pitch = asin_poly(sp);
-    yaw = atan2_poly(2.f * (w * z + x * y), 1.f - 2.f * (y * y + z * z));
+    yaw = atan2_poly(e.r10, e.r00);
+}
+
+__device__ __forceinline__ void euler_zyx(const Drone &d, float &roll, float &pitch, float &yaw) {
+    euler_of(rot_zyx(d), roll, pitch, yaw);
 }
 
 // One drone's KIN-20 row into ring slot `oslot` ([slot][20][N]) through a
@@ -116,14 +141,8 @@ __device__ __forceinline__ float wrap_pi(float a) {
 
 // Roll, pitch, yaw and the yaw's sine and cosine (straight from the atan2
 // arguments, no further transcendental).
-__device__ __forceinline__ void attitude_angles(const Drone &d, float &roll, float &pitch, float &yaw,
-                                                float &sps, float &cps) {
-    const float w = d.qw, x = d.qx, y = d.qy, z = d.qz;
-    const float sp = clampf(2.f * (w * y - z * x), -1.f, 1.f);
-    roll = atan2_poly(2.f * (w * x + y * z), 1.f - 2.f * (x * x + y * y));
-    pitch = asin_poly(sp);
-    const float ys = 2.f * (w * z + x * y), yc = 1.f - 2.f * (y * y + z * z);
-    yaw = atan2_poly(ys, yc);
+__device__ __forceinline__ void yaw_sincos(const RotZYX &e, float &sps, float &cps) {
+    const float ys = e.r10, yc = e.r00;
     const float h2 = ys * ys + yc * yc;
     const float hinv = h2 > 0.f ? rsqrtf(h2) : 0.f;
     sps = h2 > 0.f ? ys * hinv : 0.f;
@@ -170,11 +189,14 @@ __device__ __forceinline__ void thrust_direction(const KConst &c, float ax, floa
 //   ACT 3 ATTITUDE: collective thrust, roll, pitch, yaw rate;
 //   ACT 4 DSL-style PID: rate-limited setpoint sp (x, y, z, yaw) toward the
 //         waypoint, own gains and clamps, feed-forward acceleration cmd[4..6].
+// control_rpy takes the angles already formed from the same rotation
+// entries (euler_of(e)); control forms them itself.
 template <int ACT>
-__device__ __forceinline__ void control(const KConst &c, const Drone &d, const float *cmd, float I[6],
-                                        float sp[4], float n[4]) {
-    float roll, pitch, yaw, sps, cps;
-    attitude_angles(d, roll, pitch, yaw, sps, cps);
+__device__ __forceinline__ void control_rpy(const KConst &c, const Drone &d, const RotZYX &e, float roll,
+                                            float pitch, float yaw, const float *cmd, float I[6], float sp[4],
+                                            float n[4]) {
+    float sps, cps;
+    yaw_sincos(e, sps, cps);
     if (ACT == 1) {
         const float ex = cmd[0] - d.px, ey = cmd[1] - d.py, ez = cmd[2] - d.pz;
         I[0] = clampf(I[0] + ex * c.dt_c, -c.p_clamp, c.p_clamp);
@@ -218,6 +240,15 @@ __device__ __forceinline__ void control(const KConst &c, const Drone &d, const f
         attitude_allocate(c, d, roll, pitch, T, rt, pt, wrap_pi(sp[3] - yaw), 0.f, c.dsl_akp, c.dsl_aki,
                           c.dsl_akd, c.dsl_a_clamp, I + 3, n);
     }
+}
+
+template <int ACT>
+__device__ __forceinline__ void control(const KConst &c, const Drone &d, const float *cmd, float I[6],
+                                        float sp[4], float n[4]) {
+    const RotZYX e = rot_zyx(d);
+    float roll, pitch, yaw;
+    euler_of(e, roll, pitch, yaw);
+    control_rpy<ACT>(c, d, e, roll, pitch, yaw, cmd, I, sp, n);
 }
 
 // Motor model and X mixer (Eq. 1-3).  Contraction into fused multiply-adds is

@@ -367,13 +367,15 @@ __global__ void __launch_bounds__(DIST == 2 ? MAX_THREADS_DR : 1024) step_kernel
     int hslot = (int)(a.step0 % (long long)MD_DR_HIST);
     // Nominal step with the rotation sweep: each observation row is stored
     // during the next step between the sweep's segments (RowSeg); the state
-    // is still that row until the integration, its angles (computed where the
-    // row is complete) and rotor speeds are kept in rpy and nprev, and the
-    // launch's last row is stored after the loop.
+    // is still that row until the integration, its angles are formed at the
+    // start of the next step (from the rotation entries that step's
+    // controller also reads; the same expressions as euler_zyx), its rotor
+    // speeds are kept in nprev, and the launch's last row is stored after
+    // the loop.
     constexpr bool seg_obs = DIST == 0 && SYM == 3 && (MASK & 4u) && LPD == 1;
     const bool seg_on = seg_obs && a.obs != nullptr && N <= (1 << 24);  // uniform
     float nprev[4] = {0.f, 0.f, 0.f, 0.f};
-    float rpy[3] = {0.f, 0.f, 0.f};  // the previous row's angles, computed right after its integration
+    float rpy[3] = {0.f, 0.f, 0.f};  // the previous row's angles
     int pslot = 0;
     for (int step = 0; step < a.n_steps; ++step) {
         float4 *buf = lds_pos + (step & 1) * (2 * slots);
@@ -387,6 +389,15 @@ __global__ void __launch_bounds__(DIST == 2 ? MAX_THREADS_DR : 1024) step_kernel
                 buf[slot] = make_float4(d.px, d.py, d.pz, 0.f);
             }
             __syncthreads();
+        }
+        // the rotation sweep's instantiation forms the attitude angles once:
+        // for the previous row's observation and for this step's controller
+        RotZYX ez{};
+        float att[3] = {0.f, 0.f, 0.f};
+        if constexpr (seg_obs) {
+            ez = rot_zyx(d);
+            if ((seg_on && step > 0) || (ACT >= 1 && phase == 0)) euler_of(ez, att[0], att[1], att[2]);
+            for (int k = 0; k < 3; ++k) rpy[k] = att[k];
         }
         // ---- rotor speeds
         const float *act = a.action + a.act_step_stride * step;
@@ -403,7 +414,10 @@ __global__ void __launch_bounds__(DIST == 2 ? MAX_THREADS_DR : 1024) step_kernel
                 if (phase == 0 && valid) {
                     float cmd[ROWS];
                     for (int k = 0; k < ROWS; ++k) cmd[k] = held ? tgt_held[k] : act[(long long)k * N + di];
-                    control<ACT>(c, d, cmd, I, sp, n);
+                    if constexpr (seg_obs)
+                        control_rpy<ACT>(c, d, ez, att[0], att[1], att[2], cmd, I, sp, n);
+                    else
+                        control<ACT>(c, d, cmd, I, sp, n);
                 }
                 phase = (phase + 1 == c.decim) ? 0 : phase + 1;
             }
@@ -489,7 +503,6 @@ __global__ void __launch_bounds__(DIST == 2 ? MAX_THREADS_DR : 1024) step_kernel
         // ---- KIN observation
         const bool otail = oring && step >= a.n_steps - MD_DR_OBS_HIST;
         if (seg_on) {
-            euler_zyx(d, rpy[0], rpy[1], rpy[2]);
             for (int k = 0; k < 4; ++k) nprev[k] = n[k];
             pslot = oslot;
         } else if ((a.obs != nullptr || otail) && writer) {
@@ -537,6 +550,7 @@ __global__ void __launch_bounds__(DIST == 2 ? MAX_THREADS_DR : 1024) step_kernel
         if (oring) osl = (osl + 1 == MD_DR_OBS_HIST) ? 0 : osl + 1;
     }
     if (seg_on && writer && a.n_steps > 0) {
+        euler_zyx(d, rpy[0], rpy[1], rpy[2]);
         const float orow[20] = {d.px, d.py, d.pz, d.qw, d.qx, d.qy, d.qz, rpy[0], rpy[1], rpy[2],
                                 d.vx, d.vy, d.vz, d.wx, d.wy, d.wz, n[0], n[1], n[2], n[3]};
         store_obs(a.obs, pslot, N, di, orow);
