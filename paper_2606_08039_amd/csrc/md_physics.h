@@ -345,16 +345,18 @@ __device__ __forceinline__ float ground_effect(const KConst &c, const Drone &d, 
 }
 
 // Blade drag (Eq. 5) in the world frame: R (-diag(c_xy, c_xy, c_z) S R^T v).
+// With e3 = (R02, R12, R22) the body z axis and R R^T = I,
+// R diag(c_xy, c_xy, c_z) R^T = c_xy I + (c_z - c_xy) e3 e3^T, so the force is
+// -S (c_xy v + (c_z - c_xy) (e3 . v) e3): the same vector, formed without
+// rotating v into the body frame and back.
 __device__ __forceinline__ void drag(const KConst &c, const Drone &d, const Rot &R, const float n[4],
                                      float &Fx, float &Fy, float &Fz) {
     const float S = c.drag_s * (n[0] + n[1] + n[2] + n[3]);
-    const float bx = R.r00 * d.vx + R.r10 * d.vy + R.r20 * d.vz;
-    const float by = R.r01 * d.vx + R.r11 * d.vy + R.r21 * d.vz;
-    const float bz = R.r02 * d.vx + R.r12 * d.vy + R.r22 * d.vz;
-    const float fx = -c.c_xy * S * bx, fy = -c.c_xy * S * by, fz = -c.c_z * S * bz;
-    Fx = R.r00 * fx + R.r01 * fy + R.r02 * fz;
-    Fy = R.r10 * fx + R.r11 * fy + R.r12 * fz;
-    Fz = R.r20 * fx + R.r21 * fy + R.r22 * fz;
+    const float vb = R.r02 * d.vx + R.r12 * d.vy + R.r22 * d.vz;
+    const float a = -S * c.c_xy, b = -S * ((c.c_z - c.c_xy) * vb);
+    Fx = a * d.vx + b * R.r02;
+    Fy = a * d.vy + b * R.r12;
+    Fz = a * d.vz + b * R.r22;
 }
 
 }  // namespace phys
