@@ -571,8 +571,7 @@ def main():
         k0 = float(np.mean(kms0)) * 1e-3
         out["plain_no_obs"] = {"value": ds / wall0, "unit": "drone-steps/s", "kernel_ms_avg": k0 * 1e3,
                                "alu_tflops": round(flop0 / k0 / 1e12, 3),
-                               "frac_fp32_peak": round(flop0 / k0 / 1e12 / FP32_PEAK_TFLOPS, 4),
-                               "frac_fp32_non_packed_peak": round(flop0 / k0 / 1e12 / (FP32_PEAK_TFLOPS / 2), 4)}
+                               "frac_fp32_peak": round(flop0 / k0 / 1e12 / FP32_PEAK_TFLOPS, 4)}
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(args, w, p, with_obs)
         if out["surrogate"].get("value"):
