@@ -340,8 +340,6 @@ __device__ __forceinline__ float tilt_sq(const Drone &d) {
     return a + b;
 }
 
-__device__ __forceinline__ float silu(float z) { return z * __builtin_amdgcn_rcpf(1.f + __expf(-z)); }
-
 // Weight fragments are read through a global (address space 1) pointer, so
 // that their loads count on the vector-memory counter alone and the wait for
 // one fragment does not also wait for the LDS traffic in flight.
@@ -406,13 +404,24 @@ __device__ __forceinline__ void mlp_wave(const bf16 *feat, float *out, const bf1
                 x[kc][dt] = *(const bf16x8 *)(feat + (16 * (t0 + dt) + r) * FEAT_STRIDE + 32 * kc + 8 * g);
         bf16x4 h1[8][DT], h2[8][DT];
         // SiLU epilogue of a hidden-layer job: layers 1 and 3 write h1, layer 2 h2
+        // four SiLUs at a time, each stage fenced, so that the four chains
+        // interleave (the exponential and the reciprocal of one SiLU hide the
+        // others' latency instead of a no-op per transcendental)
         auto epilogue = [&](int jj, const f32x4 (&ac)[DT]) {
             const int layer = jj / 8, ot = jj % 8;
             bf16x4(&hout)[8][DT] = layer == 1 ? h2 : h1;
 #pragma unroll
-            for (int dt = 0; dt < DT; ++dt)
+            for (int dt = 0; dt < DT; ++dt) {
+                float e[4];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) hout[ot][dt][t] = (bf16)silu(ac[dt][t]);
+                for (int t = 0; t < 4; ++t) e[t] = __expf(-ac[dt][t]);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) e[t] = __builtin_amdgcn_rcpf(1.f + e[t]);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) hout[ot][dt][t] = (bf16)(ac[dt][t] * e[t]);
+            }
         };
         f32x4 prev[DT];
 #pragma unroll
@@ -929,6 +938,8 @@ md_status load_surrogate(md_ctx *ctx, const float *params, const float *norm, fl
     }
     for (int o = 0; o < MLP_OUT; ++o) b[BOFF4 + o] = params[kParamOff[7] + o];
     SurrogateState *S = ctx->sur;
+    // captured rollouts go stale before any buffer changes (also when a copy fails)
+    invalidate_graphs(ctx);
     hipError_t e = hipMemcpy(S->W, W.data(), sizeof(bf16) * WTOTAL, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(S->b, b.data(), sizeof(float) * BTOTAL, hipMemcpyHostToDevice);
     // standardisation as one fused multiply-add per input: x' = x s + (-m s)
@@ -943,7 +954,6 @@ md_status load_surrogate(md_ctx *ctx, const float *params, const float *norm, fl
         ctx->err = hip_msg("md_load_surrogate", e);
         return MD_E_HIP;
     }
-    invalidate_graphs(ctx);
     S->dz_ood = dz_ood;
     S->ood_speed = S->ood_rel = S->ood_tilt_s = 0.f;
     S->near_dz = S->near_r2 = S->far_dz = 0.f;
