@@ -89,6 +89,28 @@ __device__ __forceinline__ uint4 philox4x32(uint4 c, uint32_t k0, uint32_t k1) {
 
 __device__ __forceinline__ float unit24(uint32_t x) { return (float)(x >> 8) * (1.f / 16777216.f); }
 
+// sin(2 pi r) and cos(2 pi r) for r in revolutions, on the hardware units
+// (they take revolutions: no range reduction for |r| <= 256).
+__device__ __forceinline__ float sin_rev(float r) { return __builtin_amdgcn_sinf(r); }
+__device__ __forceinline__ float cos_rev(float r) { return __builtin_amdgcn_cosf(r); }
+
+// Box-Muller on two 24-bit uniforms: rho = sqrt(-2 ln(1 - u_a)) with the
+// hardware log2 (1 - u_a >= 2^-24 is a normal number), angle 2 pi u_b.
+__device__ __forceinline__ void normal_pair(uint32_t a, uint32_t b, float &n0, float &n1) {
+    const float rho = fsqrt(-1.3862943611198906f * __builtin_amdgcn_logf(1.f - unit24(a)));
+    const float u = unit24(b);
+    n0 = rho * cos_rev(u);
+    n1 = rho * sin_rev(u);
+}
+
+// 1 - e^{-2c} for c >= 0 without cancellation: its Taylor series below
+// 2c = 1/16 (truncation error < 2e-8 relative), expm1 above.
+__device__ __forceinline__ float one_minus_exp2c(float c) {
+    const float x = 2.f * c;
+    if (x < 0.0625f) return x * (1.f + x * (-0.5f + x * (1.f / 6.f + x * (-1.f / 24.f + x * (1.f / 120.f)))));
+    return -expm1f(-x);
+}
+
 // World-frame wind force of one drone at global step t (pre-step state d);
 // vm = its mean wind; ws = the drone's wind state (Dryden x, y, z; gust step,
 // -1 idle; gust heading), updated in place.  Models as documented at
@@ -109,18 +131,17 @@ __device__ __forceinline__ void wind_force(const WindArgs &W, float dt, long lon
     }
     if (W.models & MD_WIND_DRYDEN) {
         const uint4 r = philox4x32(make_uint4((uint32_t)di, tl, th, 0u), W.key0, W.key1);
-        const float rad0 = fsqrt(-2.f * logf(1.f - unit24(r.x)));
-        const float rad1 = fsqrt(-2.f * logf(1.f - unit24(r.z)));
-        float s1, c1, s3, c3;
-        sincospif(2.f * unit24(r.y), &s1, &c1);
-        sincospif(2.f * unit24(r.w), &s3, &c3);
-        const float xi[3] = {rad0 * c1, rad0 * s1, rad1 * c3};
+        float xi[4];
+        normal_pair(r.x, r.y, xi[0], xi[1]);
+        normal_pair(r.z, r.w, xi[2], xi[3]);
         const float h = clampf(d.pz * (1.f / 0.3048f), 10.f, 1000.f);
-        const float Lu = h / powf(0.177f + 8.23e-4f * h, 1.2f) * 0.3048f, Lw = h * 0.3048f;
+        // (0.177 + 8.23e-4 h)^1.2 through the hardware log2 and exp2
+        const float Lu = h / __builtin_amdgcn_exp2f(1.2f * __builtin_amdgcn_logf(0.177f + 8.23e-4f * h)) * 0.3048f,
+                    Lw = h * 0.3048f;
         const float cu = dt * W.airspeed / Lu, cw = dt * W.airspeed / Lw;
-        // alpha = e^{-c}; 1 - alpha^2 = -expm1(-2c) without cancellation
-        const float au = expf(-cu), aw = expf(-cw);
-        const float bu = W.sigma * fsqrt(-expm1f(-2.f * cu)), bw = W.sigma * fsqrt(-expm1f(-2.f * cw));
+        // alpha = e^{-c}; 1 - alpha^2 = 1 - e^{-2c} without cancellation
+        const float au = __expf(-cu), aw = __expf(-cw);
+        const float bu = W.sigma * fsqrt(one_minus_exp2c(cu)), bw = W.sigma * fsqrt(one_minus_exp2c(cw));
         ws[0] = au * ws[0] + bu * xi[0];
         ws[1] = au * ws[1] + bu * xi[1];
         ws[2] = aw * ws[2] + bw * xi[2];
@@ -138,9 +159,9 @@ __device__ __forceinline__ void wind_force(const WindArgs &W, float dt, long lon
             }
         }
         if (ws[3] >= 0.f) {
-            const float env = sinpif(ws[3] / (float)W.gust_steps);
-            float sh, ch;
-            sincosf(ws[4], &sh, &ch);
+            const float env = sin_rev(0.5f * ws[3] / (float)W.gust_steps);
+            const float hr = ws[4] * 0.15915494309189535f;  // heading in revolutions
+            const float sh = sin_rev(hr), ch = cos_rev(hr);
             Fx += W.gust_amp * ch * env;
             Fy += W.gust_amp * sh * env;
             ws[3] += 1.f;
@@ -148,12 +169,10 @@ __device__ __forceinline__ void wind_force(const WindArgs &W, float dt, long lon
         }
     }
     if (W.models & MD_WIND_SINUSOIDAL) {
-        // phase reduced in double: t dt grows without bound
-        const double ph = W.sin_wdt * (double)t;
-        const double red = ph - 6.283185307179586 * floor(ph * (1.0 / 6.283185307179586));
-        float s1, c1, s2, c2;
-        sincosf((float)red, &s1, &c1);
-        sincosf((float)(2.0 * red), &s2, &c2);
+        // phase reduced in double (t dt grows without bound), in revolutions
+        const double ph = W.sin_wdt * (double)t * (1.0 / 6.283185307179586);
+        const float rev = (float)(ph - floor(ph));
+        const float s1 = sin_rev(rev), c1 = cos_rev(rev), s2 = sin_rev(2.f * rev);
         Fx += W.sin_amp * s1;
         Fy += W.sin_amp * c1;
         Fz += W.sin_amp * 0.3f * s2;
@@ -171,15 +190,8 @@ __device__ __forceinline__ void sensor_noise(const DrPtr &dr, int di, long long 
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
         const uint4 r = philox4x32(make_uint4((uint32_t)di, tl, th, 2u + (uint32_t)b), dr.key0, dr.key1);
-        const float rad0 = fsqrt(-2.f * logf(1.f - unit24(r.x)));
-        const float rad1 = fsqrt(-2.f * logf(1.f - unit24(r.z)));
-        float s1, c1, s3, c3;
-        sincospif(2.f * unit24(r.y), &s1, &c1);
-        sincospif(2.f * unit24(r.w), &s3, &c3);
-        xi[4 * b + 0] = rad0 * c1;
-        xi[4 * b + 1] = rad0 * s1;
-        xi[4 * b + 2] = rad1 * c3;
-        xi[4 * b + 3] = rad1 * s3;
+        normal_pair(r.x, r.y, xi[4 * b + 0], xi[4 * b + 1]);
+        normal_pair(r.z, r.w, xi[4 * b + 2], xi[4 * b + 3]);
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
