@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(256) mse_grad_kernel(const float *Y, const flo
     red[threadIdx.x] = e2;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
     if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(256) col_sum_kernel(const float *X, int rows, 
     red[threadIdx.x] = s;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
         __syncthreads();
     }
     if (threadIdx.x == 0) out[c] = red[0];
