@@ -462,6 +462,20 @@ def wind_leg(args, w, p, with_obs):
             "launch_config": cfg, "final_state": chk, "wind": WIND_BENCH}
 
 
+def pid_field_leg(args, p, hover):
+    """The latency-bound single-drone field: 4096 environments of one drone,
+    PID every 5th step, ground effect and drag, 2400 physics steps per
+    launch, no observations; 64 waves leave most of the chip idle, so the
+    figure is the time per physics step of the dependency chain."""
+    w, cfg_w = workload("pid_field", hover)
+    n = int(w["env_offsets"][-1])
+    wall, kernel_ms, cfg, _, chk = timed_rollouts(args, w, p, False)
+    k = float(np.median(kernel_ms))
+    return {"value": float(n) * w["n_steps"] * args.steps / wall, "unit": "drone-steps/s",
+            "kernel_ms_median": k, "ns_per_step": k * 1e6 / w["n_steps"], "launch_config": cfg,
+            "final_state": chk, "workload": cfg_w["workload"]}
+
+
 def rk4_leg(args, w, p, with_obs):
     """The same rollouts with the classic Runge-Kutta integrator (four force
     evaluations, four neighbour sweeps per physics step)."""
@@ -486,6 +500,7 @@ def main():
     ap.add_argument("--no-dr", action="store_true", help="skip the domain-randomisation leg")
     ap.add_argument("--no-wind", action="store_true", help="skip the wind leg")
     ap.add_argument("--no-graph", action="store_true", help="skip the ragged-layout hipGraph leg")
+    ap.add_argument("--no-pid-field", action="store_true", help="skip the single-drone PID field leg")
     ap.add_argument("--no-compute-only", action="store_true",
                     help="skip plain_no_obs (the same launches without observation writes)")
     ap.add_argument("--no-tune", action="store_true", help="default launch configuration, no autotuning")
@@ -591,6 +606,8 @@ def main():
         out["domain_randomization"]["speed_vs_plain"] = out["domain_randomization"]["value"] / value
     if not args.no_graph:
         out["ragged_graph"] = ragged_graph_leg(args, p, hover)
+    if not args.no_pid_field:
+        out["pid_field"] = pid_field_leg(args, p, hover)
     if not args.no_wind:
         out["wind"] = wind_leg(args, w, p, with_obs)
         out["wind"]["speed_vs_plain"] = out["wind"]["value"] / value
