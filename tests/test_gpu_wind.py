@@ -43,6 +43,17 @@ def test_combined_wind_on_formation_subset():
     print("combined wind, formation 256 envs, worst:", worst)
 
 
+def test_dryden_scale_at_high_airspeed():
+    """Dryden turbulence at 40 m/s airspeed: with the height clamped to 10 ft,
+    2 dt V / L_w = 0.11 takes the vertical scale sqrt(1 - e^{-2c}) through
+    expm1 while the lateral ones (L_u = 23 m, 2c = 0.015) take its Taylor
+    series, so both branches meet the oracle in one run."""
+    w = dict(wl.subset_envs(wl.formation(n_envs=8192, n_steps=1000, seed=4), 64),
+             wind=dict(COMBINED, models=md.MD_WIND_DRYDEN, dryden_airspeed=40.0, seed=11))
+    worst = _parity(w, [0, 1, 2, 30, 90], pu.BLOCKS + ("pid_int", "wind"))
+    print("dryden at 40 m/s, worst:", worst)
+
+
 def test_per_environment_mean_wind():
     """COMBINED wind whose mean differs per environment (the table's
     per-episode wind magnitude): md_wind.v_mean_drone."""
