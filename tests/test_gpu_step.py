@@ -37,6 +37,21 @@ def test_single_drone_rpm_per_step():
     print("single drone, 240 steps, worst scaled error per block:", worst)
 
 
+def test_fast_spin_takes_the_exact_sine_and_cosine():
+    """Body rates of 150-260 rad/s put th = |w| dt / 2 above 1/4, where the
+    exponential map leaves its Taylor series for sine and cosine; per-step
+    parity with the oracle over 40 steps (ground effect and drag on)."""
+    w = wl.single(pu.hover_rpm(), n_steps=40, seed=5)
+    w = dict(w, aero_mask=3)
+    w["state"]["w"][:, 0] = (150.0, -80.0, 200.0)
+    assert np.linalg.norm(w["state"]["w"][:, 0]) * wl.DT / 2 > 0.25
+    g = pu.DeviceRun(w)
+    obs = g.run(40, obs_slots=40)
+    g.close()
+    worst = _per_step_from_obs(w, obs, w["state"], range(40))
+    print("fast spin, 40 steps, worst scaled error per block:", worst)
+
+
 def test_single_drone_hover_1000_steps_trajectory():
     w = wl.single(pu.hover_rpm(), n_steps=1000, jitter=0.0, seed=0)
     g = pu.DeviceRun(w)
