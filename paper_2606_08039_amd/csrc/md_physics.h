@@ -319,26 +319,38 @@ __device__ __forceinline__ void integrate(const KConst &c, Drone &d, float Fx, f
 }
 
 // Downwash term of one candidate neighbour j on drone i (Eq. 6) without its
-// constant factor K1 = C1 r_p^2 / 16 (applied once to the sum): given
-// dx, dy, dz = p_j - p_i formed from stored positions (so the sign of dz and
-// dz == 0 are exact), returns exp(-dxy^2 / (2 beta^2)) / dz^2 if dz > 0 and
-// dxy < 10 m, else 0.  The Gaussian is evaluated as 2^(-dxy^2 / beta'^2)
+// constant factor K1 = C1 r_p^2 / 16 (applied once to the sum), split in two:
+// dw_d2 forms the horizontal distance squared and dw_raw the value
+// exp(-dxy^2 / (2 beta^2)) / dz^2 for |dz| = adz > 0, with no gate (at
+// adz = 0 it is not finite); dw_term applies the gate dz > 0, dxy < 10 m.
+// dx, dy, dz = p_j - p_i are formed from stored positions, so the sign of dz
+// and dz == 0 are exact.  The Gaussian is evaluated as 2^(-dxy^2 / beta'^2)
 // with beta' = sqrt(2 ln 2) beta (C2, C3 pre-scaled on the host); 1/dz and
 // 1/beta'^2 both come from the one reciprocal 1/(dz beta'^2).  beta'^2 + 1e-30
 // (one fused multiply-add; the addend is below half an ulp of any
 // beta'^2 > 2e-23) reproduces the beta -> 0 limit (1 at dxy = 0, 0 at any
-// float-representable dxy > 0) and keeps dz beta'^2 a normal number.
+// float-representable dxy > 0) and keeps dz beta'^2 a normal number.  The
+// fused multiply-adds are written out, so every sweep rounds alike.
+__device__ __forceinline__ float dw_d2(float dx, float dy) { return fmaf(dx, dx, dy * dy); }
+
 template <bool DZMIN>
-__device__ __forceinline__ float dw_term(const KConst &c, float dx, float dy, float dz) {
-    const float d2 = dx * dx + dy * dy;
-    const float dze = DZMIN ? fmaxf(dz, c.dz_min) : dz;
-    const float bs = c.C2s * dze + c.C3s;
+__device__ __forceinline__ float dw_raw(const KConst &c, float d2, float adz) {
+    const float dze = DZMIN ? fmaxf(adz, c.dz_min) : adz;
+    const float bs = fmaf(c.C2s, dze, c.C3s);
     const float b2 = fmaf(bs, bs, 1e-30f);
     const float inv = rcp(dze * b2);  // one reciprocal for 1/dz and 1/beta'^2
     const float r = b2 * inv;
     const float gauss = __builtin_amdgcn_exp2f(-d2 * (dze * inv));
-    const bool on = (dz > 0.f) && (d2 < 100.f);
-    return on ? (r * r) * gauss : 0.f;
+    return (r * r) * gauss;
+}
+
+__device__ __forceinline__ bool dw_near(float d2) { return d2 < 100.f; }
+
+template <bool DZMIN>
+__device__ __forceinline__ float dw_term(const KConst &c, float dx, float dy, float dz) {
+    const float d2 = dw_d2(dx, dy);
+    const float t = dw_raw<DZMIN>(c, d2, fabsf(dz));
+    return (dz > 0.f && dw_near(d2)) ? t : 0.f;
 }
 
 // Ground effect (Eq. 4) on the world z force: C_gnd T (r_p / 4 h)^2 with

@@ -66,17 +66,21 @@ __device__ __forceinline__ void dw_pairs(const KConst &c, const float4 *buf, flo
         lj -= (lj >= m) ? m : 0;
         const float4 pj = buf[lo + lj];
         const float dz = pj.z - d.pz;
-        const float t = dw_term<DZMIN>(c, pj.x - d.px, pj.y - d.py, fabsf(dz));
-        T[slot * ts + lj] = dz > 0.f ? t : 0.f;
-        T[(lo + lj) * ts + li] = dz < 0.f ? t : 0.f;
+        const float d2 = dw_d2(pj.x - d.px, pj.y - d.py);
+        const float t = dw_raw<DZMIN>(c, d2, fabsf(dz));
+        const bool near = dw_near(d2);
+        T[slot * ts + lj] = (near && dz > 0.f) ? t : 0.f;
+        T[(lo + lj) * ts + li] = (near && dz < 0.f) ? t : 0.f;
     }
     if ((m & 1) == 0 && li < (m >> 1) && m > 0) {
         const int lj = li + (m >> 1);
         const float4 pj = buf[lo + lj];
         const float dz = pj.z - d.pz;
-        const float t = dw_term<DZMIN>(c, pj.x - d.px, pj.y - d.py, fabsf(dz));
-        T[slot * ts + lj] = dz > 0.f ? t : 0.f;
-        T[(lo + lj) * ts + li] = dz < 0.f ? t : 0.f;
+        const float d2 = dw_d2(pj.x - d.px, pj.y - d.py);
+        const float t = dw_raw<DZMIN>(c, d2, fabsf(dz));
+        const bool near = dw_near(d2);
+        T[slot * ts + lj] = (near && dz > 0.f) ? t : 0.f;
+        T[(lo + lj) * ts + li] = (near && dz < 0.f) ? t : 0.f;
     }
 }
 
@@ -115,10 +119,14 @@ __device__ __forceinline__ float dw_pairs_shfl(const KConst &c0, const float4 *b
         ps = (ps == p_beg) ? p_last : ps - 4;
         const float4 q = *qj;
         const float dz = q.z - d.pz;
-        float t = dw_term<DZMIN>(c, q.x - d.px, q.y - d.py, fabsf(dz));
-        if (!UNIFORM) t = (k <= h) ? t : 0.f;
-        const float mine = dz > 0.f ? t : 0.f;
-        const float theirs = t - mine;  // exactly t when the partner is below, else 0
+        const float d2 = dw_d2(q.x - d.px, q.y - d.py);
+        const float t = dw_raw<DZMIN>(c, d2, fabsf(dz));
+        const bool near = dw_near(d2) && (UNIFORM || k <= h);
+        // the term stays with the lower drone: each of the two lane masks
+        // selects it or 0 (at dz = 0 neither does, and t is not used)
+        float mine = (near && dz > 0.f) ? t : 0.f;
+        asm volatile("" : "+v"(mine));
+        const float theirs = (near && dz < 0.f) ? t : 0.f;
         const float recv = __int_as_float(__builtin_amdgcn_ds_bpermute(ps, __float_as_int(theirs)));
         acc += mine;
         acc += recv;
@@ -127,9 +135,7 @@ __device__ __forceinline__ float dw_pairs_shfl(const KConst &c0, const float4 *b
         const int half = m >> 1;
         const int lj = li < half ? li + half : li - half;
         const float4 q = buf[lo + lj];
-        const float dz = q.z - d.pz;
-        const float t = dw_term<DZMIN>(c, q.x - d.px, q.y - d.py, fabsf(dz));
-        acc += dz > 0.f ? t : 0.f;
+        acc += dw_term<DZMIN>(c, q.x - d.px, q.y - d.py, q.z - d.pz);
     }
     return acc;
 }
@@ -160,15 +166,24 @@ __device__ __forceinline__ float dw_pairs_rot(const KConst &c0, const float4 *ow
     constexpr int M = 64 / E;
     constexpr int H = (M - 1) / 2;
     const KConst c = pair_consts(c0);
-    const int pa = 4 * lane;
+    // the permute addresses pa + 256 - 4 E k fold into the instructions'
+    // offset field when pa is formed inside the step: hoisted out of the
+    // step loop instead, they would hold one register per shift
+    int pa = 4 * lane;
+    asm volatile("" : "+v"(pa));
     float acc = 0.f;
 #pragma unroll
     for (int k = 1; k <= H; ++k) {
         const float4 q = own[E * k];
         const float dz = q.z - d.pz;
-        const float t = dw_term<DZMIN>(c, q.x - d.px, q.y - d.py, fabsf(dz));
-        const float mine = dz > 0.f ? t : 0.f;
-        const float theirs = t - mine;
+        const float d2 = dw_d2(q.x - d.px, q.y - d.py);
+        const float t = dw_raw<DZMIN>(c, d2, fabsf(dz));
+        const bool near = dw_near(d2);
+        float mine = (near && dz > 0.f) ? t : 0.f;
+        // formed here, not where the serial sum reaches it: otherwise its
+        // lane mask stays live across shifts and the masks spill
+        asm volatile("" : "+v"(mine));
+        const float theirs = (near && dz < 0.f) ? t : 0.f;
         const float recv = __int_as_float(__builtin_amdgcn_ds_bpermute(pa + (256 - 4 * E * k), __float_as_int(theirs)));
         acc += mine;
         acc += recv;
@@ -177,9 +192,7 @@ __device__ __forceinline__ float dw_pairs_rot(const KConst &c0, const float4 *ow
     {
         // M is even: the pair at distance M / 2 (lane + 32), kept by the lower drone
         const float4 q = own[32];
-        const float dz = q.z - d.pz;
-        const float t = dw_term<DZMIN>(c, q.x - d.px, q.y - d.py, fabsf(dz));
-        acc += dz > 0.f ? t : 0.f;
+        acc += dw_term<DZMIN>(c, q.x - d.px, q.y - d.py, q.z - d.pz);
     }
     seg.template at<H>(H);
     return acc;
