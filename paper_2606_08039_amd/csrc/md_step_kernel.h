@@ -369,10 +369,14 @@ __global__ void __launch_bounds__(DIST == 2 ? MAX_THREADS_DR : 1024) step_kernel
     // Per-step rotor-speed actions are read one step ahead: the row of step
     // k + 1 is requested during step k, so its memory latency overlaps the
     // step instead of opening the next one (short launches of small layouts
-    // are latency-bound).
+    // are latency-bound).  The read is unconditional (the last step reads
+    // its own row again; idle lanes read drone 0's row and keep zero rotor
+    // speeds): a read under a condition leaves the loaded value to be merged
+    // into the loop's register right after the load, which waits for it.
+    const int da = valid ? di : 0;
     float nact[4] = {0.f, 0.f, 0.f, 0.f};
-    if (ACT == 0 && !rnd && valid && a.n_steps > 0)
-        for (int k = 0; k < 4; ++k) nact[k] = a.action[(long long)k * N + di];
+    if (ACT == 0 && !rnd && a.n_steps > 0)
+        for (int k = 0; k < 4; ++k) nact[k] = a.action[(long long)k * N + da];
     // controller phase, observation slot and ring slot advance as counters
     int phase = (ACT >= 1) ? (int)(a.step0 % (long long)c.decim) : 0;
     int oslot = 0;
@@ -415,13 +419,9 @@ __global__ void __launch_bounds__(DIST == 2 ? MAX_THREADS_DR : 1024) step_kernel
         const float *act = a.action + a.act_step_stride * step;
         if (!rnd) {
             if (ACT == 0) {
-                if (valid) {
-                    for (int k = 0; k < 4; ++k) n[k] = clampf(nact[k], 0.f, c.max_rpm);
-                    if (a.act_step_stride != 0 && step + 1 < a.n_steps) {
-                        const float *nx = act + a.act_step_stride;
-                        for (int k = 0; k < 4; ++k) nact[k] = nx[(long long)k * N + di];
-                    }
-                }
+                for (int k = 0; k < 4; ++k) n[k] = valid ? clampf(nact[k], 0.f, c.max_rpm) : 0.f;
+                const float *nx = (step + 1 < a.n_steps) ? act + a.act_step_stride : act;
+                for (int k = 0; k < 4; ++k) nact[k] = nx[(long long)k * N + da];
             } else {
                 if (phase == 0 && valid) {
                     float cmd[ROWS];
