@@ -74,12 +74,16 @@ __device__ __forceinline__ void dr_constants(const KConst &c, const DrPtr &dr, i
 
 // Philox4x32-10 (Salmon et al., SC 2011): ten rounds of the two 32x32-bit
 // products with the round multipliers, high halves xored with the other
-// counter words and the round key, key bumped by the Weyl constants.
+// counter words and the round key, key bumped by the Weyl constants.  Each
+// product is formed whole (one 32x32 -> 64-bit multiply-add gives both
+// halves) instead of as separate high and low multiplies.
 __device__ __forceinline__ uint4 philox4x32(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+        const unsigned long long p0 = (unsigned long long)0xD2511F53u * c.x;
+        const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
