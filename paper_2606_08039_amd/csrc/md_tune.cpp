@@ -3,7 +3,8 @@
 // Autotuner: for the bound layout and the context's mask, time every valid
 // launch configuration (lanes per drone for the neighbour sweep, bin size in
 // waves, neighbour-loop unroll, all-pairs or pair-symmetric sweep) on scratch
-// copies of the caller's state, keep the fastest, and remember it in a small
+// copies of the caller's state (round robin, the median of three timed
+// repetitions after a warm-up round), keep the fastest, and remember it in a small
 // JSON cache keyed by the layout signature.  Every configuration computes the
 // same physics; the pair-symmetric and the one-lane all-pairs sweeps are
 // bitwise identical, the multi-lane sweeps differ only in summation order.
@@ -220,27 +221,38 @@ md_status autotune(md_ctx *ctx, const md_state *s, const float *d_action, int ac
     const char *venv = std::getenv("MD_AUTOTUNE_VERBOSE");
     const bool verbose = venv && *venv && *venv != '0';
     md_status rc = MD_OK;
-    for (const LaunchCfg &c : candidates(ctx)) {
-        if (e != hipSuccess) break;
-        float t_best = 1e30f;
-        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+    // Round robin: every repetition times each candidate once, so all of
+    // them see the same drift of the clock under sustained load (a long
+    // launch lowers it); the first round warms up, the score is the median
+    // of the other three.
+    const std::vector<LaunchCfg> cands = candidates(ctx);
+    constexpr int REPS = 4;
+    std::vector<float> ms_of(cands.size() * (REPS - 1), 0.f);
+    for (int rep = 0; rep < REPS && e == hipSuccess && rc == MD_OK; ++rep) {
+        for (size_t i = 0; i < cands.size() && e == hipSuccess; ++i) {
             e = hipMemcpyAsync(work, scratch, sizeof(float) * rows * N, hipMemcpyDeviceToDevice, st);
             if (e != hipSuccess) break;
             e = hipEventRecord(a, st);
-            rc = launch(ctx, &ws, d_action, action_per_step, d_obs, d_obs ? n_obs_slots : 0, n_steps, step0, st, c);
+            rc = launch(ctx, &ws, d_action, action_per_step, d_obs, d_obs ? n_obs_slots : 0, n_steps, step0, st,
+                        cands[i]);
             if (rc != MD_OK) break;
             e = hipEventRecord(b, st);
             if (e == hipSuccess) e = hipEventSynchronize(b);
             float ms = 0.f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-            if (rep > 0) t_best = std::min(t_best, ms);  // first repetition warms up
+            if (rep > 0) ms_of[i * (REPS - 1) + (rep - 1)] = ms;
         }
-        if (rc != MD_OK) break;
-        if (verbose && e == hipSuccess)
+    }
+    for (size_t i = 0; i < cands.size() && e == hipSuccess && rc == MD_OK; ++i) {
+        float *t = &ms_of[i * (REPS - 1)];
+        std::sort(t, t + (REPS - 1));
+        const double us = t[(REPS - 1) / 2] * 1000.0;
+        const LaunchCfg &c = cands[i];
+        if (verbose)
             std::fprintf(stderr, "md_autotune %s: lpd %d unroll %d waves %d sym %d: %.1f us\n", sig.c_str(), c.lpd,
-                         c.unroll, c.waves, c.sym, t_best * 1000.0);
-        if (e == hipSuccess && t_best * 1000.0 < best_us) {
-            best_us = t_best * 1000.0;
+                         c.unroll, c.waves, c.sym, us);
+        if (us < best_us) {
+            best_us = us;
             best = c;
         }
     }
