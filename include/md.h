@@ -340,7 +340,8 @@ md_status md_set_launch_config(md_ctx *ctx, md_launch_config *cfg);
 
 /* Time every valid launch configuration for the bound layout on scratch
  * copies of s (s itself is not modified) over n_steps steps of d_action,
- * and select the fastest.  The choice is remembered in the JSON file
+ * and select the fastest: the candidates run round robin, one warm-up round
+ * and three timed ones, and each is scored by its median.  The choice is remembered in the JSON file
  * cache_path (NULL: the MD_AUTOTUNE_CACHE environment variable; empty: no
  * cache) under a signature of the layout, mask, action type and integrator; a cached
  * choice is reused unless force is non-zero.  Synchronous; allocates two
