@@ -263,13 +263,17 @@ __device__ __forceinline__ float dw_sum(const KConst &c, const float4 *buf, floa
     } else {
         acc = dw_sweep<false, LPD, UNROLL>(c, buf, lo, sub, mmax, menv, uniform, d);
     }
+    // the partial sums of a drone's lanes, combined across the lanes of a
+    // quad by DPP quad permutes (lane ^ 1, then lane ^ 2; every lane of the
+    // wave is active here); a + b = b + a exactly, so all lanes of a drone
+    // hold the same sum
     if (LPD >= 2) {
-        const float o = __shfl_xor(acc, 1, 64);
-        acc = (sub & 1) ? (o + acc) : (acc + o);
+        const float o = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(acc), 0xB1, 0xF, 0xF, true));
+        acc = acc + o;
     }
     if (LPD >= 4) {
-        const float o = __shfl_xor(acc, 2, 64);
-        acc = (sub & 2) ? (o + acc) : (acc + o);
+        const float o = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(acc), 0x4E, 0xF, 0xF, true));
+        acc = acc + o;
     }
     return acc;
 }
