@@ -341,7 +341,9 @@ md_status md_set_launch_config(md_ctx *ctx, md_launch_config *cfg);
 /* Time every valid launch configuration for the bound layout on scratch
  * copies of s (s itself is not modified) over n_steps steps of d_action,
  * and select the fastest: the candidates run round robin, one warm-up round
- * and three timed ones, and each is scored by its median.  The choice is remembered in the JSON file
+ * and three timed ones, each scored by its median; the three best are timed
+ * again as runs of six consecutive launches (the sustained load of a
+ * rollout), which decide.  The choice is remembered in the JSON file
  * cache_path (NULL: the MD_AUTOTUNE_CACHE environment variable; empty: no
  * cache) under a signature of the layout, mask, action type and integrator; a cached
  * choice is reused unless force is non-zero.  Synchronous; allocates two
