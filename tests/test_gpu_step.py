@@ -116,13 +116,22 @@ def test_pid_field_full_size_sampled():
     print("pid field 4096 envs, worst:", worst)
 
 
-def test_ragged_downwash_full_size_per_step():
+@pytest.mark.parametrize("cfg", ["default", "autotuned"])
+def test_ragged_downwash_full_size_per_step(cfg):
+    """The ragged 1024-environment layout, every drone at every one of its
+    100 steps, in the default configuration and in the one the autotuner
+    picks for it (the benchmark's: several lanes per drone, their partial
+    sums combined across lanes)."""
     w = wl.ragged_grid(pu.hover_rpm(), n_envs=1024, n_steps=100, seed=2)
     g = pu.DeviceRun(w)
+    c = None
+    if cfg == "autotuned":
+        md.md_autotune(g.ctx, g.state, g.action_slice(0, 10), w["action_per_step"], n_steps=10, cache_path="")
+        c = md.md_get_launch_config(g.ctx)
     obs = g.run(100, obs_slots=100)
     g.close()
     worst = _per_step_from_obs(w, obs, w["state"], range(100))
-    print("ragged grid 1024 envs, worst:", worst)
+    print("ragged grid 1024 envs, %s %s, worst:" % (cfg, c), worst)
 
 
 @pytest.mark.parametrize("cfg", ["default", "autotuned", "rotation"])
