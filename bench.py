@@ -387,9 +387,9 @@ def dr_leg(args, w, p, with_obs):
 def ragged_graph_leg(args, p, hover):
     """The latency-bound ragged layout (1024 environments of 2..32 drones on a
     coplanar grid, 17.4k drones, per-step rotor speeds, all aero terms): a
-    100-step rollout as one persistent launch of 100 steps (the value), and
-    as 10 launches of 10 steps replayed from one captured hipGraph and issued
-    eagerly."""
+    100-step rollout as one persistent launch of 100 steps (the value), as
+    that launch replayed from a captured hipGraph, and as 10 launches of 10
+    steps replayed from one captured hipGraph and issued eagerly."""
     import torch
     from paper_2606_08039_amd import md, workloads as wl
     w = wl.ragged_grid(hover, n_envs=1024, n_steps=100, seed=2)
@@ -423,26 +423,31 @@ def ragged_graph_leg(args, p, hover):
             torch.cuda.synchronize()
             if r >= 2:
                 t_one.append(a.elapsed_time(b))
-        graph = md.md_rollout_graph_create(ctx, state, action, True, None, 0, steps_per_launch=10,
-                                           n_launches=10, step0=0, stream=stream)
-        t_graph = []
-        try:
-            for r in range(reps + 2):
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record(stream)
-                md.md_graph_launch(graph, stream)
-                b.record(stream)
-                torch.cuda.synchronize()
-                if r >= 2:
-                    t_graph.append(a.elapsed_time(b))
-        finally:
-            md.md_graph_destroy(graph)
+        def replay(steps_per_launch, n_launches):
+            graph = md.md_rollout_graph_create(ctx, state, action, True, None, 0, steps_per_launch=steps_per_launch,
+                                               n_launches=n_launches, step0=0, stream=stream)
+            t = []
+            try:
+                for r in range(reps + 2):
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    md.md_graph_launch(graph, stream)
+                    b.record(stream)
+                    torch.cuda.synchronize()
+                    if r >= 2:
+                        t.append(a.elapsed_time(b))
+            finally:
+                md.md_graph_destroy(graph)
+            return t
+        t_graph = replay(10, 10)
+        t_graph1 = replay(100, 1)
     finally:
         md.md_destroy(ctx)
     mg, me, m1 = float(np.median(t_graph)), float(np.median(t_eager)), float(np.median(t_one))
     return {"value": float(n) * 100 / (m1 * 1e-3), "unit": "drone-steps/s", "n_drones": n,
             "rollout_ms_single_launch_median": m1, "ns_per_step_single_launch": m1 * 1e6 / 100,
-            "rollout_ms_graph_median": mg, "rollout_ms_eager_median": me, "replays": reps,
+            "rollout_ms_graph_median": mg, "rollout_ms_graph_one_launch_median": float(np.median(t_graph1)),
+            "rollout_ms_eager_median": me, "replays": reps,
             "value_graph": float(n) * 100 / (mg * 1e-3),
             "launch_config": cfg, "workload": "ragged_grid_1024envs_m2to32_rpm_gnd_drag_dw_100steps"}
 
